@@ -1,0 +1,128 @@
+/*
+ * sht.h -- C ABI of the MI355X (gfx950) spherical harmonic transform library
+ * (libsht.so): the Legendre stage and ring FFTs of the transforms described
+ * in Szydlarski et al., "Parallel Spherical Harmonic Transforms on
+ * heterogeneous architectures".
+ *
+ * Problem statement (Sec. 2.1, eqs. map2almDef and alm2mapDef):
+ *   synthesis  s(theta_n, phi_n) = sum_{l<=lmax} sum_{|m|<=min(l,mmax)} a_lm Y_lm(theta_n, phi_n)
+ *   analysis   a_lm = sum_n w_n s_n conj(Y_lm(theta_n, phi_n))
+ * with Y_lm = lambda_lm(cos theta) e^{i m phi} (eq. YlmDef, Condon-Shortley
+ * phase), real maps and therefore a_{l,-m} = (-1)^m conj(a_lm) (the symmetry
+ * stated after eq. YlmDef), so only m >= 0 is stored.
+ *
+ * Geometry (Sec. 2.2, iso-latitude rings): ring r has colatitude theta[r],
+ * nphi[r] equidistant pixels at phi_j = phi0[r] + 2 pi j / nphi[r], and one
+ * per-pixel quadrature weight weight[r]; its pixels are map[ofs[r] + j].
+ *
+ * Data layouts (all device buffers are caller-owned; the library never
+ * keeps a pointer to them after a call returns):
+ *   a_lm   complex128 (re, im interleaved, 16-byte aligned), [nmaps][nalm],
+ *          m-major packed: index(l, m) = m*(2*lmax+1-m)/2 + l, m <= l <= lmax,
+ *          nalm = (mmax+1)*(2*lmax+2-mmax)/2.
+ *   map    float64, [nmaps][npix], npix = max_r(ofs[r] + nphi[r]).
+ *   delta  complex128, [nmaps][nrings][mmax+1]: Delta_m(r) of Sec. 2.2
+ *          (eq. DeltaDef for synthesis, eq. almfftdef for analysis).
+ *
+ * Conventions: Im a_l0 is ignored on input and written as exactly 0 on
+ * output.  Rings r, r' whose colatitudes satisfy |theta_r + theta_r' - pi|
+ * <= 1e-14 are treated as mirror images (cos theta_r' = -cos theta_r) and
+ * share one Legendre recurrence.
+ *
+ * Execution: every compute call validates its arguments on the host, then
+ * enqueues kernels on `stream` (a hipStream_t; NULL = the null stream) and
+ * returns without waiting.  A failed validation returns an error before
+ * anything is enqueued and leaves all outputs untouched.  Kernel faults
+ * surface at the caller's next synchronisation of the stream.  The first call
+ * for a (lmax, mmax, geometry) builds and caches device tables (coefficients
+ * and FFT plans); that call synchronises the device once.
+ *
+ * Thread safety: all functions may be called from several host threads.
+ * Buffers passed to concurrent calls must not overlap (outputs), and inputs
+ * must not be written while a call that reads them is in flight.
+ */
+#ifndef SHT_H
+#define SHT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Ring geometry, HOST memory, read only during the call. */
+typedef struct sht_geom {
+    int32_t nrings;         /* >= 1 */
+    const double *theta;    /* [nrings] colatitude in [0, pi] */
+    const int32_t *nphi;    /* [nrings] pixels per ring, >= 1 */
+    const double *phi0;     /* [nrings] longitude of pixel j = 0 (finite) */
+    const double *weight;   /* [nrings] per-pixel quadrature weight; required by
+                               analysis, may be NULL for synthesis */
+    const int64_t *ofs;     /* [nrings] first-pixel offset; NULL = rings packed
+                               in order from 0.  Ring ranges must not overlap. */
+} sht_geom;
+
+enum sht_status {
+    SHT_OK = 0,
+    SHT_EINVAL = -1,        /* invalid argument (sizes, geometry, pointers) */
+    SHT_EWORKSPACE = -2,    /* workspace NULL or smaller than required */
+    SHT_EDEVICE = -3,       /* a HIP runtime call failed (see sht_strerror) */
+    SHT_ENOMEM = -4,        /* device or host allocation for plan tables failed */
+    SHT_EUNSUPPORTED = -5   /* unknown flag bit, or a size beyond the kernels' limits */
+};
+
+/* Bytes of device workspace needed by sht_alm2map, sht_map2alm and
+ * sht_alm2delta for these arguments (a multiple of 256; the same value serves
+ * all three).  Returns 0 if the arguments are invalid. */
+size_t sht_workspace_bytes(int lmax, int mmax, const sht_geom *g, int nmaps, uint32_t flags);
+
+/* Synthesis (Sec. 3, Alg. 2): Delta^A_m(r) by the l-recurrence contracted
+ * with a_lm (eqs. assLegRec, pmm, pm1m, DeltaDef), then one Fourier sum per
+ * ring (eq. Delta2map, phase e^{i m phi_j}).
+ *   alm        DEVICE complex128 [nmaps][nalm], read only
+ *   map        DEVICE float64   [nmaps][npix], written (pixels outside the
+ *              rings are left untouched)
+ *   workspace  DEVICE, >= sht_workspace_bytes(...) bytes, 256-byte aligned,
+ *              must not alias alm or map; contents undefined afterwards
+ *   flags      0 (FP64).  Any other bit: SHT_EUNSUPPORTED. */
+int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *map,
+                int nmaps, void *workspace, size_t ws_bytes, uint32_t flags, void *stream);
+
+/* Analysis (Sec. 3, Alg. 1): Delta^S_m(r) = w_r sum_j s_rj e^{-i m phi_j}
+ * per ring (eq. almfftdef), then a_lm = sum_r Delta^S_m(r) lambda_lm(cos theta_r)
+ * (eq. almdef), a reduction over rings done in a fixed order (deterministic).
+ * Requires g->weight.
+ *   map        DEVICE float64   [nmaps][npix], read only
+ *   alm        DEVICE complex128 [nmaps][nalm], fully written
+ *   workspace  as for sht_alm2map. */
+int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *alm,
+                int nmaps, void *workspace, size_t ws_bytes, uint32_t flags, void *stream);
+
+/* The two stages of each transform, for callers that keep Delta
+ * themselves (and for per-stage timing).  sht_alm2map = sht_alm2delta then
+ * sht_delta2map; sht_map2alm = sht_map2delta then sht_delta2alm.
+ *   delta      DEVICE complex128 [nmaps][nrings][mmax+1]
+ * sht_alm2delta writes every Delta_m(r) (eq. DeltaDef) and needs a workspace
+ * of sht_workspace_bytes(...) bytes; the other three need none. */
+int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *delta,
+                  int nmaps, void *workspace, size_t ws_bytes, uint32_t flags, void *stream);
+int sht_delta2map(int mmax, const sht_geom *g, const void *delta, double *map, int nmaps,
+                  uint32_t flags, void *stream);
+int sht_map2delta(int mmax, const sht_geom *g, const double *map, void *delta, int nmaps,
+                  uint32_t flags, void *stream);
+int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void *alm,
+                  int nmaps, uint32_t flags, void *stream);
+
+/* Static description of a status code.  For SHT_EDEVICE the text of the
+ * last HIP error seen by the calling thread is returned instead. */
+const char *sht_strerror(int code);
+
+/* Frees every cached plan table on every device.  Calls in flight must have
+ * completed.  Later calls rebuild the tables. */
+void sht_shutdown(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SHT_H */

@@ -1,0 +1,223 @@
+"""Python binding of libsht.so: argument marshalling only.
+
+Every step of the transforms runs in the HIP library; torch is used for
+device memory and the current stream.  If libsht.so has not been built the
+import of the binding functions raises immediately: there is no CPU path.
+
+Geometry objects are anything with numpy attributes ``theta`` (float64),
+``nphi`` (int32), ``phi0`` (float64), ``weight`` (float64) and ``ofs``
+(int64) per ring, e.g. ``sht_inputs.Geometry``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libsht.so")
+
+SHT_OK, SHT_EINVAL, SHT_EWORKSPACE, SHT_EDEVICE, SHT_ENOMEM, SHT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+EXPORTS = ("sht_workspace_bytes", "sht_alm2map", "sht_map2alm", "sht_alm2delta", "sht_delta2map",
+           "sht_map2delta", "sht_delta2alm", "sht_strerror", "sht_shutdown")
+
+
+class ShtError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"{what}: {lib().sht_strerror(code).decode()} (status {code})")
+        self.code = code
+
+
+class _Geom(ctypes.Structure):
+    _fields_ = [("nrings", ctypes.c_int32), ("theta", ctypes.c_void_p), ("nphi", ctypes.c_void_p),
+                ("phi0", ctypes.c_void_p), ("weight", ctypes.c_void_p), ("ofs", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load libsht.so (raises if it is missing: the GPU library is required)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                              "python paper_1106_0159_amd/_build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I, U, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_size_t
+        GP = ctypes.POINTER(_Geom)
+        L.sht_workspace_bytes.restype = S
+        L.sht_workspace_bytes.argtypes = [I, I, GP, I, U]
+        for name in ("sht_alm2map", "sht_map2alm", "sht_alm2delta"):
+            f = getattr(L, name)
+            f.restype = I
+            f.argtypes = [I, I, GP, P, P, I, P, S, U, P]
+        for name in ("sht_delta2map", "sht_map2delta"):
+            f = getattr(L, name)
+            f.restype = I
+            f.argtypes = [I, GP, P, P, I, U, P]
+        L.sht_delta2alm.restype = I
+        L.sht_delta2alm.argtypes = [I, I, GP, P, P, I, U, P]
+        L.sht_strerror.restype = ctypes.c_char_p
+        L.sht_strerror.argtypes = [I]
+        L.sht_shutdown.restype = None
+        L.sht_shutdown.argtypes = []
+        _lib = L
+    return _lib
+
+
+class GeomHandle:
+    """Keeps contiguous host copies of a geometry alive for ctypes."""
+
+    def __init__(self, g, with_weight: bool = True):
+        self.theta = np.ascontiguousarray(g.theta, dtype=np.float64)
+        self.nphi = np.ascontiguousarray(g.nphi, dtype=np.int32)
+        self.phi0 = np.ascontiguousarray(g.phi0, dtype=np.float64)
+        w = getattr(g, "weight", None)
+        self.weight = None if (w is None or not with_weight) else np.ascontiguousarray(w, dtype=np.float64)
+        o = getattr(g, "ofs", None)
+        self.ofs = None if o is None else np.ascontiguousarray(o, dtype=np.int64)
+        self.nrings = int(self.theta.shape[0])
+        self.npix = int(np.max(self.ofs + self.nphi)) if self.ofs is not None else int(self.nphi.sum())
+        ptr = lambda a: None if a is None else a.ctypes.data
+        self.c = _Geom(self.nrings, ptr(self.theta), ptr(self.nphi), ptr(self.phi0), ptr(self.weight),
+                       ptr(self.ofs))
+
+    def ref(self):
+        return ctypes.byref(self.c)
+
+
+def nalm(lmax: int, mmax: int) -> int:
+    return (mmax + 1) * (2 * lmax + 2 - mmax) // 2
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _check(rc: int, what: str):
+    if rc != SHT_OK:
+        raise ShtError(rc, what)
+
+
+def _gh(geom, with_weight=True) -> GeomHandle:
+    return geom if isinstance(geom, GeomHandle) else GeomHandle(geom, with_weight)
+
+
+def workspace_bytes(lmax: int, mmax: int, geom, nmaps: int = 1, flags: int = 0) -> int:
+    g = _gh(geom)
+    return int(lib().sht_workspace_bytes(lmax, mmax, g.ref(), nmaps, flags))
+
+
+def workspace(lmax: int, mmax: int, geom, nmaps: int = 1, device="cuda"):
+    torch = _torch()
+    n = workspace_bytes(lmax, mmax, geom, nmaps)
+    if n == 0:
+        raise ShtError(SHT_EINVAL, "sht_workspace_bytes")
+    return torch.empty(n, dtype=torch.uint8, device=device)
+
+
+def _nmaps_of(t, per):
+    n = t.numel() // per
+    if n * per != t.numel() or n < 1:
+        raise ValueError(f"tensor of {t.numel()} elements is not a whole number of {per}-element maps")
+    return n
+
+
+def alm2map(alm, geom, lmax: int, mmax: int | None = None, out=None, ws=None, stream=None):
+    """Synthesis.  alm: complex128 CUDA tensor [..., nalm]; returns float64 [..., npix]."""
+    torch = _torch()
+    mmax = lmax if mmax is None else mmax
+    g = _gh(geom, with_weight=False)
+    na = nalm(lmax, mmax)
+    nm = _nmaps_of(alm, na)
+    if out is None:
+        out = torch.zeros(alm.shape[:-1] + (g.npix,), dtype=torch.float64, device=alm.device)
+    if ws is None:
+        ws = workspace(lmax, mmax, g, nm, alm.device)
+    rc = lib().sht_alm2map(lmax, mmax, g.ref(), alm.data_ptr(), out.data_ptr(), nm, ws.data_ptr(),
+                           ws.numel() * ws.element_size(), 0, _stream_ptr(stream))
+    _check(rc, "sht_alm2map")
+    return out
+
+
+def map2alm(mp, geom, lmax: int, mmax: int | None = None, out=None, ws=None, stream=None):
+    """Analysis.  mp: float64 CUDA tensor [..., npix]; returns complex128 [..., nalm]."""
+    torch = _torch()
+    mmax = lmax if mmax is None else mmax
+    g = _gh(geom)
+    nm = _nmaps_of(mp, g.npix)
+    if out is None:
+        out = torch.empty(mp.shape[:-1] + (nalm(lmax, mmax),), dtype=torch.complex128, device=mp.device)
+    if ws is None:
+        ws = workspace(lmax, mmax, g, nm, mp.device)
+    rc = lib().sht_map2alm(lmax, mmax, g.ref(), mp.data_ptr(), out.data_ptr(), nm, ws.data_ptr(),
+                           ws.numel() * ws.element_size(), 0, _stream_ptr(stream))
+    _check(rc, "sht_map2alm")
+    return out
+
+
+def alm2delta(alm, geom, lmax: int, mmax: int | None = None, out=None, ws=None, stream=None):
+    """Legendre synthesis stage: complex128 Delta [..., nrings, mmax+1]."""
+    torch = _torch()
+    mmax = lmax if mmax is None else mmax
+    g = _gh(geom, with_weight=False)
+    nm = _nmaps_of(alm, nalm(lmax, mmax))
+    if out is None:
+        out = torch.empty(alm.shape[:-1] + (g.nrings, mmax + 1), dtype=torch.complex128, device=alm.device)
+    if ws is None:
+        ws = workspace(lmax, mmax, g, nm, alm.device)
+    rc = lib().sht_alm2delta(lmax, mmax, g.ref(), alm.data_ptr(), out.data_ptr(), nm, ws.data_ptr(),
+                             ws.numel() * ws.element_size(), 0, _stream_ptr(stream))
+    _check(rc, "sht_alm2delta")
+    return out
+
+
+def delta2map(delta, geom, mmax: int, out=None, stream=None):
+    """Ring synthesis stage: float64 map [..., npix] from Delta [..., nrings, mmax+1]."""
+    torch = _torch()
+    g = _gh(geom, with_weight=False)
+    nm = _nmaps_of(delta, g.nrings * (mmax + 1))
+    if out is None:
+        out = torch.zeros(delta.shape[:-2] + (g.npix,), dtype=torch.float64, device=delta.device)
+    rc = lib().sht_delta2map(mmax, g.ref(), delta.data_ptr(), out.data_ptr(), nm, 0, _stream_ptr(stream))
+    _check(rc, "sht_delta2map")
+    return out
+
+
+def map2delta(mp, geom, mmax: int, out=None, stream=None):
+    """Ring analysis stage: Delta^S [..., nrings, mmax+1] from a float64 map."""
+    torch = _torch()
+    g = _gh(geom)
+    nm = _nmaps_of(mp, g.npix)
+    if out is None:
+        out = torch.empty(mp.shape[:-1] + (g.nrings, mmax + 1), dtype=torch.complex128, device=mp.device)
+    rc = lib().sht_map2delta(mmax, g.ref(), mp.data_ptr(), out.data_ptr(), nm, 0, _stream_ptr(stream))
+    _check(rc, "sht_map2delta")
+    return out
+
+
+def delta2alm(delta, geom, lmax: int, mmax: int | None = None, out=None, stream=None):
+    """Legendre analysis stage: a_lm [..., nalm] from Delta^S [..., nrings, mmax+1]."""
+    torch = _torch()
+    mmax = lmax if mmax is None else mmax
+    g = _gh(geom, with_weight=False)
+    nm = _nmaps_of(delta, g.nrings * (mmax + 1))
+    if out is None:
+        out = torch.empty(delta.shape[:-2] + (nalm(lmax, mmax),), dtype=torch.complex128, device=delta.device)
+    rc = lib().sht_delta2alm(lmax, mmax, g.ref(), delta.data_ptr(), out.data_ptr(), nm, 0, _stream_ptr(stream))
+    _check(rc, "sht_delta2alm")
+    return out
+
+
+def shutdown() -> None:
+    lib().sht_shutdown()

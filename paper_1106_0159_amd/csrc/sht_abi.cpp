@@ -1,0 +1,173 @@
+// extern "C" entry points of libsht.so (declared in include/sht.h).
+#include <cstring>
+
+#include "sht_internal.h"
+
+namespace sht {
+const char *last_hip_error();
+void shutdown_all();
+}  // namespace sht
+
+using namespace sht;
+
+namespace {
+
+constexpr uint32_t kKnownFlags = 0u;
+
+size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
+
+size_t alm_bytes(int lmax, int mmax, int nmaps) {
+    return (size_t)nalm_of(lmax, mmax) * 16u * (size_t)nmaps;
+}
+size_t delta_bytes(int nrings, int mmax, int nmaps) {
+    return (size_t)nrings * (size_t)(mmax + 1) * 16u * (size_t)nmaps;
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return x < y + nb && y < x + na;
+}
+
+hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Common checks for the transforms; fills the validated geometry.
+int check_common(int lmax, int mmax, const sht_geom *g, int nmaps, uint32_t flags, bool need_weight,
+                 HostGeom *h) {
+    int rc = validate_sizes(lmax, mmax, nmaps);
+    if (rc) return rc;
+    if (flags & ~kKnownFlags) return SHT_EUNSUPPORTED;
+    return validate_geom(g, need_weight, h);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t sht_workspace_bytes(int lmax, int mmax, const sht_geom *g, int nmaps, uint32_t flags) {
+    HostGeom h;
+    if (check_common(lmax, mmax, g, nmaps, flags, false, &h)) return 0;
+    return round256(alm_bytes(lmax, mmax, nmaps)) + round256(delta_bytes(h.nrings, mmax, nmaps));
+}
+
+int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *delta, int nmaps,
+                  void *workspace, size_t ws_bytes, uint32_t flags, void *stream) {
+    HostGeom h;
+    int rc = check_common(lmax, mmax, g, nmaps, flags, false, &h);
+    if (rc) return rc;
+    if (!alm || !delta || !aligned(alm, 16) || !aligned(delta, 16)) return SHT_EINVAL;
+    const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
+    if (!workspace || !aligned(workspace, 16) || ws_bytes < round256(ab)) return SHT_EWORKSPACE;
+    if (overlap(alm, ab, delta, db) || overlap(workspace, ws_bytes, alm, ab) ||
+        overlap(workspace, ws_bytes, delta, db))
+        return SHT_EINVAL;
+    const CoefTables *c;
+    const GeomPlan *p;
+    if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p))) return rc;
+    if ((rc = launch_prescale(*c, alm, workspace, nmaps, as_stream(stream)))) return rc;
+    return launch_leg_syn(*c, *p, workspace, delta, nmaps, as_stream(stream));
+}
+
+int sht_delta2map(int mmax, const sht_geom *g, const void *delta, double *map, int nmaps,
+                  uint32_t flags, void *stream) {
+    HostGeom h;
+    int rc = check_common(mmax, mmax, g, nmaps, flags, false, &h);
+    if (rc) return rc;
+    if (!delta || !map || !aligned(delta, 16) || !aligned(map, 8)) return SHT_EINVAL;
+    if (overlap(delta, delta_bytes(h.nrings, mmax, nmaps), map, (size_t)h.npix * 8u * nmaps))
+        return SHT_EINVAL;
+    const GeomPlan *p;
+    if ((rc = get_geom(h, mmax, &p))) return rc;
+    return launch_fft_syn(*p, mmax, delta, map, nmaps, as_stream(stream));
+}
+
+int sht_map2delta(int mmax, const sht_geom *g, const double *map, void *delta, int nmaps,
+                  uint32_t flags, void *stream) {
+    HostGeom h;
+    int rc = check_common(mmax, mmax, g, nmaps, flags, true, &h);
+    if (rc) return rc;
+    if (!delta || !map || !aligned(delta, 16) || !aligned(map, 8)) return SHT_EINVAL;
+    if (overlap(delta, delta_bytes(h.nrings, mmax, nmaps), map, (size_t)h.npix * 8u * nmaps))
+        return SHT_EINVAL;
+    const GeomPlan *p;
+    if ((rc = get_geom(h, mmax, &p))) return rc;
+    return launch_fft_ana(*p, mmax, map, delta, nmaps, as_stream(stream));
+}
+
+int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void *alm, int nmaps,
+                  uint32_t flags, void *stream) {
+    HostGeom h;
+    int rc = check_common(lmax, mmax, g, nmaps, flags, false, &h);
+    if (rc) return rc;
+    if (!delta || !alm || !aligned(delta, 16) || !aligned(alm, 16)) return SHT_EINVAL;
+    if (overlap(delta, delta_bytes(h.nrings, mmax, nmaps), alm, alm_bytes(lmax, mmax, nmaps)))
+        return SHT_EINVAL;
+    const CoefTables *c;
+    const GeomPlan *p;
+    if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p))) return rc;
+    return launch_leg_ana(*c, *p, delta, alm, nmaps, as_stream(stream));
+}
+
+int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *map, int nmaps,
+                void *workspace, size_t ws_bytes, uint32_t flags, void *stream) {
+    HostGeom h;
+    int rc = check_common(lmax, mmax, g, nmaps, flags, false, &h);
+    if (rc) return rc;
+    if (!alm || !map || !aligned(alm, 16) || !aligned(map, 8)) return SHT_EINVAL;
+    const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
+    const size_t mb = (size_t)h.npix * 8u * nmaps;
+    if (!workspace || !aligned(workspace, 16) || ws_bytes < round256(ab) + round256(db))
+        return SHT_EWORKSPACE;
+    if (overlap(alm, ab, map, mb) || overlap(workspace, ws_bytes, alm, ab) ||
+        overlap(workspace, ws_bytes, map, mb))
+        return SHT_EINVAL;
+    const CoefTables *c;
+    const GeomPlan *p;
+    if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p))) return rc;
+    char *ws = static_cast<char *>(workspace);
+    void *aprime = ws, *delta = ws + round256(ab);
+    hipStream_t st = as_stream(stream);
+    if ((rc = launch_prescale(*c, alm, aprime, nmaps, st))) return rc;
+    if ((rc = launch_leg_syn(*c, *p, aprime, delta, nmaps, st))) return rc;
+    return launch_fft_syn(*p, mmax, delta, map, nmaps, st);
+}
+
+int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *alm, int nmaps,
+                void *workspace, size_t ws_bytes, uint32_t flags, void *stream) {
+    HostGeom h;
+    int rc = check_common(lmax, mmax, g, nmaps, flags, true, &h);
+    if (rc) return rc;
+    if (!alm || !map || !aligned(alm, 16) || !aligned(map, 8)) return SHT_EINVAL;
+    const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
+    const size_t mb = (size_t)h.npix * 8u * nmaps;
+    if (!workspace || !aligned(workspace, 16) || ws_bytes < round256(db)) return SHT_EWORKSPACE;
+    if (overlap(alm, ab, map, mb) || overlap(workspace, ws_bytes, alm, ab) ||
+        overlap(workspace, ws_bytes, map, mb))
+        return SHT_EINVAL;
+    const CoefTables *c;
+    const GeomPlan *p;
+    if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p))) return rc;
+    hipStream_t st = as_stream(stream);
+    if ((rc = launch_fft_ana(*p, mmax, map, workspace, nmaps, st))) return rc;
+    return launch_leg_ana(*c, *p, workspace, alm, nmaps, st);
+}
+
+const char *sht_strerror(int code) {
+    switch (code) {
+        case SHT_OK: return "success";
+        case SHT_EINVAL: return "invalid argument";
+        case SHT_EWORKSPACE: return "workspace missing or too small";
+        case SHT_EDEVICE: {
+            const char *s = last_hip_error();
+            return (s && *s) ? s : "HIP runtime error";
+        }
+        case SHT_ENOMEM: return "out of memory for plan tables";
+        case SHT_EUNSUPPORTED: return "unsupported flag or size";
+        default: return "unknown status code";
+    }
+}
+
+void sht_shutdown(void) { shutdown_all(); }
+
+}  // extern "C"

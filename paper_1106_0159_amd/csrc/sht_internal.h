@@ -1,0 +1,116 @@
+// Internal declarations shared by the host plan code and the HIP kernels of
+// libsht.so.  Nothing here is part of the public ABI (include/sht.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sht.h"
+
+namespace sht {
+
+constexpr int kBlock = 256;          // threads per workgroup of every kernel
+constexpr int kMaxFftLen = 8192;     // complex points one workgroup holds in LDS
+constexpr int kMaxRadices = 16;
+constexpr int kAnaMaxSlotsPerThread = 16;
+
+// Rescaling of the Legendre recurrence (exponent tracking).  A value is kept
+// as q * 2^(kScaleBits * sc) with sc <= 0.  While sc < 0 a value is below
+// 2^-(kScaleBits+60) in magnitude and its contribution is dropped; when the
+// carrier exceeds kRescaleThresh it is multiplied by 2^-kScaleBits and sc
+// incremented.  At sc == 0 the carrier is the value itself.
+constexpr int kScaleBits = 600;
+
+// Coefficient tables for one (lmax, mmax) on one device.  Packed (l, m)
+// index as for a_lm.  p_lm = cfac_lm * q_lm, q_lm = alpha_lm x q_{l-1,m} - q_{l-2,m}.
+struct CoefTables {
+    int lmax = -1, mmax = -1;
+    int64_t nalm = 0;
+    double *alpha = nullptr;  // [nalm]; alpha at l = m is 0, at l = m+1 sqrt(2m+3)
+    double *cfac = nullptr;   // [nalm]
+    double *mu = nullptr;     // [mmax+1]
+};
+
+// One FFT length (device view).  Points of length n are transformed in LDS
+// either directly (L == n, radices of n) or by Bluestein's chirp-z method
+// with a power-of-two length L >= 2n-1.
+struct FftDesc {
+    int n;
+    int L;
+    int nrad;
+    int bluestein;
+    int rad[kMaxRadices];
+    const double2 *tw;     // W_L[t] = exp(-2 pi i t / L), t < L
+    const double2 *chirp;  // b_t = exp(i pi t^2 / n), t < n          (Bluestein)
+    const double2 *kern;   // FFT_L of the extended chirp, divided by L (Bluestein)
+};
+
+// Geometry plan for one (ring set) on one device.
+struct GeomPlan {
+    int nrings = 0;
+    int nslots = 0;
+    int64_t npix = 0;
+    int max_L = 1;
+    int all_nphi_max = 1;
+    // slots: ring pairs (north, south) sharing one recurrence, sorted by sin(theta)
+    double *slot_x = nullptr;
+    double *slot_s = nullptr;
+    int32_t *slot_north = nullptr;
+    int32_t *slot_south = nullptr;   // -1 when unpaired
+    // rings
+    double *phi0 = nullptr;
+    double *weight = nullptr;        // null when the geometry has no weights
+    int64_t *ofs = nullptr;
+    int32_t *ring_desc = nullptr;    // index into descs
+    FftDesc *descs = nullptr;
+    std::vector<void *> owned;       // device allocations to free
+};
+
+struct DeviceContext;
+
+// Validated, normalised copy of the caller's geometry.
+struct HostGeom {
+    int nrings = 0;
+    std::vector<double> theta, phi0, weight;
+    std::vector<int32_t> nphi;
+    std::vector<int64_t> ofs;
+    bool has_weight = false;
+    int64_t npix = 0;
+};
+
+int validate_geom(const sht_geom *g, bool need_weight, HostGeom *out);
+int validate_sizes(int lmax, int mmax, int nmaps);
+
+// Plan lookup (builds on first use).  Thread safe.
+int get_coef(int lmax, int mmax, const CoefTables **out);
+int get_geom(const HostGeom &hg, int mmax_for_fft, const GeomPlan **out);
+
+void set_hip_error(hipError_t e, const char *where);
+#define SHT_HIP(call)                                        \
+    do {                                                     \
+        hipError_t e_ = (call);                              \
+        if (e_ != hipSuccess) {                              \
+            ::sht::set_hip_error(e_, #call);                 \
+            return SHT_EDEVICE;                              \
+        }                                                    \
+    } while (0)
+
+// Kernel launchers (k_legendre.hip, k_ring_fft.hip).  They enqueue only.
+int launch_prescale(const CoefTables &c, const void *alm, void *aprime, int nmaps, hipStream_t st);
+int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const void *aprime, void *delta,
+                   int nmaps, hipStream_t st);
+int launch_leg_ana(const CoefTables &c, const GeomPlan &p, const void *delta, void *alm, int nmaps,
+                   hipStream_t st);
+int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, double *map, int nmaps,
+                   hipStream_t st);
+int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, int nmaps,
+                   hipStream_t st);
+
+inline int64_t nalm_of(int lmax, int mmax) {
+    return (int64_t)(mmax + 1) * (2 * (int64_t)lmax + 2 - mmax) / 2;
+}
+
+}  // namespace sht

@@ -1,0 +1,431 @@
+// Host side of libsht.so: argument validation, recurrence-coefficient tables,
+// ring pairing, FFT plans and the per-device plan caches.
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+
+#include "sht_internal.h"
+
+namespace sht {
+
+static thread_local std::string g_last_hip_error;
+
+void set_hip_error(hipError_t e, const char *where) {
+    g_last_hip_error = std::string(hipGetErrorString(e)) + " (" + where + ")";
+}
+
+const char *last_hip_error() { return g_last_hip_error.c_str(); }
+
+int validate_sizes(int lmax, int mmax, int nmaps) {
+    if (lmax < 0 || mmax < 0 || mmax > lmax || nmaps < 1) return SHT_EINVAL;
+    // kernels index l in int and a_lm in int64; keep l*l and the LDS-resident
+    // FFT comfortably in range
+    if (lmax > 32768) return SHT_EUNSUPPORTED;
+    return SHT_OK;
+}
+
+int validate_geom(const sht_geom *g, bool need_weight, HostGeom *out) {
+    if (!g || g->nrings < 1 || !g->theta || !g->nphi || !g->phi0) return SHT_EINVAL;
+    if (need_weight && !g->weight) return SHT_EINVAL;
+    const int n = g->nrings;
+    HostGeom h;
+    h.nrings = n;
+    h.theta.assign(g->theta, g->theta + n);
+    h.nphi.assign(g->nphi, g->nphi + n);
+    h.phi0.assign(g->phi0, g->phi0 + n);
+    h.has_weight = g->weight != nullptr;
+    if (h.has_weight) h.weight.assign(g->weight, g->weight + n);
+    h.ofs.resize(n);
+    int64_t acc = 0;
+    for (int r = 0; r < n; ++r) {
+        const double t = h.theta[r];
+        if (!(t >= 0.0 && t <= M_PI)) return SHT_EINVAL;  // also rejects NaN
+        if (h.nphi[r] < 1 || !std::isfinite(h.phi0[r])) return SHT_EINVAL;
+        if (h.has_weight && !std::isfinite(h.weight[r])) return SHT_EINVAL;
+        if (g->ofs) {
+            h.ofs[r] = g->ofs[r];
+            if (h.ofs[r] < 0) return SHT_EINVAL;
+        } else {
+            h.ofs[r] = acc;
+            acc += h.nphi[r];
+        }
+    }
+    // ring pixel ranges must not overlap
+    std::vector<int> ord(n);
+    for (int r = 0; r < n; ++r) ord[r] = r;
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return h.ofs[a] < h.ofs[b]; });
+    int64_t npix = 0;
+    for (int i = 0; i < n; ++i) {
+        const int r = ord[i];
+        if (i > 0) {
+            const int q = ord[i - 1];
+            if (h.ofs[q] + h.nphi[q] > h.ofs[r]) return SHT_EINVAL;
+        }
+        npix = std::max<int64_t>(npix, h.ofs[r] + h.nphi[r]);
+    }
+    h.npix = npix;
+    *out = std::move(h);
+    return SHT_OK;
+}
+
+// ------------------------------------------------------------------ device memory helpers
+template <class T>
+static int upload(const std::vector<T> &v, T **dst, std::vector<void *> &owned) {
+    void *p = nullptr;
+    const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return SHT_ENOMEM;
+    }
+    owned.push_back(p);
+    if (!v.empty()) SHT_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    *dst = static_cast<T *>(p);
+    return SHT_OK;
+}
+
+static int current_device(int *dev) {
+    SHT_HIP(hipGetDevice(dev));
+    return SHT_OK;
+}
+
+// ------------------------------------------------------------------ coefficient tables
+// For one m: beta_l = sqrt((4l^2-1)/(l^2-m^2)) (eq. betaDef), c_m = c_{m+1} = 1,
+// c_l = (beta_l/beta_{l-1}) c_{l-2}, alpha_l = beta_l c_{l-1}/c_l.  Then
+// p_l = c_l q_l turns eq. assLegRec into q_l = alpha_l x q_{l-1} - q_{l-2}.
+// alpha is derived from the stored (rounded) c so that the effective
+// recurrence coefficients carry only their own rounding.
+static void coef_column(int lmax, int m, double *alpha, double *cfac) {
+    const int n = lmax - m + 1;
+    std::vector<long double> beta(n + 1, 0.0L);
+    for (int l = m + 1; l <= lmax; ++l) {
+        const long double L = l, M = m;
+        beta[l - m] = sqrtl((4.0L * L * L - 1.0L) / (L * L - M * M));
+    }
+    cfac[0] = 1.0;
+    alpha[0] = 0.0;
+    if (lmax >= m + 1) {
+        cfac[1] = 1.0;
+        alpha[1] = (double)beta[1];  // sqrt(2m+3), eq. pm1m
+    }
+    for (int l = m + 2; l <= lmax; ++l) {
+        const int i = l - m;
+        const long double c = beta[i] / beta[i - 1] * (long double)cfac[i - 2];
+        cfac[i] = (double)c;
+        alpha[i] = (double)(beta[i] * (long double)cfac[i - 1] / (long double)cfac[i]);
+    }
+}
+
+struct CoefEntry {
+    CoefTables t;
+    std::vector<void *> owned;
+};
+
+static std::mutex g_mu;
+static std::map<std::tuple<int, int, int>, std::unique_ptr<CoefEntry>> g_coef;
+
+int get_coef(int lmax, int mmax, const CoefTables **out) {
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_tuple(dev, lmax, mmax);
+    auto it = g_coef.find(key);
+    if (it != g_coef.end()) {
+        *out = &it->second->t;
+        return SHT_OK;
+    }
+    auto e = std::make_unique<CoefEntry>();
+    const int64_t na = nalm_of(lmax, mmax);
+    std::vector<double> alpha(na), cfac(na), mu(mmax + 1);
+    for (int m = 0; m <= mmax; ++m) {
+        const int64_t b = (int64_t)m * (2 * (int64_t)lmax + 1 - m) / 2 + m;
+        coef_column(lmax, m, alpha.data() + b, cfac.data() + b);
+    }
+    // mu_m of eq. pmm: mu_0 = 1/sqrt(4 pi), mu_m = mu_{m-1} sqrt((2m+1)/(2m))
+    long double v = 1.0L / sqrtl(4.0L * 3.141592653589793238462643383279502884L);
+    mu[0] = (double)v;
+    for (int m = 1; m <= mmax; ++m) {
+        v *= sqrtl((long double)(2 * m + 1) / (long double)(2 * m));
+        mu[m] = (double)v;
+    }
+    e->t.lmax = lmax;
+    e->t.mmax = mmax;
+    e->t.nalm = na;
+    if ((rc = upload(alpha, &e->t.alpha, e->owned)) || (rc = upload(cfac, &e->t.cfac, e->owned)) ||
+        (rc = upload(mu, &e->t.mu, e->owned))) {
+        for (void *p : e->owned) (void)hipFree(p);
+        return rc;
+    }
+    *out = &e->t;
+    g_coef[key] = std::move(e);
+    return SHT_OK;
+}
+
+// ------------------------------------------------------------------ FFT plans
+using cld = std::complex<long double>;
+static const long double kPiL = 3.141592653589793238462643383279502884L;
+
+static bool factor_small(int n, std::vector<int> &rad) {
+    rad.clear();
+    while (n % 4 == 0) { rad.push_back(4); n /= 4; }
+    while (n % 2 == 0) { rad.push_back(2); n /= 2; }
+    for (int p : {3, 5, 7, 11, 13}) {
+        while (n % p == 0) { rad.push_back(p); n /= p; }
+    }
+    return n == 1 && (int)rad.size() <= kMaxRadices;
+}
+
+// In-place radix-2 FFT (forward sign) in long double, length a power of two.
+static void host_fft_pow2(std::vector<cld> &a) {
+    const size_t n = a.size();
+    for (size_t i = 1, j = 0; i < n; ++i) {
+        size_t bit = n >> 1;
+        for (; j & bit; bit >>= 1) j ^= bit;
+        j ^= bit;
+        if (i < j) std::swap(a[i], a[j]);
+    }
+    for (size_t len = 2; len <= n; len <<= 1) {
+        for (size_t i = 0; i < n; i += len) {
+            for (size_t k = 0; k < len / 2; ++k) {
+                const long double ang = -2.0L * kPiL * (long double)k / (long double)len;
+                const cld w(cosl(ang), sinl(ang));
+                const cld u = a[i + k], v = a[i + k + len / 2] * w;
+                a[i + k] = u + v;
+                a[i + k + len / 2] = u - v;
+            }
+        }
+    }
+}
+
+struct FftCache {
+    std::map<int, double2 *> twiddles;      // by L
+    std::map<int, FftDesc> descs;           // by n
+    std::vector<void *> owned;
+};
+static std::map<int, std::unique_ptr<FftCache>> g_fft;  // by device
+
+static int twiddle_table(FftCache &fc, int L, const double2 **out) {
+    auto it = fc.twiddles.find(L);
+    if (it != fc.twiddles.end()) {
+        *out = it->second;
+        return SHT_OK;
+    }
+    std::vector<double2> w(L);
+    for (int t = 0; t < L; ++t) {
+        const long double a = -2.0L * kPiL * (long double)t / (long double)L;
+        w[t] = make_double2((double)cosl(a), (double)sinl(a));
+    }
+    double2 *d = nullptr;
+    int rc = upload(w, &d, fc.owned);
+    if (rc) return rc;
+    fc.twiddles[L] = d;
+    *out = d;
+    return SHT_OK;
+}
+
+static int fft_desc(FftCache &fc, int n, FftDesc *out) {
+    auto it = fc.descs.find(n);
+    if (it != fc.descs.end()) {
+        *out = it->second;
+        return SHT_OK;
+    }
+    FftDesc d;
+    std::memset(&d, 0, sizeof(d));
+    d.n = n;
+    std::vector<int> rad;
+    int rc;
+    if (factor_small(n, rad)) {
+        d.L = n;
+        d.bluestein = 0;
+    } else {
+        int L = 1;
+        while (L < 2 * n - 1) L <<= 1;
+        d.L = L;
+        d.bluestein = 1;
+        factor_small(L, rad);
+        // chirp b_t = exp(i pi t^2 / n), angle reduced exactly: t^2 mod 2n
+        std::vector<double2> b(n);
+        std::vector<cld> ext(L, cld(0, 0));
+        for (int t = 0; t < n; ++t) {
+            const long long q = (long long)t * t % (2LL * n);
+            const long double a = kPiL * (long double)q / (long double)n;
+            const cld v(cosl(a), sinl(a));
+            b[t] = make_double2((double)v.real(), (double)v.imag());
+            ext[t] = v;
+            if (t > 0) ext[L - t] = v;
+        }
+        host_fft_pow2(ext);
+        std::vector<double2> k(L);
+        for (int t = 0; t < L; ++t)
+            k[t] = make_double2((double)(ext[t].real() / L), (double)(ext[t].imag() / L));
+        double2 *db = nullptr, *dk = nullptr;
+        if ((rc = upload(b, &db, fc.owned)) || (rc = upload(k, &dk, fc.owned))) return rc;
+        d.chirp = db;
+        d.kern = dk;
+    }
+    if (d.L > kMaxFftLen) return SHT_EUNSUPPORTED;
+    d.nrad = (int)rad.size();
+    for (int i = 0; i < d.nrad; ++i) d.rad[i] = rad[i];
+    if ((rc = twiddle_table(fc, d.L, &d.tw))) return rc;
+    fc.descs[n] = d;
+    *out = d;
+    return SHT_OK;
+}
+
+// ------------------------------------------------------------------ geometry plans
+struct GeomEntry {
+    int dev;
+    HostGeom key;
+    GeomPlan plan;
+    uint64_t last_use;
+};
+static std::vector<std::unique_ptr<GeomEntry>> g_geom;
+static uint64_t g_clock = 0;
+constexpr size_t kMaxGeomPlans = 32;
+
+static bool same_geom(const HostGeom &a, const HostGeom &b) {
+    return a.nrings == b.nrings && a.has_weight == b.has_weight && a.theta == b.theta &&
+           a.nphi == b.nphi && a.phi0 == b.phi0 && a.ofs == b.ofs && a.weight == b.weight;
+}
+
+static void free_plan(GeomPlan &p) {
+    for (void *q : p.owned) (void)hipFree(q);
+    p.owned.clear();
+}
+
+// Mirror pairs: rings r, r' with |theta_r + theta_r' - pi| <= tol share one
+// recurrence (lambda_lm(-x) = (-1)^(l+m) lambda_lm(x)); the northern ring's
+// cos and sin are used for both.
+static void build_slots(const HostGeom &h, std::vector<double> &sx, std::vector<double> &ss,
+                        std::vector<int32_t> &sn, std::vector<int32_t> &sso) {
+    const double tol = 1e-14;
+    const int n = h.nrings;
+    std::vector<int> ord(n);
+    for (int r = 0; r < n; ++r) ord[r] = r;
+    std::sort(ord.begin(), ord.end(), [&](int a, int b) {
+        return h.theta[a] < h.theta[b] || (h.theta[a] == h.theta[b] && a < b);
+    });
+    struct S { double x, s; int n, so; };
+    std::vector<S> slots;
+    int i = 0, j = n - 1;
+    while (i <= j) {
+        const int a = ord[i], b = ord[j];
+        if (i == j) {
+            slots.push_back({std::cos(h.theta[a]), std::sin(h.theta[a]), a, -1});
+            break;
+        }
+        const double d = h.theta[a] + h.theta[b] - M_PI;
+        if (std::fabs(d) <= tol) {
+            slots.push_back({std::cos(h.theta[a]), std::sin(h.theta[a]), a, b});
+            ++i;
+            --j;
+        } else if (d < 0) {
+            slots.push_back({std::cos(h.theta[a]), std::sin(h.theta[a]), a, -1});
+            ++i;
+        } else {
+            slots.push_back({std::cos(h.theta[b]), std::sin(h.theta[b]), b, -1});
+            --j;
+        }
+    }
+    // polar slots first: neighbouring lanes then leave the rescaled regime together
+    std::stable_sort(slots.begin(), slots.end(), [](const S &p, const S &q) { return p.s < q.s; });
+    for (const S &s : slots) {
+        sx.push_back(s.x);
+        ss.push_back(s.s);
+        sn.push_back(s.n);
+        sso.push_back(s.so);
+    }
+}
+
+int get_geom(const HostGeom &hg, int /*mmax_for_fft*/, const GeomPlan **out) {
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    for (auto &e : g_geom) {
+        if (e->dev == dev && same_geom(e->key, hg)) {
+            e->last_use = ++g_clock;
+            *out = &e->plan;
+            return SHT_OK;
+        }
+    }
+    if (g_geom.size() >= kMaxGeomPlans) {
+        // evict the least recently used plan; kernels using it may be in flight
+        auto lru = std::min_element(g_geom.begin(), g_geom.end(),
+                                    [](const auto &a, const auto &b) { return a->last_use < b->last_use; });
+        int cur = dev;
+        SHT_HIP(hipSetDevice((*lru)->dev));
+        SHT_HIP(hipDeviceSynchronize());
+        free_plan((*lru)->plan);
+        SHT_HIP(hipSetDevice(cur));
+        g_geom.erase(lru);
+    }
+    auto &fcp = g_fft[dev];
+    if (!fcp) fcp = std::make_unique<FftCache>();
+    auto e = std::make_unique<GeomEntry>();
+    e->dev = dev;
+    e->key = hg;
+    GeomPlan &p = e->plan;
+    p.nrings = hg.nrings;
+    p.npix = hg.npix;
+    std::vector<double> sx, ss;
+    std::vector<int32_t> sn, sso;
+    build_slots(hg, sx, ss, sn, sso);
+    p.nslots = (int)sx.size();
+    std::vector<FftDesc> descs;
+    std::map<int, int> desc_index;
+    std::vector<int32_t> ring_desc(hg.nrings);
+    int maxL = 1, maxn = 1;
+    for (int r = 0; r < hg.nrings; ++r) {
+        const int n = hg.nphi[r];
+        auto it = desc_index.find(n);
+        if (it == desc_index.end()) {
+            FftDesc d;
+            rc = fft_desc(*fcp, n, &d);
+            if (rc) return rc;
+            desc_index[n] = (int)descs.size();
+            descs.push_back(d);
+            it = desc_index.find(n);
+        }
+        ring_desc[r] = it->second;
+        maxL = std::max(maxL, descs[it->second].L);
+        maxn = std::max(maxn, n);
+    }
+    p.max_L = maxL;
+    p.all_nphi_max = maxn;
+    if ((rc = upload(sx, &p.slot_x, p.owned)) || (rc = upload(ss, &p.slot_s, p.owned)) ||
+        (rc = upload(sn, &p.slot_north, p.owned)) || (rc = upload(sso, &p.slot_south, p.owned)) ||
+        (rc = upload(hg.phi0, &p.phi0, p.owned)) || (rc = upload(hg.ofs, &p.ofs, p.owned)) ||
+        (rc = upload(ring_desc, &p.ring_desc, p.owned)) || (rc = upload(descs, &p.descs, p.owned))) {
+        free_plan(p);
+        return rc;
+    }
+    if (hg.has_weight && (rc = upload(hg.weight, &p.weight, p.owned))) {
+        free_plan(p);
+        return rc;
+    }
+    e->last_use = ++g_clock;
+    *out = &e->plan;
+    g_geom.push_back(std::move(e));
+    return SHT_OK;
+}
+
+void shutdown_all() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    (void)hipDeviceSynchronize();
+    for (auto &e : g_geom) free_plan(e->plan);
+    g_geom.clear();
+    for (auto &kv : g_coef)
+        for (void *p : kv.second->owned) (void)hipFree(p);
+    g_coef.clear();
+    for (auto &kv : g_fft)
+        for (void *p : kv.second->owned) (void)hipFree(p);
+    g_fft.clear();
+}
+
+}  // namespace sht

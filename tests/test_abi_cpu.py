@@ -1,0 +1,141 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, sizes its workspace, and rejects invalid arguments on the host
+before any device work is enqueued."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import sht_inputs as si
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "sht.h")
+
+sht = pytest.importorskip("paper_1106_0159_amd")
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(sht.LIB_PATH):
+        pytest.skip("libsht.so not built")
+    return sht.lib()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sht_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_binding_exports():
+    assert declared_functions() == sorted(sht.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    # and the same names are visible to the dynamic linker
+    nm = os.popen(f"nm -D --defined-only {sht.LIB_PATH}").read()
+    for name in declared_functions():
+        assert re.search(rf"\bT {name}$", nm, flags=re.M), name
+
+
+def test_strerror_strings(L):
+    for code in (0, -1, -2, -4, -5, 7):
+        assert len(L.sht_strerror(code)) > 0
+    assert L.sht_strerror(sht.SHT_EINVAL) == b"invalid argument"
+
+
+def _ws(lmax, mmax, g, nmaps=1, flags=0):
+    return sht.workspace_bytes(lmax, mmax, g, nmaps, flags)
+
+
+def test_workspace_bytes_values_and_monotonic():
+    g = si.healpix(8)
+    lmax = 16
+    na = si.nalm(lmax, lmax)
+    r256 = lambda b: (b + 255) // 256 * 256
+    assert _ws(lmax, lmax, g) == r256(na * 16) + r256(g.nrings * (lmax + 1) * 16)
+    assert _ws(lmax, lmax, g, 3) == r256(3 * na * 16) + r256(3 * g.nrings * (lmax + 1) * 16)
+    prev = 0
+    for l in range(0, 40, 3):
+        cur = _ws(l, l, g)
+        assert cur > prev
+        prev = cur
+    assert _ws(lmax, lmax, g) % 256 == 0
+
+
+@pytest.mark.parametrize("args", [
+    (-1, 0, 1, 0), (4, 5, 1, 0), (4, -1, 1, 0), (4, 4, 0, 0), (4, 4, 1, 1 << 3),
+])
+def test_workspace_bytes_invalid(args):
+    lmax, mmax, nmaps, flags = args
+    assert _ws(lmax, mmax, si.healpix(2), nmaps, flags) == 0
+
+
+def _geom_variant(**kw):
+    g = si.healpix(2)
+    d = dict(theta=g.theta.copy(), nphi=g.nphi.copy(), phi0=g.phi0.copy(), weight=g.weight.copy(),
+             ofs=g.ofs.copy())
+    d.update(kw)
+    return si.Geometry(d["theta"], d["nphi"], d["phi0"], d["weight"], d["ofs"])
+
+
+BAD_GEOMS = {
+    "theta_negative": lambda g: _geom_variant(theta=np.r_[-0.1, g.theta[1:]]),
+    "theta_above_pi": lambda g: _geom_variant(theta=np.r_[g.theta[:-1], 3.2]),
+    "theta_nan": lambda g: _geom_variant(theta=np.r_[np.nan, g.theta[1:]]),
+    "nphi_zero": lambda g: _geom_variant(nphi=np.r_[0, g.nphi[1:]].astype(np.int32)),
+    "phi0_inf": lambda g: _geom_variant(phi0=np.r_[np.inf, g.phi0[1:]]),
+    "overlap": lambda g: _geom_variant(ofs=np.r_[0, 1, g.ofs[2:]].astype(np.int64)),
+    "ofs_negative": lambda g: _geom_variant(ofs=np.r_[-4, g.ofs[1:]].astype(np.int64)),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BAD_GEOMS))
+def test_invalid_geometry_rejected_on_host(L, name):
+    g = BAD_GEOMS[name](si.healpix(2))
+    gh = sht.GeomHandle(g)
+    fake = ctypes.c_void_p(0x10000)  # never dereferenced: validation fails first
+    rc = L.sht_alm2map(4, 4, gh.ref(), fake, fake, 1, fake, 1 << 20, 0, None)
+    assert rc == sht.SHT_EINVAL
+    rc = L.sht_map2alm(4, 4, gh.ref(), fake, fake, 1, fake, 1 << 20, 0, None)
+    assert rc == sht.SHT_EINVAL
+    assert L.sht_workspace_bytes(4, 4, gh.ref(), 1, 0) == 0
+
+
+def test_invalid_arguments_rejected_on_host(L):
+    g = sht.GeomHandle(si.healpix(2))
+    a = ctypes.c_void_p(0x100000)
+    m = ctypes.c_void_p(0x200000)
+    w = ctypes.c_void_p(0x300000)
+    big = 1 << 20
+    # sizes
+    assert L.sht_alm2map(-1, 0, g.ref(), a, m, 1, w, big, 0, None) == sht.SHT_EINVAL
+    assert L.sht_alm2map(4, 5, g.ref(), a, m, 1, w, big, 0, None) == sht.SHT_EINVAL
+    assert L.sht_alm2map(4, 4, g.ref(), a, m, 0, w, big, 0, None) == sht.SHT_EINVAL
+    # flags
+    assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, big, 1, None) == sht.SHT_EUNSUPPORTED
+    # null and misaligned pointers
+    assert L.sht_alm2map(4, 4, g.ref(), None, m, 1, w, big, 0, None) == sht.SHT_EINVAL
+    assert L.sht_alm2map(4, 4, g.ref(), a, None, 1, w, big, 0, None) == sht.SHT_EINVAL
+    assert L.sht_alm2map(4, 4, g.ref(), ctypes.c_void_p(0x100008), m, 1, w, big, 0, None) == sht.SHT_EINVAL
+    assert L.sht_alm2map(4, 4, None, a, m, 1, w, big, 0, None) == sht.SHT_EINVAL
+    # workspace
+    need = L.sht_workspace_bytes(4, 4, g.ref(), 1, 0)
+    assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, None, big, 0, None) == sht.SHT_EWORKSPACE
+    assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, need - 1, 0, None) == sht.SHT_EWORKSPACE
+    assert L.sht_map2alm(4, 4, g.ref(), m, a, 1, w, 16, 0, None) == sht.SHT_EWORKSPACE
+    # aliasing buffers
+    assert L.sht_alm2map(4, 4, g.ref(), a, a, 1, w, big, 0, None) == sht.SHT_EINVAL
+    assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, a, big, 0, None) == sht.SHT_EINVAL
+    # analysis needs weights
+    nw = sht.GeomHandle(si.healpix(2), with_weight=False)
+    assert L.sht_map2alm(4, 4, nw.ref(), m, a, 1, w, big, 0, None) == sht.SHT_EINVAL
+    assert L.sht_map2delta(4, nw.ref(), m, a, 1, 0, None) == sht.SHT_EINVAL
+    # stage entry points
+    assert L.sht_delta2alm(4, 5, g.ref(), a, m, 1, 0, None) == sht.SHT_EINVAL
+    assert L.sht_delta2map(4, g.ref(), None, m, 1, 0, None) == sht.SHT_EINVAL
+    assert L.sht_alm2delta(4, 4, g.ref(), a, m, 1, w, 8, 0, None) == sht.SHT_EWORKSPACE
