@@ -1,0 +1,244 @@
+"""Benchmark: FP64 alm2map + map2alm on HEALPix N_side=1024, lmax=mmax=2048.
+
+One step = one map through both transforms, with inputs resident in HBM:
+    alm --(Legendre synthesis)--> Delta --(ring FFT synthesis)--> map
+    map --(ring FFT analysis)--> Delta^S --(Legendre analysis)--> alm'
+called through the four stage entry points of the C ABI (their composition is
+exactly sht_alm2map followed by sht_map2alm), with HIP events on the launch
+stream between stages.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_FP64_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+PEAK_HBM_GBS = 8000.0
+FLOPS_PER_TRIPLE = 8           # recurrence 4 + complex-by-real contraction 4 per (slot, l, m)
+DOMINANT_SOURCES = ["paper_1106_0159_amd/csrc/k_legendre.hip"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in DOMINANT_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: str):
+    """HBM bytes per launch from committed counter runs, if the kernel source is unchanged."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(kernel)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def count_triples(geom_handle_slots: int, lmax: int, mmax: int) -> int:
+    nalm = (mmax + 1) * (2 * lmax + 2 - mmax) // 2
+    return geom_handle_slots * nalm
+
+
+def mirror_slots(theta) -> int:
+    """Number of ring slots (mirror pairs plus unpaired rings), as the library forms them."""
+    th = sorted(float(t) for t in theta)
+    i, j, n = 0, len(th) - 1, 0
+    while i <= j:
+        if i == j:
+            n += 1
+            break
+        d = th[i] + th[j] - math.pi
+        if abs(d) <= 1e-14:
+            i += 1
+            j -= 1
+        elif d < 0:
+            i += 1
+        else:
+            j -= 1
+        n += 1
+    return n
+
+
+def cpu_baseline(g, lmax, a, mp, target_s: float = 12.0):
+    """Time the oracle on a strided sample of rings (alm2map) and of m (map2alm)."""
+    import numpy as np
+
+    import oracle
+    cores = oracle.get_threads()
+    # calibrate with a small sample, then size the sample to about target_s in total
+    rings = np.arange(0, g.nrings, 256, dtype=np.int32)
+    t0 = time.perf_counter()
+    oracle.alm2map(lmax, lmax, g, a, rings=rings)
+    t_r = (time.perf_counter() - t0) / len(rings)
+    ms = np.arange(0, lmax + 1, 256, dtype=np.int32)
+    t0 = time.perf_counter()
+    oracle.map2alm(lmax, lmax, g, mp, ms=ms)
+    t_m = (time.perf_counter() - t0) / len(ms)
+    k_r = max(1, min(g.nrings, int(0.5 * target_s / max(t_r, 1e-9))))
+    k_m = max(1, min(lmax + 1, int(0.5 * target_s / max(t_m, 1e-9))))
+    rings = np.unique(np.linspace(0, g.nrings - 1, k_r).round().astype(np.int32))
+    ms = np.unique(np.linspace(0, lmax, k_m).round().astype(np.int32))
+    t0 = time.perf_counter()
+    oracle.alm2map(lmax, lmax, g, a, rings=rings)
+    t_syn = (time.perf_counter() - t0) * g.nrings / len(rings)
+    t0 = time.perf_counter()
+    oracle.map2alm(lmax, lmax, g, mp, ms=ms)
+    t_ana = (time.perf_counter() - t0) * (lmax + 1) / len(ms)
+    return {
+        "value": 1.0 / (t_syn + t_ana),
+        "unit": "maps/s",
+        "cores": int(cores),
+        "kind": "oracle",
+        "sample": (f"oracle alm2map on {len(rings)} of {g.nrings} rings (evenly spaced) and map2alm on "
+                   f"{len(ms)} of {lmax + 1} m values (evenly spaced), scaled to the full map; "
+                   f"est. {t_syn:.1f} s + {t_ana:.1f} s per map"),
+    }
+
+
+def copy_probe(nbytes: int) -> None:
+    """A plain device copy of known size, for calibrating HBM byte counters."""
+    import torch
+    src = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "launches": 3}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nside", type=int, default=1024)
+    ap.add_argument("--lmax", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, help="run only a device copy of this many bytes")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); run it with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+    if args.copy_probe:
+        copy_probe(args.copy_probe)
+        return
+
+    import numpy as np
+    import torch
+
+    import paper_1106_0159_amd as sht
+    import sht_inputs as si
+
+    nside = args.nside
+    lmax = args.lmax if args.lmax is not None else 2 * nside
+    g = si.healpix(nside)
+    gh = sht.GeomHandle(g)
+    a_np = si.powerlaw_alm(lmax, lmax, si.config_seed(2))
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    a = torch.from_numpy(a_np).to(dev)
+    delta = torch.empty((g.nrings, lmax + 1), dtype=torch.complex128, device=dev)
+    delta_s = torch.empty_like(delta)
+    mp = torch.zeros(g.npix, dtype=torch.float64, device=dev)
+    a_out = torch.empty_like(a)
+    ws = sht.workspace(lmax, lmax, gh, 1, dev)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        sht.alm2delta(a, gh, lmax, lmax, out=delta, ws=ws)
+        if ev is not None:
+            ev[1].record()
+        sht.delta2map(delta, gh, lmax, out=mp)
+        if ev is not None:
+            ev[2].record()
+        sht.map2delta(mp, gh, lmax, out=delta_s)
+        if ev is not None:
+            ev[3].record()
+        sht.delta2alm(delta_s, gh, lmax, lmax, out=a_out)
+        if ev is not None:
+            ev[4].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    K = args.steps
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    stage_names = ["leg_syn", "fft_syn", "fft_ana", "leg_ana"]
+    stage_ms = {n: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(K)]))
+                for i, n in enumerate(stage_names)}
+    step_ms = float(np.mean([evs[k][0].elapsed_time(evs[k][4]) for k in range(K)]))
+    ms_per_step = max(wall * 1000.0 / K, step_ms)
+
+    nslots = mirror_slots(g.theta)
+    triples = count_triples(nslots, lmax, lmax)
+    flops = FLOPS_PER_TRIPLE * triples
+    dom = max(("leg_syn", "leg_ana"), key=lambda n: stage_ms[n])
+    achieved = flops / (stage_ms[dom] * 1e-3) / 1e12
+    rec = {
+        "metric": "maps/s at lmax=2048 (plain FP64 vs batched mixed); p50/p99 solve latency",
+        "value": 1000.0 / ms_per_step,
+        "unit": "maps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"FP64 alm2map+map2alm, HEALPix nside={nside}, lmax=mmax={lmax}, 1 map, power-law a_lm",
+            "mode": "plain_fp64",
+            "nside": nside, "lmax": lmax, "mmax": lmax, "nmaps": 1,
+            "nrings": g.nrings, "npix": g.npix, "slots": nslots,
+        },
+        "stages_ms": stage_ms,
+        "alm2map_maps_per_s": 1000.0 / (stage_ms["leg_syn"] + stage_ms["fft_syn"]),
+        "map2alm_maps_per_s": 1000.0 / (stage_ms["fft_ana"] + stage_ms["leg_ana"]),
+        "roofline": {
+            "kernel": {"leg_syn": "k_prescale + k_leg_syn", "leg_ana": "k_leg_ana"}[dom],
+            "bound": "alu",
+            "achieved": achieved,
+            "peak": PEAK_FP64_VALU_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP64_VALU_TFLOPS,
+            "traffic": stored_traffic(dom),
+            "flops_per_launch": flops,
+        },
+    }
+    if not args.no_cpu_baseline:
+        mp_np = mp.cpu().numpy()
+        rec["cpu_baseline"] = cpu_baseline(g, lmax, a_np, mp_np)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -70,6 +70,14 @@ def _pack(theta, nphi, phi0, weight, name) -> Geometry:
     return g
 
 
+def _mirror(theta_n):
+    """Colatitudes of the mirror rings: pi - theta computed in long double, rounded once."""
+    return (_PI_L - np.asarray(theta_n, dtype=np.longdouble)).astype(np.float64)
+
+
+_PI_L = np.longdouble("3.14159265358979323846264338327950288")
+
+
 @functools.lru_cache(maxsize=16)
 def _gl_north(n: int):
     """Positive Gauss-Legendre nodes (descending) and weights, long-double Newton.
@@ -111,7 +119,7 @@ def gauss_legendre(nrings: int, nphi: int, phi0: float = 0.0) -> Geometry:
     wts = np.empty(nrings)
     theta[:half] = th_n
     wts[:half] = w_n
-    theta[nrings - half:] = (math.pi - th_n)[::-1]
+    theta[nrings - half:] = _mirror(th_n)[::-1]
     wts[nrings - half:] = w_n[::-1]
     if nrings % 2:
         theta[half] = math.pi / 2
@@ -150,7 +158,7 @@ def healpix(nside: int) -> Geometry:
     for i in range(2 * nside + 1, 4 * nside):           # southern half
         r = i - 1
         m = 4 * nside - i                               # mirrored northern ring index
-        theta[r] = math.pi - theta[m - 1]
+        theta[r] = float(_mirror(np.array([theta[m - 1]]))[0])
         if i > 3 * nside:
             nphi[r] = nphi[m - 1]
             phi0[r] = phi0[m - 1]

@@ -15,7 +15,7 @@ def test_healpix_geometry(nside):
     assert abs(float(np.sum(g.weight * g.nphi)) - 4 * math.pi) < 1e-12
     assert np.all(np.diff(g.theta) > 0)
     # mirror symmetry of the ring set
-    assert np.allclose(g.theta + g.theta[::-1], math.pi, rtol=0, atol=4e-16)
+    assert np.allclose(g.theta + g.theta[::-1], math.pi, rtol=0, atol=1e-15)
     assert np.array_equal(g.nphi, g.nphi[::-1])
     # equatorial belt
     assert np.all(g.nphi[nside - 1: 3 * nside] == 4 * nside)
