@@ -174,7 +174,7 @@ def main():
         sht.map2delta(mp, gh, lmax, out=delta_s)
         if ev is not None:
             ev[3].record()
-        sht.delta2alm(delta_s, gh, lmax, lmax, out=a_out)
+        sht.delta2alm(delta_s, gh, lmax, lmax, out=a_out, ws=ws)
         if ev is not None:
             ev[4].record()
 
@@ -224,7 +224,7 @@ def main():
         "alm2map_maps_per_s": 1000.0 / (stage_ms["leg_syn"] + stage_ms["fft_syn"]),
         "map2alm_maps_per_s": 1000.0 / (stage_ms["fft_ana"] + stage_ms["leg_ana"]),
         "roofline": {
-            "kernel": {"leg_syn": "k_prescale + k_leg_syn", "leg_ana": "k_leg_ana"}[dom],
+            "kernel": {"leg_syn": "k_prescale + k_leg_syn", "leg_ana": "k_leg_ana + k_ana_combine"}[dom],
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP64_VALU_TFLOPS,

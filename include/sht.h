@@ -72,9 +72,9 @@ enum sht_status {
     SHT_EUNSUPPORTED = -5   /* unknown flag bit, or a size beyond the kernels' limits */
 };
 
-/* Bytes of device workspace needed by sht_alm2map, sht_map2alm and
- * sht_alm2delta for these arguments (a multiple of 256; the same value serves
- * all three).  Returns 0 if the arguments are invalid. */
+/* Bytes of device workspace needed by sht_alm2map, sht_map2alm,
+ * sht_alm2delta and sht_delta2alm for these arguments (a multiple of 256; the
+ * same value serves all four).  Returns 0 if the arguments are invalid. */
 size_t sht_workspace_bytes(int lmax, int mmax, const sht_geom *g, int nmaps, uint32_t flags);
 
 /* Synthesis (Sec. 3, Alg. 2): Delta^A_m(r) by the l-recurrence contracted
@@ -103,8 +103,8 @@ int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *
  * themselves (and for per-stage timing).  sht_alm2map = sht_alm2delta then
  * sht_delta2map; sht_map2alm = sht_map2delta then sht_delta2alm.
  *   delta      DEVICE complex128 [nmaps][nrings][mmax+1]
- * sht_alm2delta writes every Delta_m(r) (eq. DeltaDef) and needs a workspace
- * of sht_workspace_bytes(...) bytes; the other three need none. */
+ * sht_alm2delta and sht_delta2alm need a workspace of sht_workspace_bytes(...)
+ * bytes (it must not alias their other buffers); the two ring stages need none. */
 int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *delta,
                   int nmaps, void *workspace, size_t ws_bytes, uint32_t flags, void *stream);
 int sht_delta2map(int mmax, const sht_geom *g, const void *delta, double *map, int nmaps,
@@ -112,7 +112,7 @@ int sht_delta2map(int mmax, const sht_geom *g, const void *delta, double *map, i
 int sht_map2delta(int mmax, const sht_geom *g, const double *map, void *delta, int nmaps,
                   uint32_t flags, void *stream);
 int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void *alm,
-                  int nmaps, uint32_t flags, void *stream);
+                  int nmaps, void *workspace, size_t ws_bytes, uint32_t flags, void *stream);
 
 /* Static description of a status code.  For SHT_EDEVICE the text of the
  * last HIP error seen by the calling thread is returned instead. */

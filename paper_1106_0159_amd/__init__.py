@@ -59,7 +59,7 @@ def lib() -> ctypes.CDLL:
             f.restype = I
             f.argtypes = [I, GP, P, P, I, U, P]
         L.sht_delta2alm.restype = I
-        L.sht_delta2alm.argtypes = [I, I, GP, P, P, I, U, P]
+        L.sht_delta2alm.argtypes = [I, I, GP, P, P, I, P, S, U, P]
         L.sht_strerror.restype = ctypes.c_char_p
         L.sht_strerror.argtypes = [I]
         L.sht_shutdown.restype = None
@@ -206,7 +206,7 @@ def map2delta(mp, geom, mmax: int, out=None, stream=None):
     return out
 
 
-def delta2alm(delta, geom, lmax: int, mmax: int | None = None, out=None, stream=None):
+def delta2alm(delta, geom, lmax: int, mmax: int | None = None, out=None, ws=None, stream=None):
     """Legendre analysis stage: a_lm [..., nalm] from Delta^S [..., nrings, mmax+1]."""
     torch = _torch()
     mmax = lmax if mmax is None else mmax
@@ -214,7 +214,10 @@ def delta2alm(delta, geom, lmax: int, mmax: int | None = None, out=None, stream=
     nm = _nmaps_of(delta, g.nrings * (mmax + 1))
     if out is None:
         out = torch.empty(delta.shape[:-2] + (nalm(lmax, mmax),), dtype=torch.complex128, device=delta.device)
-    rc = lib().sht_delta2alm(lmax, mmax, g.ref(), delta.data_ptr(), out.data_ptr(), nm, 0, _stream_ptr(stream))
+    if ws is None:
+        ws = workspace(lmax, mmax, g, nm, delta.device)
+    rc = lib().sht_delta2alm(lmax, mmax, g.ref(), delta.data_ptr(), out.data_ptr(), nm, ws.data_ptr(),
+                             ws.numel() * ws.element_size(), 0, _stream_ptr(stream))
     _check(rc, "sht_delta2alm")
     return out
 

@@ -20,11 +20,12 @@
 // rings loop outermost; here a workgroup owns one m for a tile of ring
 // pairs, so the m-dependent loop length is uniform across the workgroup and
 // a_lm, alpha are wave-uniform scalar loads):
-//   synthesis  grid.x = (m, 256-slot tile) with m ascending (longest first),
-//              grid.y = map; one slot per lane, no reduction needed.
-//   analysis   grid.x = m (ascending), grid.y = map; a workgroup owns every
-//              slot of its m (T slots per lane), sums over its lanes in LDS
-//              in a fixed order: no atomics, bitwise deterministic.
+//   synthesis  grid.x = (m, 512-slot tile) with m ascending (longest first),
+//              grid.y = map; two slots per lane, no reduction needed.
+//   analysis   grid.x = (m ascending, slot group), grid.y = map; a workgroup
+//              owns up to 1024 slots of its m (T slots per lane), sums over its
+//              lanes in LDS in a fixed order, and groups are summed in order
+//              by a second small kernel: no atomics, bitwise deterministic.
 //
 // Underflow near the poles (Sec. 2.1, rescaling; the paper leaves the
 // algorithm to its references): a value is held as q * 2^(600 sc), sc <= 0.
@@ -87,6 +88,8 @@ __global__ __launch_bounds__(kBlock) void k_prescale(int64_t nalm, int lmax, int
     }
 }
 
+// Synthesis: lane i of tile t owns slots t*256*T + i + 256*u, u < T.
+template <int T>
 __global__ __launch_bounds__(kBlock) void k_leg_syn(int lmax, int mmax, int nslots, int tiles,
                                                     int nrings, int64_t nalm,
                                                     const double2 *__restrict__ ap,
@@ -98,98 +101,210 @@ __global__ __launch_bounds__(kBlock) void k_leg_syn(int lmax, int mmax, int nslo
                                                     const int32_t *__restrict__ rsouth,
                                                     double2 *__restrict__ delta) {
     const int m = blockIdx.x / tiles;
-    const int slot = (blockIdx.x - m * tiles) * kBlock + threadIdx.x;
+    const int tile = blockIdx.x - m * tiles;
     const int map = blockIdx.y;
-    const bool active = slot < nslots;
-    const double x = active ? sx[slot] : 0.0;
-    const double s = active ? ss[slot] : 1.0;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;  // (l, m) lives at base + l
     const double2 *__restrict__ a = ap + (int64_t)map * nalm + base;
     const double *__restrict__ al = alpha + base;
+    const double mu_m = mu[m];
 
-    int sc;
-    const double seed = seed_carrier(m, s, mu[m], sc);
-    // state (q_{l-2}, q_{l-1}) before step l; (-seed, 0) makes step l = m yield the seed
-    double q2 = -seed, q1 = 0.0;
-    double cf = (sc == 0) ? 1.0 : 0.0;
-    double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
-
-#define SHT_REC(L)                               \
-    {                                            \
-        const double t_ = al[(L)] * x;           \
-        const double q_ = fma(t_, q1, -q2);      \
-        q2 = q1;                                 \
-        q1 = q_;                                 \
+    double x[T], q1[T], q2[T], cf[T], er[T], ei[T], orr[T], oi[T];
+    int sc[T];
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int slot = tile * kBlock * T + u * kBlock + threadIdx.x;
+        const bool act = slot < nslots;
+        x[u] = act ? sx[slot] : 0.0;
+        const double s = act ? ss[slot] : 1.0;
+        const double seed = seed_carrier(m, s, mu_m, sc[u]);
+        // state (q_{l-2}, q_{l-1}) before step l; (-seed, 0) makes step l = m yield the seed
+        q2[u] = -seed;
+        q1[u] = 0.0;
+        cf[u] = (sc[u] == 0) ? 1.0 : 0.0;
+        er[u] = ei[u] = orr[u] = oi[u] = 0.0;
     }
-#define SHT_RESCALE()                            \
-    if (sc < 0 && fabs(q1) > kThresh) {          \
-        q1 *= kDown;                             \
-        q2 *= kDown;                             \
-        ++sc;                                    \
-        cf = (sc == 0) ? 1.0 : 0.0;              \
-    }
+    auto any_scaled = [&]() {
+        bool b = false;
+#pragma unroll
+        for (int u = 0; u < T; ++u) b |= (sc[u] < 0);
+        return b;
+    };
+    auto all_scaled = [&]() {
+        bool b = true;
+#pragma unroll
+        for (int u = 0; u < T; ++u) b &= (sc[u] < 0);
+        return b;
+    };
+    auto rec = [&](double av) {
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const double q = fma(av * x[u], q1[u], -q2[u]);
+            q2[u] = q1[u];
+            q1[u] = q;
+        }
+    };
+    auto rescale = [&]() {
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            if (sc[u] < 0 && fabs(q1[u]) > kThresh) {
+                q1[u] *= kDown;
+                q2[u] *= kDown;
+                ++sc[u];
+                cf[u] = (sc[u] == 0) ? 1.0 : 0.0;
+            }
+        }
+    };
 
     int l = m;
-    // (A0) all lanes below range: recurrence only
-    while (l + 1 <= lmax && __all(sc < 0)) {
-        SHT_REC(l);
-        SHT_REC(l + 1);
-        SHT_RESCALE();
+    // (A0) every value below range: recurrence only
+    while (l + 1 <= lmax && __all(all_scaled())) {
+        rec(al[l]);
+        rec(al[l + 1]);
+        rescale();
         l += 2;
     }
-    // (A) mixed: weight terms by cf
-    while (l + 1 <= lmax && __any(sc < 0)) {
-        SHT_REC(l);
-        {
-            const double p = cf * q1;
-            const double2 c = a[l];
-            er = fma(c.x, p, er);
-            ei = fma(c.y, p, ei);
+    // (A) some value below range: terms weighted by cf (0 or 1)
+    while (l + 1 <= lmax && __any(any_scaled())) {
+        const double2 c0 = a[l], c1 = a[l + 1];
+        rec(al[l]);
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const double p = cf[u] * q1[u];
+            er[u] = fma(c0.x, p, er[u]);
+            ei[u] = fma(c0.y, p, ei[u]);
         }
-        SHT_REC(l + 1);
-        {
-            const double p = cf * q1;
-            const double2 c = a[l + 1];
-            orr = fma(c.x, p, orr);
-            oi = fma(c.y, p, oi);
+        rec(al[l + 1]);
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const double p = cf[u] * q1[u];
+            orr[u] = fma(c1.x, p, orr[u]);
+            oi[u] = fma(c1.y, p, oi[u]);
         }
-        SHT_RESCALE();
+        rescale();
         l += 2;
     }
-    // (B) all lanes in range
+    // (B) all values in range: four steps per iteration, next block's
+    // coefficients loaded one iteration ahead
+    if (l + 3 <= lmax) {
+        double a0 = al[l], a1 = al[l + 1], a2 = al[l + 2], a3 = al[l + 3];
+        double2 c0 = a[l], c1 = a[l + 1], c2 = a[l + 2], c3 = a[l + 3];
+        for (;;) {
+            const bool more = (l + 7 <= lmax);
+            double n0 = 0, n1 = 0, n2 = 0, n3 = 0;
+            double2 d0 = c0, d1 = c1, d2 = c2, d3 = c3;
+            if (more) {
+                n0 = al[l + 4]; n1 = al[l + 5]; n2 = al[l + 6]; n3 = al[l + 7];
+                d0 = a[l + 4]; d1 = a[l + 5]; d2 = a[l + 6]; d3 = a[l + 7];
+            }
+            rec(a0);
+#pragma unroll
+            for (int u = 0; u < T; ++u) { er[u] = fma(c0.x, q1[u], er[u]); ei[u] = fma(c0.y, q1[u], ei[u]); }
+            rec(a1);
+#pragma unroll
+            for (int u = 0; u < T; ++u) { orr[u] = fma(c1.x, q1[u], orr[u]); oi[u] = fma(c1.y, q1[u], oi[u]); }
+            rec(a2);
+#pragma unroll
+            for (int u = 0; u < T; ++u) { er[u] = fma(c2.x, q1[u], er[u]); ei[u] = fma(c2.y, q1[u], ei[u]); }
+            rec(a3);
+#pragma unroll
+            for (int u = 0; u < T; ++u) { orr[u] = fma(c3.x, q1[u], orr[u]); oi[u] = fma(c3.y, q1[u], oi[u]); }
+            l += 4;
+            if (!more) break;
+            a0 = n0; a1 = n1; a2 = n2; a3 = n3;
+            c0 = d0; c1 = d1; c2 = d2; c3 = d3;
+        }
+    }
+    // remaining steps (fewer than four), weighted by cf in case phase (A) ran out of l
     for (; l + 1 <= lmax; l += 2) {
-        SHT_REC(l);
-        const double2 c0 = a[l];
-        er = fma(c0.x, q1, er);
-        ei = fma(c0.y, q1, ei);
-        SHT_REC(l + 1);
-        const double2 c1 = a[l + 1];
-        orr = fma(c1.x, q1, orr);
-        oi = fma(c1.y, q1, oi);
+        const double2 c0 = a[l], c1 = a[l + 1];
+        rec(al[l]);
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const double p = cf[u] * q1[u];
+            er[u] = fma(c0.x, p, er[u]);
+            ei[u] = fma(c0.y, p, ei[u]);
+        }
+        rec(al[l + 1]);
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const double p = cf[u] * q1[u];
+            orr[u] = fma(c1.x, p, orr[u]);
+            oi[u] = fma(c1.y, p, oi[u]);
+        }
     }
     if (l == lmax) {  // one trailing step with even (l - m)
-        SHT_REC(l);
-        const double p = cf * q1;
-        const double2 c = a[l];
-        er = fma(c.x, p, er);
-        ei = fma(c.y, p, ei);
+        const double2 c0 = a[l];
+        rec(al[l]);
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const double p = cf[u] * q1[u];
+            er[u] = fma(c0.x, p, er[u]);
+            ei[u] = fma(c0.y, p, ei[u]);
+        }
     }
-#undef SHT_REC
-#undef SHT_RESCALE
 
-    if (active) {
-        double2 *d = delta + (int64_t)map * nrings * (mmax + 1);
-        d[(int64_t)rn[slot] * (mmax + 1) + m] = make_double2(er + orr, ei + oi);
-        const int r2 = rsouth[slot];
-        if (r2 >= 0) d[(int64_t)r2 * (mmax + 1) + m] = make_double2(er - orr, ei - oi);
+    double2 *d = delta + (int64_t)map * nrings * (mmax + 1);
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int slot = tile * kBlock * T + u * kBlock + threadIdx.x;
+        if (slot < nslots) {
+            d[(int64_t)rn[slot] * (mmax + 1) + m] = make_double2(er[u] + orr[u], ei[u] + oi[u]);
+            const int r2 = rsouth[slot];
+            if (r2 >= 0) d[(int64_t)r2 * (mmax + 1) + m] = make_double2(er[u] - orr[u], ei[u] - oi[u]);
+        }
     }
 }
 
-constexpr int kChunk = 16;  // l values per reduction round in analysis
+constexpr int kChunk = 8;  // l values per reduction round in analysis
 
+// One chunk of kChunk recurrence steps for the T slots of a lane, accumulating
+// sum_slots q_l * D(parity) per l, with the chunk's alpha_l in av.  SLOW:
+// weight by cf and rescale; FULL: no l <= lmax guard.
+template <int T, bool SLOW, bool FULL>
+__device__ __forceinline__ void ana_chunk(int l0, int lmax, const double (&av)[kChunk],
+                                          double (&x)[T], double (&q1)[T], double (&q2)[T],
+                                          double (&cf)[T], int (&sc)[T], const double (&pr)[T],
+                                          const double (&pi)[T], const double (&mr)[T],
+                                          const double (&mi)[T], double (&accr)[kChunk],
+                                          double (&acci)[kChunk]) {
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i) {
+        accr[i] = 0.0;
+        acci[i] = 0.0;
+        if (FULL || l0 + i <= lmax) {
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+                // alpha * (x q_{l-1}): keeps the product on the dependency chain
+                const double q = fma(av[i], x[t] * q1[t], -q2[t]);
+                q2[t] = q1[t];
+                q1[t] = q;
+                const double p = SLOW ? cf[t] * q : q;
+                accr[i] = fma(p, (i & 1) ? mr[t] : pr[t], accr[i]);
+                acci[i] = fma(p, (i & 1) ? mi[t] : pi[t], acci[i]);
+            }
+            if (SLOW && (i & 1)) {
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    if (sc[t] < 0 && fabs(q1[t]) > kThresh) {
+                        q1[t] *= kDown;
+                        q2[t] *= kDown;
+                        ++sc[t];
+                        cf[t] = (sc[t] == 0) ? 1.0 : 0.0;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Analysis: grid.x = m * groups + group; the group's workgroup owns slots
+// [group * 256T, (group+1) * 256T), T per thread (contiguous).  With one group
+// the finished a_lm (times c_lm) is written; otherwise the group's partial sum
+// goes to part[(map * groups + group) * nalm + idx] for k_ana_combine.
 template <int T>
 __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslots, int nrings,
-                                                    int64_t nalm, const double2 *__restrict__ delta,
+                                                    int64_t nalm, int groups,
+                                                    const double2 *__restrict__ delta,
                                                     const double *__restrict__ alpha,
                                                     const double *__restrict__ cfac,
                                                     const double *__restrict__ mu,
@@ -197,10 +312,14 @@ __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslo
                                                     const double *__restrict__ ss,
                                                     const int32_t *__restrict__ rn,
                                                     const int32_t *__restrict__ rsouth,
-                                                    double2 *__restrict__ alm) {
-    __shared__ double red_re[kChunk][kBlock];
-    __shared__ double red_im[kChunk][kBlock];
-    const int m = blockIdx.x;
+                                                    double2 *__restrict__ alm,
+                                                    double2 *__restrict__ part) {
+    // two reduction buffers: chunk i is written to buffer i%2, so one barrier
+    // per chunk separates its writes from its reads and from chunk i+2's writes
+    __shared__ double red_re[2][kChunk][kBlock];
+    __shared__ double red_im[2][kChunk][kBlock];
+    const int m = blockIdx.x / groups;
+    const int grp = blockIdx.x - m * groups;
     const int map = blockIdx.y;
     const int tid = threadIdx.x;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
@@ -211,7 +330,7 @@ __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslo
     int sc[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-        const int slot = tid * T + t;
+        const int slot = grp * kBlock * T + tid * T + t;
         const bool act = slot < nslots;
         x[t] = act ? sx[slot] : 0.0;
         const double s = act ? ss[slot] : 1.0;
@@ -232,73 +351,81 @@ __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslo
         cf[t] = (sc[t] == 0) ? 1.0 : 0.0;
     }
 
-    for (int l0 = m; l0 <= lmax; l0 += kChunk) {
+    double av[kChunk];
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i) av[i] = (m + i <= lmax) ? al[m + i] : 0.0;
+    int par = 0;
+    for (int l0 = m; l0 <= lmax; l0 += kChunk, par ^= 1) {
+        // next chunk's alpha, loaded while this chunk computes
+        double avn[kChunk];
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) avn[i] = (l0 + kChunk + i <= lmax) ? al[l0 + kChunk + i] : 0.0;
         double accr[kChunk], acci[kChunk];
-        bool slow = false;
+        bool scaled = false;
 #pragma unroll
-        for (int t = 0; t < T; ++t) slow |= (sc[t] < 0);
-        slow = __any(slow);
+        for (int t = 0; t < T; ++t) scaled |= (sc[t] < 0);
+        const bool slow = __any(scaled);
         const bool full = (l0 + kChunk - 1 <= lmax);
+        if (full && !slow)
+            ana_chunk<T, false, true>(l0, lmax, av, x, q1, q2, cf, sc, pr, pi, mr, mi, accr, acci);
+        else if (full)
+            ana_chunk<T, true, true>(l0, lmax, av, x, q1, q2, cf, sc, pr, pi, mr, mi, accr, acci);
+        else
+            ana_chunk<T, true, false>(l0, lmax, av, x, q1, q2, cf, sc, pr, pi, mr, mi, accr, acci);
 #pragma unroll
         for (int i = 0; i < kChunk; ++i) {
-            accr[i] = 0.0;
-            acci[i] = 0.0;
-            const int l = l0 + i;
-            if (full || l <= lmax) {
-                const double a_l = al[l];
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    const double q = fma(a_l * x[t], q1[t], -q2[t]);
-                    q2[t] = q1[t];
-                    q1[t] = q;
-                    const double p = slow ? cf[t] * q : q;
-                    const double dr = (i & 1) ? mr[t] : pr[t];
-                    const double di = (i & 1) ? mi[t] : pi[t];
-                    accr[i] = fma(p, dr, accr[i]);
-                    acci[i] = fma(p, di, acci[i]);
-                }
-                if (slow && (i & 1)) {
-#pragma unroll
-                    for (int t = 0; t < T; ++t) {
-                        if (sc[t] < 0 && fabs(q1[t]) > kThresh) {
-                            q1[t] *= kDown;
-                            q2[t] *= kDown;
-                            ++sc[t];
-                            cf[t] = (sc[t] == 0) ? 1.0 : 0.0;
-                        }
-                    }
-                }
-            }
-        }
-        // a slot left mid-rescale at an odd chunk end is checked next chunk
-#pragma unroll
-        for (int i = 0; i < kChunk; ++i) {
-            red_re[i][tid] = accr[i];
-            red_im[i][tid] = acci[i];
+            red_re[par][i][tid] = accr[i];
+            red_im[par][i][tid] = acci[i];
+            av[i] = avn[i];
         }
         __syncthreads();
-        // thread (li = tid/16, g = tid%16) sums lanes g, g+16, ..., g+240 of row li,
-        // then the 16 lanes of the group combine with xor shuffles
+        // thread (li = tid/32, g = tid%32) sums lanes g, g+32, ..., g+224 of row li,
+        // then the 32 lanes of the group combine with xor shuffles
+        static_assert(kChunk * 32 == kBlock, "one 32-lane group per l of the chunk");
         {
-            const int li = tid >> 4, g = tid & 15;
+            const int li = tid >> 5, g = tid & 31;
             double sr = 0.0, si = 0.0;
 #pragma unroll
-            for (int j = 0; j < kBlock / 16; ++j) {
-                sr += red_re[li][j * 16 + g];
-                si += red_im[li][j * 16 + g];
+            for (int j = 0; j < kBlock / 32; ++j) {
+                sr += red_re[par][li][j * 32 + g];
+                si += red_im[par][li][j * 32 + g];
             }
 #pragma unroll
-            for (int off = 8; off >= 1; off >>= 1) {
-                sr += __shfl_xor(sr, off, 16);
-                si += __shfl_xor(si, off, 16);
+            for (int off = 16; off >= 1; off >>= 1) {
+                sr += __shfl_xor(sr, off, 32);
+                si += __shfl_xor(si, off, 32);
             }
             const int l = l0 + li;
             if (g == 0 && l <= lmax) {
-                const double c = cfac[base + l];
-                alm[(int64_t)map * nalm + base + l] = make_double2(sr * c, m == 0 ? 0.0 : si * c);
+                if (groups == 1) {
+                    const double c = cfac[base + l];
+                    alm[(int64_t)map * nalm + base + l] = make_double2(sr * c, m == 0 ? 0.0 : si * c);
+                } else {
+                    part[((int64_t)map * groups + grp) * nalm + base + l] = make_double2(sr, si);
+                }
             }
         }
-        __syncthreads();
+    }
+}
+
+// a_lm = c_lm * sum_{g < groups} part[map][g][idx], groups summed in order.
+__global__ __launch_bounds__(kBlock) void k_ana_combine(int64_t nalm, int lmax, int nmaps, int groups,
+                                                        const double2 *__restrict__ part,
+                                                        const double *__restrict__ cfac,
+                                                        double2 *__restrict__ alm) {
+    const int64_t total = nalm * nmaps;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * kBlock) {
+        const int64_t map = i / nalm, k = i - map * nalm;
+        const double2 *src = part + map * groups * nalm + k;
+        double sr = 0.0, si = 0.0;
+        for (int g = 0; g < groups; ++g) {
+            const double2 v = src[(int64_t)g * nalm];
+            sr += v.x;
+            si += v.y;
+        }
+        const double c = cfac[k];
+        alm[i] = make_double2(sr * c, k <= lmax ? 0.0 : si * c);
     }
 }
 
@@ -315,12 +442,15 @@ int launch_prescale(const CoefTables &c, const void *alm, void *aprime, int nmap
     return SHT_OK;
 }
 
+constexpr int kSynSlotsPerLane = 2;
+
 int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const void *aprime, void *delta, int nmaps,
                    hipStream_t st) {
-    const int tiles = (p.nslots + kBlock - 1) / kBlock;
+    constexpr int T = kSynSlotsPerLane;
+    const int tiles = (p.nslots + kBlock * T - 1) / (kBlock * T);
     const int64_t gx = (int64_t)tiles * (c.mmax + 1);
     if (!grid_ok(gx) || nmaps > 65535) return SHT_EUNSUPPORTED;
-    hipLaunchKernelGGL(k_leg_syn, dim3((unsigned)gx, (unsigned)nmaps), dim3(kBlock), 0, st, c.lmax,
+    hipLaunchKernelGGL(k_leg_syn<T>, dim3((unsigned)gx, (unsigned)nmaps), dim3(kBlock), 0, st, c.lmax,
                        c.mmax, p.nslots, tiles, p.nrings, c.nalm, static_cast<const double2 *>(aprime),
                        c.alpha, c.mu, p.slot_x, p.slot_s, p.slot_north, p.slot_south,
                        static_cast<double2 *>(delta));
@@ -329,25 +459,34 @@ int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const void *aprime, v
 }
 
 template <int T>
-static void launch_ana_t(const CoefTables &c, const GeomPlan &p, const void *delta, void *alm, int nmaps,
-                         hipStream_t st) {
-    hipLaunchKernelGGL(k_leg_ana<T>, dim3((unsigned)(c.mmax + 1), (unsigned)nmaps), dim3(kBlock), 0, st,
-                       c.lmax, c.mmax, p.nslots, p.nrings, c.nalm, static_cast<const double2 *>(delta),
-                       c.alpha, c.cfac, c.mu, p.slot_x, p.slot_s, p.slot_north, p.slot_south,
-                       static_cast<double2 *>(alm));
+static void launch_ana_t(const CoefTables &c, const GeomPlan &p, int groups, const void *delta, void *alm,
+                         void *part, int nmaps, hipStream_t st) {
+    hipLaunchKernelGGL(k_leg_ana<T>, dim3((unsigned)((c.mmax + 1) * groups), (unsigned)nmaps), dim3(kBlock),
+                       0, st, c.lmax, c.mmax, p.nslots, p.nrings, c.nalm, groups,
+                       static_cast<const double2 *>(delta), c.alpha, c.cfac, c.mu, p.slot_x, p.slot_s,
+                       p.slot_north, p.slot_south, static_cast<double2 *>(alm), static_cast<double2 *>(part));
 }
 
 int launch_leg_ana(const CoefTables &c, const GeomPlan &p, const void *delta, void *alm, int nmaps,
-                   hipStream_t st) {
+                   void *partials, hipStream_t st) {
     if (nmaps > 65535) return SHT_EUNSUPPORTED;
-    const int per = (p.nslots + kBlock - 1) / kBlock;
-    if (per <= 1) launch_ana_t<1>(c, p, delta, alm, nmaps, st);
-    else if (per <= 2) launch_ana_t<2>(c, p, delta, alm, nmaps, st);
-    else if (per <= 4) launch_ana_t<4>(c, p, delta, alm, nmaps, st);
-    else if (per <= 8) launch_ana_t<8>(c, p, delta, alm, nmaps, st);
-    else if (per <= kAnaMaxSlotsPerThread) launch_ana_t<16>(c, p, delta, alm, nmaps, st);
-    else return SHT_EUNSUPPORTED;
+    const int T = ana_slots_per_thread(p.nslots);
+    const int groups = ana_groups(p.nslots);
+    if (!grid_ok((int64_t)(c.mmax + 1) * groups)) return SHT_EUNSUPPORTED;
+    if (groups > 1 && !partials) return SHT_EWORKSPACE;
+    switch (T) {
+        case 1: launch_ana_t<1>(c, p, groups, delta, alm, partials, nmaps, st); break;
+        case 2: launch_ana_t<2>(c, p, groups, delta, alm, partials, nmaps, st); break;
+        default: launch_ana_t<kAnaSlotsPerThread>(c, p, groups, delta, alm, partials, nmaps, st); break;
+    }
     SHT_HIP(hipGetLastError());
+    if (groups > 1) {
+        const int64_t total = c.nalm * nmaps;
+        const int64_t blocks = std::min<int64_t>((total + kBlock - 1) / kBlock, 1 << 16);
+        hipLaunchKernelGGL(k_ana_combine, dim3((unsigned)blocks), dim3(kBlock), 0, st, c.nalm, c.lmax, nmaps,
+                           groups, static_cast<const double2 *>(partials), c.cfac, static_cast<double2 *>(alm));
+        SHT_HIP(hipGetLastError());
+    }
     return SHT_OK;
 }
 

@@ -1,4 +1,5 @@
 // extern "C" entry points of libsht.so (declared in include/sht.h).
+#include <algorithm>
 #include <cstring>
 
 #include "sht_internal.h"
@@ -25,6 +26,19 @@ size_t delta_bytes(int nrings, int mmax, int nmaps) {
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
+// Workspace layout: [Delta (synthesis/analysis)][aux], aux holding either the
+// c-scaled a_lm of synthesis or the per-group partial a_lm of analysis.
+size_t partial_bytes(int lmax, int mmax, int nslots, int nmaps) {
+    const int G = ana_groups(nslots);
+    return G > 1 ? (size_t)G * alm_bytes(lmax, mmax, nmaps) : 0;
+}
+size_t aux_bytes(int lmax, int mmax, int nslots, int nmaps) {
+    return std::max(round256(alm_bytes(lmax, mmax, nmaps)), round256(partial_bytes(lmax, mmax, nslots, nmaps)));
+}
+size_t ws_need(int lmax, int mmax, const HostGeom &h, int nmaps) {
+    return round256(delta_bytes(h.nrings, mmax, nmaps)) + aux_bytes(lmax, mmax, count_slots(h), nmaps);
+}
+
 bool overlap(const void *a, size_t na, const void *b, size_t nb) {
     const uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
     return x < y + nb && y < x + na;
@@ -48,7 +62,7 @@ extern "C" {
 size_t sht_workspace_bytes(int lmax, int mmax, const sht_geom *g, int nmaps, uint32_t flags) {
     HostGeom h;
     if (check_common(lmax, mmax, g, nmaps, flags, false, &h)) return 0;
-    return round256(alm_bytes(lmax, mmax, nmaps)) + round256(delta_bytes(h.nrings, mmax, nmaps));
+    return ws_need(lmax, mmax, h, nmaps);
 }
 
 int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *delta, int nmaps,
@@ -58,7 +72,8 @@ int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *
     if (rc) return rc;
     if (!alm || !delta || !aligned(alm, 16) || !aligned(delta, 16)) return SHT_EINVAL;
     const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
-    if (!workspace || !aligned(workspace, 16) || ws_bytes < round256(ab)) return SHT_EWORKSPACE;
+    if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps))
+        return SHT_EWORKSPACE;
     if (overlap(alm, ab, delta, db) || overlap(workspace, ws_bytes, alm, ab) ||
         overlap(workspace, ws_bytes, delta, db))
         return SHT_EINVAL;
@@ -96,17 +111,21 @@ int sht_map2delta(int mmax, const sht_geom *g, const double *map, void *delta, i
 }
 
 int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void *alm, int nmaps,
-                  uint32_t flags, void *stream) {
+                  void *workspace, size_t ws_bytes, uint32_t flags, void *stream) {
     HostGeom h;
     int rc = check_common(lmax, mmax, g, nmaps, flags, false, &h);
     if (rc) return rc;
     if (!delta || !alm || !aligned(delta, 16) || !aligned(alm, 16)) return SHT_EINVAL;
-    if (overlap(delta, delta_bytes(h.nrings, mmax, nmaps), alm, alm_bytes(lmax, mmax, nmaps)))
+    const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
+    if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps))
+        return SHT_EWORKSPACE;
+    if (overlap(delta, db, alm, ab) || overlap(workspace, ws_bytes, alm, ab) ||
+        overlap(workspace, ws_bytes, delta, db))
         return SHT_EINVAL;
     const CoefTables *c;
     const GeomPlan *p;
     if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p))) return rc;
-    return launch_leg_ana(*c, *p, delta, alm, nmaps, as_stream(stream));
+    return launch_leg_ana(*c, *p, delta, alm, nmaps, workspace, as_stream(stream));
 }
 
 int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *map, int nmaps,
@@ -117,7 +136,7 @@ int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *
     if (!alm || !map || !aligned(alm, 16) || !aligned(map, 8)) return SHT_EINVAL;
     const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
     const size_t mb = (size_t)h.npix * 8u * nmaps;
-    if (!workspace || !aligned(workspace, 16) || ws_bytes < round256(ab) + round256(db))
+    if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps))
         return SHT_EWORKSPACE;
     if (overlap(alm, ab, map, mb) || overlap(workspace, ws_bytes, alm, ab) ||
         overlap(workspace, ws_bytes, map, mb))
@@ -126,7 +145,7 @@ int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *
     const GeomPlan *p;
     if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p))) return rc;
     char *ws = static_cast<char *>(workspace);
-    void *aprime = ws, *delta = ws + round256(ab);
+    void *delta = ws, *aprime = ws + round256(db);
     hipStream_t st = as_stream(stream);
     if ((rc = launch_prescale(*c, alm, aprime, nmaps, st))) return rc;
     if ((rc = launch_leg_syn(*c, *p, aprime, delta, nmaps, st))) return rc;
@@ -141,7 +160,8 @@ int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *
     if (!alm || !map || !aligned(alm, 16) || !aligned(map, 8)) return SHT_EINVAL;
     const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
     const size_t mb = (size_t)h.npix * 8u * nmaps;
-    if (!workspace || !aligned(workspace, 16) || ws_bytes < round256(db)) return SHT_EWORKSPACE;
+    if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps))
+        return SHT_EWORKSPACE;
     if (overlap(alm, ab, map, mb) || overlap(workspace, ws_bytes, alm, ab) ||
         overlap(workspace, ws_bytes, map, mb))
         return SHT_EINVAL;
@@ -149,8 +169,10 @@ int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *
     const GeomPlan *p;
     if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p))) return rc;
     hipStream_t st = as_stream(stream);
-    if ((rc = launch_fft_ana(*p, mmax, map, workspace, nmaps, st))) return rc;
-    return launch_leg_ana(*c, *p, workspace, alm, nmaps, st);
+    char *ws = static_cast<char *>(workspace);
+    void *delta = ws, *partials = ws + round256(db);
+    if ((rc = launch_fft_ana(*p, mmax, map, delta, nmaps, st))) return rc;
+    return launch_leg_ana(*c, *p, delta, alm, nmaps, partials, st);
 }
 
 const char *sht_strerror(int code) {

@@ -15,7 +15,20 @@ namespace sht {
 constexpr int kBlock = 256;          // threads per workgroup of every kernel
 constexpr int kMaxFftLen = 8192;     // complex points one workgroup holds in LDS
 constexpr int kMaxRadices = 16;
-constexpr int kAnaMaxSlotsPerThread = 16;
+constexpr int kFftClasses = 4;
+constexpr int kFftClassLen[kFftClasses] = {1024, 2048, 4096, 8192};
+// Analysis: a workgroup of kBlock threads holds kAnaSlotsPerThread ring
+// slots per thread; an m whose slots need several workgroups writes one
+// partial a_lm per group to the workspace, summed afterwards in group order.
+constexpr int kAnaSlotsPerThread = 4;
+
+inline int ana_slots_per_thread(int nslots) {
+    return nslots <= kBlock ? 1 : (nslots <= 2 * kBlock ? 2 : kAnaSlotsPerThread);
+}
+inline int ana_groups(int nslots) {
+    const int per = kBlock * ana_slots_per_thread(nslots);
+    return (nslots + per - 1) / per;
+}
 
 // Rescaling of the Legendre recurrence (exponent tracking).  A value is kept
 // as q * 2^(kScaleBits * sc) with sc <= 0.  While sc < 0 a value is below
@@ -66,6 +79,9 @@ struct GeomPlan {
     int64_t *ofs = nullptr;
     int32_t *ring_desc = nullptr;    // index into descs
     FftDesc *descs = nullptr;
+    // rings grouped by FFT length class (L <= kFftClassLen[c]), one launch per class
+    int class_count[4] = {0, 0, 0, 0};
+    int32_t *class_rings[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<void *> owned;       // device allocations to free
 };
 
@@ -82,6 +98,8 @@ struct HostGeom {
 };
 
 int validate_geom(const sht_geom *g, bool need_weight, HostGeom *out);
+// Number of recurrence slots (mirror pairs plus unpaired rings) of a geometry.
+int count_slots(const HostGeom &h);
 int validate_sizes(int lmax, int mmax, int nmaps);
 
 // Plan lookup (builds on first use).  Thread safe.
@@ -103,7 +121,7 @@ int launch_prescale(const CoefTables &c, const void *alm, void *aprime, int nmap
 int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const void *aprime, void *delta,
                    int nmaps, hipStream_t st);
 int launch_leg_ana(const CoefTables &c, const GeomPlan &p, const void *delta, void *alm, int nmaps,
-                   hipStream_t st);
+                   void *partials, hipStream_t st);
 int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, double *map, int nmaps,
                    hipStream_t st);
 int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, int nmaps,

@@ -174,31 +174,36 @@ static bool factor_small(int n, std::vector<int> &rad) {
     rad.clear();
     while (n % 4 == 0) { rad.push_back(4); n /= 4; }
     while (n % 2 == 0) { rad.push_back(2); n /= 2; }
-    for (int p : {3, 5, 7, 11, 13}) {
+    for (int p : {3, 5}) {
         while (n % p == 0) { rad.push_back(p); n /= p; }
     }
     return n == 1 && (int)rad.size() <= kMaxRadices;
 }
 
-// In-place radix-2 FFT (forward sign) in long double, length a power of two.
-static void host_fft_pow2(std::vector<cld> &a) {
+static bool smooth5(int n) {
+    for (int p : {2, 3, 5})
+        while (n % p == 0) n /= p;
+    return n == 1;
+}
+
+// Forward DFT (sign -1) of a 5-smooth length in long double, by recursive
+// decimation in time over the factors 2, 3, 5.
+static void host_fft_smooth(std::vector<cld> &a) {
     const size_t n = a.size();
-    for (size_t i = 1, j = 0; i < n; ++i) {
-        size_t bit = n >> 1;
-        for (; j & bit; bit >>= 1) j ^= bit;
-        j ^= bit;
-        if (i < j) std::swap(a[i], a[j]);
-    }
-    for (size_t len = 2; len <= n; len <<= 1) {
-        for (size_t i = 0; i < n; i += len) {
-            for (size_t k = 0; k < len / 2; ++k) {
-                const long double ang = -2.0L * kPiL * (long double)k / (long double)len;
-                const cld w(cosl(ang), sinl(ang));
-                const cld u = a[i + k], v = a[i + k + len / 2] * w;
-                a[i + k] = u + v;
-                a[i + k + len / 2] = u - v;
-            }
+    if (n == 1) return;
+    size_t p = (n % 2 == 0) ? 2 : (n % 3 == 0) ? 3 : 5;
+    const size_t m = n / p;
+    std::vector<std::vector<cld>> sub(p, std::vector<cld>(m));
+    for (size_t j = 0; j < m; ++j)
+        for (size_t r = 0; r < p; ++r) sub[r][j] = a[j * p + r];
+    for (auto &v : sub) host_fft_smooth(v);
+    for (size_t k = 0; k < n; ++k) {
+        cld acc(0, 0);
+        for (size_t r = 0; r < p; ++r) {
+            const long double ang = -2.0L * kPiL * (long double)((r * k) % n) / (long double)n;
+            acc += sub[r][k % m] * cld(cosl(ang), sinl(ang));
         }
+        a[k] = acc;
     }
 }
 
@@ -243,8 +248,8 @@ static int fft_desc(FftCache &fc, int n, FftDesc *out) {
         d.L = n;
         d.bluestein = 0;
     } else {
-        int L = 1;
-        while (L < 2 * n - 1) L <<= 1;
+        int L = 2 * n - 1;
+        while (!smooth5(L)) ++L;
         d.L = L;
         d.bluestein = 1;
         factor_small(L, rad);
@@ -259,7 +264,7 @@ static int fft_desc(FftCache &fc, int n, FftDesc *out) {
             ext[t] = v;
             if (t > 0) ext[L - t] = v;
         }
-        host_fft_pow2(ext);
+        host_fft_smooth(ext);
         std::vector<double2> k(L);
         for (int t = 0; t < L; ++t)
             k[t] = make_double2((double)(ext[t].real() / L), (double)(ext[t].imag() / L));
@@ -342,6 +347,13 @@ static void build_slots(const HostGeom &h, std::vector<double> &sx, std::vector<
     }
 }
 
+int count_slots(const HostGeom &h) {
+    std::vector<double> sx, ss;
+    std::vector<int32_t> sn, sso;
+    build_slots(h, sx, ss, sn, sso);
+    return (int)sx.size();
+}
+
 int get_geom(const HostGeom &hg, int /*mmax_for_fft*/, const GeomPlan **out) {
     int dev = 0;
     int rc = current_device(&dev);
@@ -398,6 +410,21 @@ int get_geom(const HostGeom &hg, int /*mmax_for_fft*/, const GeomPlan **out) {
     }
     p.max_L = maxL;
     p.all_nphi_max = maxn;
+    std::vector<int32_t> cls[kFftClasses];
+    for (int r = 0; r < hg.nrings; ++r) {
+        const int L = descs[ring_desc[r]].L;
+        int c = 0;
+        while (c < kFftClasses - 1 && L > kFftClassLen[c]) ++c;
+        cls[c].push_back(r);
+    }
+    for (int c = 0; c < kFftClasses; ++c) {
+        p.class_count[c] = (int)cls[c].size();
+        if (cls[c].empty()) continue;
+        if ((rc = upload(cls[c], &p.class_rings[c], p.owned))) {
+            free_plan(p);
+            return rc;
+        }
+    }
     if ((rc = upload(sx, &p.slot_x, p.owned)) || (rc = upload(ss, &p.slot_s, p.owned)) ||
         (rc = upload(sn, &p.slot_north, p.owned)) || (rc = upload(sso, &p.slot_south, p.owned)) ||
         (rc = upload(hg.phi0, &p.phi0, p.owned)) || (rc = upload(hg.ofs, &p.ofs, p.owned)) ||

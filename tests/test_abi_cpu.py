@@ -57,8 +57,13 @@ def test_workspace_bytes_values_and_monotonic():
     lmax = 16
     na = si.nalm(lmax, lmax)
     r256 = lambda b: (b + 255) // 256 * 256
+    # [Delta][aux]; 16 slots need one analysis group, so aux holds the scaled a_lm
     assert _ws(lmax, lmax, g) == r256(na * 16) + r256(g.nrings * (lmax + 1) * 16)
     assert _ws(lmax, lmax, g, 3) == r256(3 * na * 16) + r256(3 * g.nrings * (lmax + 1) * 16)
+    # HEALPix nside=1024: 2048 slots -> two analysis groups of 1024 slots
+    big = si.healpix(1024)
+    na2 = si.nalm(64, 64)
+    assert _ws(64, 64, big) == r256(big.nrings * 65 * 16) + r256(2 * na2 * 16)
     prev = 0
     for l in range(0, 40, 3):
         cur = _ws(l, l, g)
@@ -136,6 +141,7 @@ def test_invalid_arguments_rejected_on_host(L):
     assert L.sht_map2alm(4, 4, nw.ref(), m, a, 1, w, big, 0, None) == sht.SHT_EINVAL
     assert L.sht_map2delta(4, nw.ref(), m, a, 1, 0, None) == sht.SHT_EINVAL
     # stage entry points
-    assert L.sht_delta2alm(4, 5, g.ref(), a, m, 1, 0, None) == sht.SHT_EINVAL
+    assert L.sht_delta2alm(4, 5, g.ref(), a, m, 1, w, big, 0, None) == sht.SHT_EINVAL
+    assert L.sht_delta2alm(4, 4, g.ref(), a, m, 1, None, big, 0, None) == sht.SHT_EWORKSPACE
     assert L.sht_delta2map(4, g.ref(), None, m, 1, 0, None) == sht.SHT_EINVAL
     assert L.sht_alm2delta(4, 4, g.ref(), a, m, 1, w, 8, 0, None) == sht.SHT_EWORKSPACE
