@@ -23,9 +23,10 @@
 //   synthesis  grid.x = (m, 512-slot tile) with m ascending (longest first),
 //              grid.y = map; two slots per lane, no reduction needed.
 //   analysis   grid.x = (m ascending, slot group), grid.y = map; a workgroup
-//              owns up to 1024 slots of its m (T slots per lane), sums over its
-//              lanes in LDS in a fixed order, and groups are summed in order
-//              by a second small kernel: no atomics, bitwise deterministic.
+//              owns up to 1024 slots of its m (T slots per lane); each wave sums
+//              its lanes through its own LDS rows, the four waves are added in
+//              wave order every 64 l, and groups are summed in order by a
+//              second small kernel: no atomics, bitwise deterministic.
 //
 // Underflow near the poles (Sec. 2.1, rescaling; the paper leaves the
 // algorithm to its references): a value is held as q * 2^(600 sc), sc <= 0.
@@ -255,18 +256,20 @@ __global__ __launch_bounds__(kBlock) void k_leg_syn(int lmax, int mmax, int nslo
     }
 }
 
-constexpr int kChunk = 8;  // l values per reduction round in analysis
+constexpr int kChunk = 8;   // l values per in-wave reduction in analysis
+constexpr int kFlush = 8;   // chunks between cross-wave flushes (one barrier each)
+constexpr int kTPad = 65;   // padded row (doubles) of the wave-private transpose buffer
 
 // One chunk of kChunk recurrence steps for the T slots of a lane, accumulating
 // sum_slots q_l * D(parity) per l, with the chunk's alpha_l in av.  SLOW:
-// weight by cf and rescale; FULL: no l <= lmax guard.
+// terms of slots still below range (sc < 0) are dropped and carriers rescaled;
+// FULL: no l <= lmax guard.
 template <int T, bool SLOW, bool FULL>
 __device__ __forceinline__ void ana_chunk(int l0, int lmax, const double (&av)[kChunk],
-                                          double (&x)[T], double (&q1)[T], double (&q2)[T],
-                                          double (&cf)[T], int (&sc)[T], const double (&pr)[T],
-                                          const double (&pi)[T], const double (&mr)[T],
-                                          const double (&mi)[T], double (&accr)[kChunk],
-                                          double (&acci)[kChunk]) {
+                                          const double (&x)[T], double (&q1)[T], double (&q2)[T],
+                                          int (&sc)[T], const double (&pr)[T], const double (&pi)[T],
+                                          const double (&mr)[T], const double (&mi)[T],
+                                          double (&accr)[kChunk], double (&acci)[kChunk]) {
 #pragma unroll
     for (int i = 0; i < kChunk; ++i) {
         accr[i] = 0.0;
@@ -278,7 +281,7 @@ __device__ __forceinline__ void ana_chunk(int l0, int lmax, const double (&av)[k
                 const double q = fma(av[i], x[t] * q1[t], -q2[t]);
                 q2[t] = q1[t];
                 q1[t] = q;
-                const double p = SLOW ? cf[t] * q : q;
+                const double p = SLOW ? (sc[t] == 0 ? q : 0.0) : q;
                 accr[i] = fma(p, (i & 1) ? mr[t] : pr[t], accr[i]);
                 acci[i] = fma(p, (i & 1) ? mi[t] : pi[t], acci[i]);
             }
@@ -289,7 +292,6 @@ __device__ __forceinline__ void ana_chunk(int l0, int lmax, const double (&av)[k
                         q1[t] *= kDown;
                         q2[t] *= kDown;
                         ++sc[t];
-                        cf[t] = (sc[t] == 0) ? 1.0 : 0.0;
                     }
                 }
             }
@@ -297,10 +299,26 @@ __device__ __forceinline__ void ana_chunk(int l0, int lmax, const double (&av)[k
     }
 }
 
-// Analysis: grid.x = m * groups + group; the group's workgroup owns slots
-// [group * 256T, (group+1) * 256T), T per thread (contiguous).  With one group
-// the finished a_lm (times c_lm) is written; otherwise the group's partial sum
-// goes to part[(map * groups + group) * nalm + idx] for k_ana_combine.
+// quad all-reduce (lanes l, l^1, l^2, l^3) of a double through DPP moves
+__device__ __forceinline__ double quad_sum(double v) {
+    int lo = __double2loint(v), hi = __double2hiint(v);
+    double w = __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xf, 0xf, false),
+                                __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xf, 0xf, false));  // quad_perm [1,0,3,2]
+    v += w;
+    lo = __double2loint(v);
+    hi = __double2hiint(v);
+    w = __hiloint2double(__builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xf, 0xf, false),
+                         __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xf, 0xf, false));  // quad_perm [2,3,0,1]
+    return v + w;
+}
+
+// Analysis: workgroups of 4 waves; wave w of group g of m owns slots
+// (g*4 + w) * 64T + lane*T + t.  Per chunk of kChunk l values each lane sums
+// its T slots; the wave sums its 64 lanes through its own LDS rows (no
+// barrier); every kFlush chunks the 4 wave sums are added in wave order after
+// one barrier.  With one group the finished a_lm (times c_lm) is written;
+// otherwise the group's partial goes to part[(map * groups + group) * nalm + idx]
+// for k_ana_combine.
 template <int T>
 __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslots, int nrings,
                                                     int64_t nalm, int groups,
@@ -314,23 +332,24 @@ __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslo
                                                     const int32_t *__restrict__ rsouth,
                                                     double2 *__restrict__ alm,
                                                     double2 *__restrict__ part) {
-    // two reduction buffers: chunk i is written to buffer i%2, so one barrier
-    // per chunk separates its writes from its reads and from chunk i+2's writes
-    __shared__ double red_re[2][kChunk][kBlock];
-    __shared__ double red_im[2][kChunk][kBlock];
+    constexpr int kVals = 2 * kChunk;                 // (l, re/im) values per chunk
+    constexpr int kWaves = kBlock / 64;
+    __shared__ double tbuf[kWaves][kVals][kTPad];     // wave-private transpose rows
+    __shared__ double ring[2][kFlush][kWaves][kVals]; // per-wave chunk sums awaiting the flush
+    static_assert(kFlush * kVals <= kBlock, "one thread per flushed value");
     const int m = blockIdx.x / groups;
     const int grp = blockIdx.x - m * groups;
     const int map = blockIdx.y;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const double *__restrict__ al = alpha + base;
     const double2 *__restrict__ d = delta + (int64_t)map * nrings * (mmax + 1);
 
-    double x[T], q1[T], q2[T], cf[T], pr[T], pi[T], mr[T], mi[T];
+    double x[T], q1[T], q2[T], pr[T], pi[T], mr[T], mi[T];
     int sc[T];
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-        const int slot = grp * kBlock * T + tid * T + t;
+        const int slot = (grp * kWaves + wave) * 64 * T + lane * T + t;
         const bool act = slot < nslots;
         x[t] = act ? sx[slot] : 0.0;
         const double s = act ? ss[slot] : 1.0;
@@ -348,16 +367,40 @@ __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslo
         const double seed = seed_carrier(m, s, mu[m], sc[t]);
         q2[t] = -seed;
         q1[t] = 0.0;
-        cf[t] = (sc[t] == 0) ? 1.0 : 0.0;
     }
+
+    // flush bookkeeping: thread f < kFlush*kVals owns value (chunk f/kVals, j = f%kVals)
+    const int fk = tid / kVals, fj = tid - fk * kVals;
+    auto flush_out = [&](int lbase, int par, int nchunks, double cval) {
+        if (tid < nchunks * kVals) {
+            double v = 0.0;
+#pragma unroll
+            for (int w = 0; w < kWaves; ++w) v += ring[par][fk][w][fj];
+            const int l = lbase + fk * kChunk + (fj >> 1);
+            if (l <= lmax) {
+                double *dst;
+                if (groups == 1) {
+                    dst = reinterpret_cast<double *>(alm + (int64_t)map * nalm + base + l) + (fj & 1);
+                    v = (m == 0 && (fj & 1)) ? 0.0 : v * cval;
+                } else {
+                    dst = reinterpret_cast<double *>(part + ((int64_t)map * groups + grp) * nalm + base + l) + (fj & 1);
+                }
+                *dst = v;
+            }
+        }
+    };
+    auto cfac_for = [&](int lbase) {
+        const int l = lbase + fk * kChunk + (fj >> 1);
+        return (groups == 1 && tid < kFlush * kVals && l <= lmax) ? cfac[base + l] : 0.0;
+    };
 
     double av[kChunk];
 #pragma unroll
     for (int i = 0; i < kChunk; ++i) av[i] = (m + i <= lmax) ? al[m + i] : 0.0;
-    int par = 0;
-    for (int l0 = m; l0 <= lmax; l0 += kChunk, par ^= 1) {
-        // next chunk's alpha, loaded while this chunk computes
-        double avn[kChunk];
+    int par = 0, kc = 0, lbase = m;
+    double cval = cfac_for(lbase);
+    for (int l0 = m; l0 <= lmax; l0 += kChunk) {
+        double avn[kChunk];  // next chunk's alpha, loaded while this one computes
 #pragma unroll
         for (int i = 0; i < kChunk; ++i) avn[i] = (l0 + kChunk + i <= lmax) ? al[l0 + kChunk + i] : 0.0;
         double accr[kChunk], acci[kChunk];
@@ -367,43 +410,38 @@ __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslo
         const bool slow = __any(scaled);
         const bool full = (l0 + kChunk - 1 <= lmax);
         if (full && !slow)
-            ana_chunk<T, false, true>(l0, lmax, av, x, q1, q2, cf, sc, pr, pi, mr, mi, accr, acci);
+            ana_chunk<T, false, true>(l0, lmax, av, x, q1, q2, sc, pr, pi, mr, mi, accr, acci);
         else if (full)
-            ana_chunk<T, true, true>(l0, lmax, av, x, q1, q2, cf, sc, pr, pi, mr, mi, accr, acci);
+            ana_chunk<T, true, true>(l0, lmax, av, x, q1, q2, sc, pr, pi, mr, mi, accr, acci);
         else
-            ana_chunk<T, true, false>(l0, lmax, av, x, q1, q2, cf, sc, pr, pi, mr, mi, accr, acci);
+            ana_chunk<T, true, false>(l0, lmax, av, x, q1, q2, sc, pr, pi, mr, mi, accr, acci);
+        // wave sum: each lane writes its 16 values as one column of the wave's
+        // rows; lane (j = lane/4, q = lane%4) adds lanes 16q..16q+15 of row j,
+        // and the quad of lanes 4j..4j+3 combines by DPP (lane 4j holds the sum)
 #pragma unroll
         for (int i = 0; i < kChunk; ++i) {
-            red_re[par][i][tid] = accr[i];
-            red_im[par][i][tid] = acci[i];
+            tbuf[wave][2 * i][lane] = accr[i];
+            tbuf[wave][2 * i + 1][lane] = acci[i];
             av[i] = avn[i];
         }
-        __syncthreads();
-        // thread (li = tid/32, g = tid%32) sums lanes g, g+32, ..., g+224 of row li,
-        // then the 32 lanes of the group combine with xor shuffles
-        static_assert(kChunk * 32 == kBlock, "one 32-lane group per l of the chunk");
+        __builtin_amdgcn_wave_barrier();
         {
-            const int li = tid >> 5, g = tid & 31;
-            double sr = 0.0, si = 0.0;
+            const int j = lane >> 2, q = lane & 3;
+            double v = 0.0;
 #pragma unroll
-            for (int j = 0; j < kBlock / 32; ++j) {
-                sr += red_re[par][li][j * 32 + g];
-                si += red_im[par][li][j * 32 + g];
-            }
-#pragma unroll
-            for (int off = 16; off >= 1; off >>= 1) {
-                sr += __shfl_xor(sr, off, 32);
-                si += __shfl_xor(si, off, 32);
-            }
-            const int l = l0 + li;
-            if (g == 0 && l <= lmax) {
-                if (groups == 1) {
-                    const double c = cfac[base + l];
-                    alm[(int64_t)map * nalm + base + l] = make_double2(sr * c, m == 0 ? 0.0 : si * c);
-                } else {
-                    part[((int64_t)map * groups + grp) * nalm + base + l] = make_double2(sr, si);
-                }
-            }
+            for (int k = 0; k < 16; ++k) v += tbuf[wave][j][q * 16 + k];
+            v = quad_sum(v);
+            if (q == 0) ring[par][kc][wave][j] = v;
+        }
+        __builtin_amdgcn_wave_barrier();
+        ++kc;
+        if (kc == kFlush || l0 + kChunk > lmax) {
+            __syncthreads();
+            flush_out(lbase, par, kc, cval);
+            lbase += kFlush * kChunk;
+            cval = cfac_for(lbase);
+            par ^= 1;
+            kc = 0;
         }
     }
 }

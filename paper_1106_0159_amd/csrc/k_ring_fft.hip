@@ -144,12 +144,16 @@ __device__ void fft_stage(double2 *buf, int L, int Ns, const double2 *__restrict
     constexpr int kMaxB = (MAXL / R + NT - 1) / NT;
     const int nbf = L / R;
     const int tstep = L / (Ns * R);
+    // j / Ns from a float reciprocal: (j + 0.5) / Ns stays at least 0.5/Ns away
+    // from an integer, far beyond the float rounding for j, Ns <= 8192
+    const float inv_ns = 1.0f / (float)Ns;
     double2 v[kMaxB][R];
 #pragma unroll
     for (int b = 0; b < kMaxB; ++b) {
         const int j = threadIdx.x + b * NT;
         if (j < nbf) {
-            const int k = j % Ns;
+            const int jq = (int)(((float)j + 0.5f) * inv_ns);
+            const int k = j - jq * Ns;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const double2 xv = buf[j + r * nbf];
@@ -163,8 +167,9 @@ __device__ void fft_stage(double2 *buf, int L, int Ns, const double2 *__restrict
     for (int b = 0; b < kMaxB; ++b) {
         const int j = threadIdx.x + b * NT;
         if (j < nbf) {
-            const int k = j % Ns;
-            const int o = (j / Ns) * Ns * R + k;
+            const int jq = (int)(((float)j + 0.5f) * inv_ns);
+            const int k = j - jq * Ns;
+            const int o = jq * Ns * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) buf[o + r * Ns] = v[b][r];
         }
@@ -218,68 +223,165 @@ __device__ __forceinline__ double2 input_point(double2 v, const FftDesc *__restr
     return d->bluestein ? cmul(v, conj2(d->chirp[t])) : v;
 }
 
+// ---------------------------------------------------------------- ring jobs
+// A job is one ring or two rings of the same length n, transformed together
+// as the real and imaginary parts of one complex sequence.
+//
+// Synthesis of a job (a, b): per ring, the folded and phased spectrum c is
+// made Hermitian, h_k = (c_k + conj c_{-k}) / 2, so that its inverse DFT is the
+// real ring; g = h_a + i h_b, z = IDFT(g) = conj(FFT(conj g)), and
+// s_a = Re z, s_b = Im z.  Analysis: z = s_a + i s_b, Z = FFT(z),
+// S_a,k = (Z_k + conj Z_{-k}) / 2, S_b,k = (Z_k - conj Z_{-k}) / (2i).
+
+// c_k of one ring: sum over m = k mod n (m <= mmax) of w_m Delta_m e^{i m phi0}
+__device__ __forceinline__ double2 fold_bin(const double2 *__restrict__ D, int k, int n, int mmax,
+                                            double ph0) {
+    double cr = 0.0, ci = 0.0;
+    for (int m = k; m <= mmax; m += n) {
+        const double2 dv = D[m];
+        if (m == 0) {
+            cr += dv.x;
+        } else {
+            const double2 e = phase_exp(m, ph0);
+            cr += 2.0 * fma(dv.x, e.x, -dv.y * e.y);
+            ci += 2.0 * fma(dv.x, e.y, dv.y * e.x);
+        }
+    }
+    return make_double2(cr, ci);
+}
+
+// phased terms of one ring for m = tid, tid+NT, ...: w_m Delta_m e^{i m phi0}
+template <int NT>
+__device__ __forceinline__ void phased_terms(const double2 *__restrict__ D, int mmax, double ph0,
+                                             double2 *__restrict__ out) {
+    for (int m = threadIdx.x; m <= mmax; m += NT) {
+        const double2 dv = D[m];
+        if (m == 0) {
+            out[0] = make_double2(dv.x, 0.0);
+        } else {
+            const double2 e = phase_exp(m, ph0);
+            out[m] = make_double2(2.0 * fma(dv.x, e.x, -dv.y * e.y), 2.0 * fma(dv.x, e.y, dv.y * e.x));
+        }
+    }
+}
+
+// sum_{m = k mod n} t_m, in increasing m
+__device__ __forceinline__ double2 fold_terms(const double2 *__restrict__ t, int k, int n, int mmax) {
+    double cr = 0.0, ci = 0.0;
+    for (int m = k; m <= mmax; m += n) {
+        cr += t[m].x;
+        ci += t[m].y;
+    }
+    return make_double2(cr, ci);
+}
+
+// Synthesis.  LDS: buf[L], plus (fold_rows != 0) two rows of mmax+1 phased
+// terms used when the ring folds many m per bin, n < (mmax+1)/2.
 template <int MAXL, int NT>
-__global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t npix,
-                                                    const int32_t *__restrict__ rings,
-                                                    const int32_t *__restrict__ ring_desc,
-                                                    const FftDesc *__restrict__ descs,
-                                                    const double *__restrict__ phi0,
-                                                    const int64_t *__restrict__ ofs,
-                                                    const double2 *__restrict__ delta,
-                                                    double *__restrict__ map) {
+__global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t npix, int fold_rows,
+                                                const int2 *__restrict__ jobs,
+                                                const int32_t *__restrict__ ring_desc,
+                                                const FftDesc *__restrict__ descs,
+                                                const double *__restrict__ phi0,
+                                                const int64_t *__restrict__ ofs,
+                                                const double2 *__restrict__ delta,
+                                                double *__restrict__ map) {
     extern __shared__ double2 buf[];
-    const int r = rings[blockIdx.x];
+    const int2 job = jobs[blockIdx.x];
+    const int ra = job.x, rb = job.y;
     const int mp = blockIdx.y;
-    const FftDesc *d = descs + ring_desc[r];
-    const int N = d->n;
-    const double ph0 = phi0[r];
-    const double2 *__restrict__ D = delta + ((int64_t)mp * nrings + r) * (mmax + 1);
-    for (int k = threadIdx.x; k < N; k += NT) {
-        double cr = 0.0, ci = 0.0;
-        for (int m = k; m <= mmax; m += N) {
-            const double2 dv = D[m];
-            if (m == 0) {
-                cr += dv.x;
-            } else {
-                const double2 e = phase_exp(m, ph0);
-                cr += 2.0 * fma(dv.x, e.x, -dv.y * e.y);
-                ci += 2.0 * fma(dv.x, e.y, dv.y * e.x);
+    const FftDesc *d = descs + ring_desc[ra];
+    const int N = d->n, L = d->L;
+    const double2 *__restrict__ Da = delta + ((int64_t)mp * nrings + ra) * (mmax + 1);
+    const double2 *__restrict__ Db = delta + ((int64_t)mp * nrings + (rb >= 0 ? rb : ra)) * (mmax + 1);
+    const double pa = phi0[ra], pb = rb >= 0 ? phi0[rb] : 0.0;
+    const bool lds_fold = fold_rows && (2 * N < mmax + 1);
+    if (lds_fold) {
+        // all threads evaluate phases, then each bin sums its terms in m order
+        double2 *ta = buf + L, *tb = buf + L + (mmax + 1);
+        phased_terms<NT>(Da, mmax, pa, ta);
+        if (rb >= 0) phased_terms<NT>(Db, mmax, pb, tb);
+        __syncthreads();
+    }
+    // thread handles the bin pair (k, n-k), k = 0..n/2
+    for (int k = threadIdx.x; 2 * k <= N; k += NT) {
+        const int kn = (N - k) % N;
+        double2 a0, a1, b0 = make_double2(0.0, 0.0), b1 = make_double2(0.0, 0.0);
+        if (lds_fold) {
+            const double2 *ta = buf + L, *tb = buf + L + (mmax + 1);
+            a0 = fold_terms(ta, k, N, mmax);
+            a1 = fold_terms(ta, kn, N, mmax);
+            if (rb >= 0) {
+                b0 = fold_terms(tb, k, N, mmax);
+                b1 = fold_terms(tb, kn, N, mmax);
+            }
+        } else {
+            a0 = fold_bin(Da, k, N, mmax, pa);
+            a1 = fold_bin(Da, kn, N, mmax, pa);
+            if (rb >= 0) {
+                b0 = fold_bin(Db, k, N, mmax, pb);
+                b1 = fold_bin(Db, kn, N, mmax, pb);
             }
         }
-        buf[k] = input_point(make_double2(cr, -ci), d, k);
+        // h_k = (c_k + conj c_{n-k}) / 2, h_{n-k} = conj h_k
+        const double2 ha = make_double2(0.5 * (a0.x + a1.x), 0.5 * (a0.y - a1.y));
+        const double2 hb = make_double2(0.5 * (b0.x + b1.x), 0.5 * (b0.y - b1.y));
+        // g = h_a + i h_b; the transform input is conj(g)
+        const double2 gk = make_double2(ha.x - hb.y, ha.y + hb.x);
+        const double2 gn = make_double2(ha.x + hb.y, -ha.y + hb.x);  // h_a* + i h_b* at n-k
+        buf[k] = input_point(conj2(gk), d, k);
+        if (kn != k) buf[kn] = input_point(conj2(gn), d, kn);
     }
     __syncthreads();
     transform<MAXL, NT>(buf, d);
-    double *out = map + (int64_t)mp * npix + ofs[r];
-    for (int j = threadIdx.x; j < N; j += NT) out[j] = result_at(buf, d, j).x;
+    double *outa = map + (int64_t)mp * npix + ofs[ra];
+    double *outb = map + (int64_t)mp * npix + (rb >= 0 ? ofs[rb] : 0);
+    for (int j = threadIdx.x; j < N; j += NT) {
+        const double2 z = result_at(buf, d, j);  // FFT(conj g)_j; IDFT(g)_j = conj of it
+        outa[j] = z.x;
+        if (rb >= 0) outb[j] = -z.y;
+    }
 }
 
 template <int MAXL, int NT>
 __global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t npix,
-                                                    const int32_t *__restrict__ rings,
-                                                    const int32_t *__restrict__ ring_desc,
-                                                    const FftDesc *__restrict__ descs,
-                                                    const double *__restrict__ phi0,
-                                                    const double *__restrict__ weight,
-                                                    const int64_t *__restrict__ ofs,
-                                                    const double *__restrict__ map,
-                                                    double2 *__restrict__ delta) {
+                                                const int2 *__restrict__ jobs,
+                                                const int32_t *__restrict__ ring_desc,
+                                                const FftDesc *__restrict__ descs,
+                                                const double *__restrict__ phi0,
+                                                const double *__restrict__ weight,
+                                                const int64_t *__restrict__ ofs,
+                                                const double *__restrict__ map,
+                                                double2 *__restrict__ delta) {
     extern __shared__ double2 buf[];
-    const int r = rings[blockIdx.x];
+    const int2 job = jobs[blockIdx.x];
+    const int ra = job.x, rb = job.y;
     const int mp = blockIdx.y;
-    const FftDesc *d = descs + ring_desc[r];
+    const FftDesc *d = descs + ring_desc[ra];
     const int N = d->n;
-    const double *in = map + (int64_t)mp * npix + ofs[r];
-    for (int j = threadIdx.x; j < N; j += NT) buf[j] = input_point(make_double2(in[j], 0.0), d, j);
+    const double *ina = map + (int64_t)mp * npix + ofs[ra];
+    const double *inb = map + (int64_t)mp * npix + (rb >= 0 ? ofs[rb] : 0);
+    for (int j = threadIdx.x; j < N; j += NT)
+        buf[j] = input_point(make_double2(ina[j], rb >= 0 ? inb[j] : 0.0), d, j);
     __syncthreads();
     transform<MAXL, NT>(buf, d);
-    const double ph0 = phi0[r], w = weight[r];
-    double2 *D = delta + ((int64_t)mp * nrings + r) * (mmax + 1);
+    const double pa = phi0[ra], wa = weight[ra];
+    const double pb = rb >= 0 ? phi0[rb] : 0.0, wb = rb >= 0 ? weight[rb] : 0.0;
+    double2 *Da = delta + ((int64_t)mp * nrings + ra) * (mmax + 1);
+    double2 *Db = delta + ((int64_t)mp * nrings + (rb >= 0 ? rb : ra)) * (mmax + 1);
     for (int m = threadIdx.x; m <= mmax; m += NT) {
-        const double2 X = result_at(buf, d, m % N);
-        const double2 e = phase_exp(m, ph0);
-        // w * conj(e) * X
-        D[m] = make_double2(w * fma(X.x, e.x, X.y * e.y), w * fma(X.y, e.x, -X.x * e.y));
+        const int k = m % N, kn = (N - k) % N;
+        const double2 Z = result_at(buf, d, k), Zn = result_at(buf, d, kn);
+        // S_a = (Z_k + conj Z_{n-k}) / 2, S_b = (Z_k - conj Z_{n-k}) / (2i)
+        const double2 Sa = make_double2(0.5 * (Z.x + Zn.x), 0.5 * (Z.y - Zn.y));
+        const double2 Sb = make_double2(0.5 * (Z.y + Zn.y), -0.5 * (Z.x - Zn.x));
+        const double2 ea = phase_exp(m, pa);
+        // w * conj(e) * S
+        Da[m] = make_double2(wa * fma(Sa.x, ea.x, Sa.y * ea.y), wa * fma(Sa.y, ea.x, -Sa.x * ea.y));
+        if (rb >= 0) {
+            const double2 eb = phase_exp(m, pb);
+            Db[m] = make_double2(wb * fma(Sb.x, eb.x, Sb.y * eb.y), wb * fma(Sb.y, eb.x, -Sb.x * eb.y));
+        }
     }
 }
 
@@ -296,18 +398,25 @@ int set_lds_attr() {
                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
     SHT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_ana<8192, fft_threads<8192>()>),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
+    SHT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_syn<1024, fft_threads<1024>()>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     g_attr_set = true;
     return SHT_OK;
 }
 
 template <int MAXL>
-void launch_syn_class(const GeomPlan &p, int c, int mmax, const void *delta, double *map, int nmaps,
-                      hipStream_t st) {
+int launch_syn_class(const GeomPlan &p, int c, int mmax, const void *delta, double *map, int nmaps,
+                     hipStream_t st) {
     constexpr int NT = fft_threads<MAXL>();
-    const size_t lds = (size_t)std::min(MAXL, p.max_L) * sizeof(double2);
+    const size_t base = (size_t)std::min(MAXL, p.max_L) * sizeof(double2);
+    const size_t rows = 2 * (size_t)(mmax + 1) * sizeof(double2);
+    // the small-length class keeps the phased terms in LDS when they fit
+    const int fold_rows = (MAXL <= 1024 && base + rows <= 160 * 1024) ? 1 : 0;
+    const size_t lds = base + (fold_rows ? rows : 0);
     hipLaunchKernelGGL((k_fft_syn<MAXL, NT>), dim3((unsigned)p.class_count[c], (unsigned)nmaps), dim3(NT), lds,
-                       st, mmax, p.nrings, p.npix, p.class_rings[c], p.ring_desc, p.descs, p.phi0, p.ofs,
-                       static_cast<const double2 *>(delta), map);
+                       st, mmax, p.nrings, p.npix, fold_rows, p.class_jobs[c], p.ring_desc, p.descs, p.phi0,
+                       p.ofs, static_cast<const double2 *>(delta), map);
+    return SHT_OK;
 }
 
 template <int MAXL>
@@ -316,7 +425,7 @@ void launch_ana_class(const GeomPlan &p, int c, int mmax, const double *map, voi
     constexpr int NT = fft_threads<MAXL>();
     const size_t lds = (size_t)std::min(MAXL, p.max_L) * sizeof(double2);
     hipLaunchKernelGGL((k_fft_ana<MAXL, NT>), dim3((unsigned)p.class_count[c], (unsigned)nmaps), dim3(NT), lds,
-                       st, mmax, p.nrings, p.npix, p.class_rings[c], p.ring_desc, p.descs, p.phi0, p.weight,
+                       st, mmax, p.nrings, p.npix, p.class_jobs[c], p.ring_desc, p.descs, p.phi0, p.weight,
                        p.ofs, map, static_cast<double2 *>(delta));
 }
 
@@ -329,10 +438,10 @@ int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, double *map, 
     if (nmaps > 65535) return SHT_EUNSUPPORTED;
     int rc = set_lds_attr();
     if (rc) return rc;
-    if (p.class_count[0]) launch_syn_class<1024>(p, 0, mmax, delta, map, nmaps, st);
-    if (p.class_count[1]) launch_syn_class<2048>(p, 1, mmax, delta, map, nmaps, st);
-    if (p.class_count[2]) launch_syn_class<4096>(p, 2, mmax, delta, map, nmaps, st);
-    if (p.class_count[3]) launch_syn_class<8192>(p, 3, mmax, delta, map, nmaps, st);
+    if (p.class_count[0] && (rc = launch_syn_class<1024>(p, 0, mmax, delta, map, nmaps, st))) return rc;
+    if (p.class_count[1] && (rc = launch_syn_class<2048>(p, 1, mmax, delta, map, nmaps, st))) return rc;
+    if (p.class_count[2] && (rc = launch_syn_class<4096>(p, 2, mmax, delta, map, nmaps, st))) return rc;
+    if (p.class_count[3] && (rc = launch_syn_class<8192>(p, 3, mmax, delta, map, nmaps, st))) return rc;
     SHT_HIP(hipGetLastError());
     return SHT_OK;
 }

@@ -17,13 +17,13 @@ constexpr int kMaxFftLen = 8192;     // complex points one workgroup holds in LD
 constexpr int kMaxRadices = 16;
 constexpr int kFftClasses = 4;
 constexpr int kFftClassLen[kFftClasses] = {1024, 2048, 4096, 8192};
-// Analysis: a workgroup of kBlock threads holds kAnaSlotsPerThread ring
+// Analysis: a workgroup of kBlock threads holds up to kAnaSlotsPerThread ring
 // slots per thread; an m whose slots need several workgroups writes one
 // partial a_lm per group to the workspace, summed afterwards in group order.
 constexpr int kAnaSlotsPerThread = 4;
 
 inline int ana_slots_per_thread(int nslots) {
-    return nslots <= kBlock ? 1 : (nslots <= 2 * kBlock ? 2 : kAnaSlotsPerThread);
+    return nslots <= kBlock ? 1 : nslots <= 2 * kBlock ? 2 : nslots <= 4 * kBlock ? 4 : kAnaSlotsPerThread;
 }
 inline int ana_groups(int nslots) {
     const int per = kBlock * ana_slots_per_thread(nslots);
@@ -79,9 +79,10 @@ struct GeomPlan {
     int64_t *ofs = nullptr;
     int32_t *ring_desc = nullptr;    // index into descs
     FftDesc *descs = nullptr;
-    // rings grouped by FFT length class (L <= kFftClassLen[c]), one launch per class
+    // FFT jobs (one ring, or two rings of equal length: mirror pairs first),
+    // grouped by transform-length class (L <= kFftClassLen[c]), one launch per class
     int class_count[4] = {0, 0, 0, 0};
-    int32_t *class_rings[4] = {nullptr, nullptr, nullptr, nullptr};
+    int2 *class_jobs[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<void *> owned;       // device allocations to free
 };
 

@@ -410,17 +410,39 @@ int get_geom(const HostGeom &hg, int /*mmax_for_fft*/, const GeomPlan **out) {
     }
     p.max_L = maxL;
     p.all_nphi_max = maxn;
-    std::vector<int32_t> cls[kFftClasses];
+    // FFT jobs: mirror pairs with equal nphi, then leftover rings paired by length
+    std::vector<int2> jobs;
+    std::vector<char> used(hg.nrings, 0);
+    for (size_t i = 0; i < sn.size(); ++i) {
+        const int a = sn[i], b = sso[i];
+        if (b >= 0 && hg.nphi[a] == hg.nphi[b]) {
+            jobs.push_back(make_int2(a, b));
+            used[a] = used[b] = 1;
+        }
+    }
+    std::map<int, int> waiting;  // nphi -> ring without a partner yet
     for (int r = 0; r < hg.nrings; ++r) {
-        const int L = descs[ring_desc[r]].L;
+        if (used[r]) continue;
+        auto it = waiting.find(hg.nphi[r]);
+        if (it == waiting.end()) {
+            waiting[hg.nphi[r]] = r;
+        } else {
+            jobs.push_back(make_int2(it->second, r));
+            waiting.erase(it);
+        }
+    }
+    for (auto &kv : waiting) jobs.push_back(make_int2(kv.second, -1));
+    std::vector<int2> cls[kFftClasses];
+    for (const int2 &j : jobs) {
+        const int L = descs[ring_desc[j.x]].L;
         int c = 0;
         while (c < kFftClasses - 1 && L > kFftClassLen[c]) ++c;
-        cls[c].push_back(r);
+        cls[c].push_back(j);
     }
     for (int c = 0; c < kFftClasses; ++c) {
         p.class_count[c] = (int)cls[c].size();
         if (cls[c].empty()) continue;
-        if ((rc = upload(cls[c], &p.class_rings[c], p.owned))) {
+        if ((rc = upload(cls[c], &p.class_jobs[c], p.owned))) {
             free_plan(p);
             return rc;
         }
