@@ -9,39 +9,43 @@
 //
 // The recurrence runs in a rescaled variable q_l = lambda_l / c_l for which
 // the coefficient of q_{l-2} is -1 (q_l = alpha_l x q_{l-1} - q_{l-2}); the
-// plan tabulates alpha and c.  Synthesis folds c into a_lm once per call
-// (k_prescale); analysis multiplies each finished a_lm by c.
+// plan tabulates alpha and c (0.16 < c < 1.13).  Synthesis folds c into a_lm
+// once per call (k_prescale); analysis multiplies each finished a_lm by c.
 //
 // One recurrence serves a ring and its mirror image (x -> -x) because
 // lambda_lm(-x) = (-1)^(l+m) lambda_lm(x): even and odd (l+m) partial sums
 // are kept apart and combined as E+O (north) and E-O (south).
 //
+// Underflow near the poles (Sec. 2.1 asks for rescaling and leaves the
+// algorithm to its references).  Once per plan, k_leg_start runs every
+// (m, slot) recurrence from its seed with exponent tracking (a value held as
+// q * 2^(600 sc), sc <= 0) until |q| first reaches 2^-100, and stores the l
+// that opens the block of kStep steps (counted from m) holding that step,
+// with the two recurrence values before it.  The transform kernels start
+// each slot there: every term they leave out has |lambda| < 1.13 * 2^-100,
+// and from its start on a slot's values stay in normal double range, so the
+// hot loops have no rescaling.  A slot whose values stay below 2^-100 up to
+// lmax is not started at all.
+//
 // Work mapping (the paper's GPU design assigns one ring per thread and the
 // rings loop outermost; here a workgroup owns one m for a tile of ring
-// pairs, so the m-dependent loop length is uniform across the workgroup and
-// a_lm, alpha are wave-uniform scalar loads):
-//   synthesis  grid.x = (m, 512-slot tile) with m ascending (longest first),
-//              grid.y = map; two slots per lane, no reduction needed.
-//   analysis   grid.x = (m ascending, slot group), grid.y = map; a workgroup
-//              owns up to 1024 slots of its m (T slots per lane); each wave sums
-//              its lanes through its own LDS rows, the four waves are added in
-//              wave order every 64 l, and groups are summed in order by a
-//              second small kernel: no atomics, bitwise deterministic.
-//
-// Underflow near the poles (Sec. 2.1, rescaling; the paper leaves the
-// algorithm to its references): a value is held as q * 2^(600 sc), sc <= 0.
-// While sc < 0 the value is below 2^-660 and its term is dropped; when the
-// carrier exceeds 2^-60 it is scaled by 2^-600 and sc incremented (checked
-// every second step).  Waves run three loops: (A0) every lane negligible:
-// recurrence only; (A) some lane still rescaling: terms weighted by 0/1;
-// (B) all lanes in range: no checks.
+// pairs, so the loop over l is uniform across a wave and a_lm, alpha are
+// wave-uniform scalar operands):
+//   synthesis  grid.x = (m, 512-slot tile), m ascending (longest first),
+//              grid.y = map; two adjacent slots per lane, no reduction.
+//   analysis   grid.x = (m, slot group), grid.y = map; a workgroup owns up
+//              to 256T slots of its m (T adjacent slots per lane); each wave
+//              sums its lanes through its own LDS rows, the four waves are
+//              added in wave order every 64 l, and groups are summed in
+//              order by a second small kernel: no atomics, deterministic.
 #include "sht_internal.h"
 
 namespace sht {
 namespace {
 
-constexpr double kDown = 0x1p-600;       // 2^-kScaleBits
-constexpr double kThresh = 0x1p-60;
+constexpr double kDown = 0x1p-600;   // 2^-kScaleBits
+constexpr double kThresh = 0x1p-60;  // carrier bound that triggers rescaling
+constexpr double kStart = 0x1p-100;  // a slot starts once |q| reaches this
 static_assert(kScaleBits == 600, "kDown must equal 2^-kScaleBits");
 
 // lambda_mm = (-1)^m mu_m s^m as carrier * 2^(600 sc).  s^m by binary
@@ -74,6 +78,54 @@ __device__ __forceinline__ double seed_carrier(int m, double s, double mu_m, int
     return ldexp(v, E + kScaleBits * ns);
 }
 
+// Plan kernel: one thread per (m, slot); grid.x covers slots, grid.y = m.
+// Writes lstart[m * nslots + slot] (lmax + 1 when never reached) and
+// state[m * nslots + slot] = (q_{l-2}, q_{l-1}) before step l = lstart.
+__global__ __launch_bounds__(kBlock) void k_leg_start(int lmax, int nslots, const double *__restrict__ alpha,
+                                                      const double *__restrict__ mu,
+                                                      const double *__restrict__ sx,
+                                                      const double *__restrict__ ss,
+                                                      int32_t *__restrict__ lstart,
+                                                      double2 *__restrict__ state) {
+    const int slot = blockIdx.x * kBlock + threadIdx.x;
+    const int m = blockIdx.y;
+    if (slot >= nslots) return;
+    const double x = sx[slot];
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const double *__restrict__ al = alpha + base;
+    int sc;
+    const double seed = seed_carrier(m, ss[slot], mu[m], sc);
+    // (q_{l-2}, q_{l-1}) before step l; (-seed, 0) makes step l = m yield the seed
+    double q2 = -seed, q1 = 0.0;
+    int found = lmax + 1;
+    double s2 = 0.0, s1 = 0.0;
+    for (int l0 = m; l0 <= lmax && found > lmax; l0 += kStartStep) {
+        const double b2 = q2, b1 = q1;
+        const int bsc = sc;
+        bool hit = false;
+        for (int i = 0; i < kStartStep && l0 + i <= lmax; ++i) {
+            const double q = fma(al[l0 + i] * x, q1, -q2);
+            q2 = q1;
+            q1 = q;
+            hit |= (sc == 0 && fabs(q) >= kStart);
+            if ((i & 1) && sc < 0 && fabs(q1) > kThresh) {
+                q1 *= kDown;
+                q2 *= kDown;
+                ++sc;
+            }
+        }
+        if (hit) {
+            found = l0;
+            // a value leaves sc < 0 near 2^-660 and cannot grow past 2^-100
+            // within one block, so bsc is 0 here in practice
+            s2 = ldexp(b2, kScaleBits * bsc);
+            s1 = ldexp(b1, kScaleBits * bsc);
+        }
+    }
+    lstart[(int64_t)m * nslots + slot] = found;
+    state[(int64_t)m * nslots + slot] = make_double2(s2, s1);
+}
+
 __global__ __launch_bounds__(kBlock) void k_prescale(int64_t nalm, int lmax, int nmaps,
                                                      const double2 *__restrict__ alm,
                                                      const double *__restrict__ cfac,
@@ -89,15 +141,28 @@ __global__ __launch_bounds__(kBlock) void k_prescale(int64_t nalm, int lmax, int
     }
 }
 
-// Synthesis: lane i of tile t owns slots t*256*T + i + 256*u, u < T.
+// Wave-wide min / max, returned as a wave-uniform (scalar) value so that
+// loops bounded by it stay uniform and their coefficient loads scalar.
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// Synthesis: lane i of tile t owns slots (t*256 + i)*T + u, u < T.
 template <int T>
 __global__ __launch_bounds__(kBlock) void k_leg_syn(int lmax, int mmax, int nslots, int tiles,
                                                     int nrings, int64_t nalm,
                                                     const double2 *__restrict__ ap,
                                                     const double *__restrict__ alpha,
-                                                    const double *__restrict__ mu,
+                                                    const int32_t *__restrict__ lstart,
+                                                    const double2 *__restrict__ state,
                                                     const double *__restrict__ sx,
-                                                    const double *__restrict__ ss,
                                                     const int32_t *__restrict__ rn,
                                                     const int32_t *__restrict__ rsouth,
                                                     double2 *__restrict__ delta) {
@@ -107,35 +172,26 @@ __global__ __launch_bounds__(kBlock) void k_leg_syn(int lmax, int mmax, int nslo
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;  // (l, m) lives at base + l
     const double2 *__restrict__ a = ap + (int64_t)map * nalm + base;
     const double *__restrict__ al = alpha + base;
-    const double mu_m = mu[m];
 
-    double x[T], q1[T], q2[T], cf[T], er[T], ei[T], orr[T], oi[T];
-    int sc[T];
+    double x[T], q1[T], q2[T], er[T], ei[T], orr[T], oi[T];
+    int ls[T];
+    double2 st[T];
+    int lo = lmax + 1, hi = m;
 #pragma unroll
     for (int u = 0; u < T; ++u) {
-        const int slot = tile * kBlock * T + u * kBlock + threadIdx.x;
+        const int slot = (tile * kBlock + (int)threadIdx.x) * T + u;
         const bool act = slot < nslots;
         x[u] = act ? sx[slot] : 0.0;
-        const double s = act ? ss[slot] : 1.0;
-        const double seed = seed_carrier(m, s, mu_m, sc[u]);
-        // state (q_{l-2}, q_{l-1}) before step l; (-seed, 0) makes step l = m yield the seed
-        q2[u] = -seed;
-        q1[u] = 0.0;
-        cf[u] = (sc[u] == 0) ? 1.0 : 0.0;
+        ls[u] = act ? lstart[(int64_t)m * nslots + slot] : lmax + 1;
+        st[u] = act ? state[(int64_t)m * nslots + slot] : make_double2(0.0, 0.0);
+        q1[u] = q2[u] = 0.0;  // a slot carries zeros until it starts
         er[u] = ei[u] = orr[u] = oi[u] = 0.0;
+        lo = min(lo, ls[u]);
+        if (ls[u] <= lmax) hi = max(hi, ls[u]);
     }
-    auto any_scaled = [&]() {
-        bool b = false;
-#pragma unroll
-        for (int u = 0; u < T; ++u) b |= (sc[u] < 0);
-        return b;
-    };
-    auto all_scaled = [&]() {
-        bool b = true;
-#pragma unroll
-        for (int u = 0; u < T; ++u) b &= (sc[u] < 0);
-        return b;
-    };
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+
     auto rec = [&](double av) {
 #pragma unroll
         for (int u = 0; u < T; ++u) {
@@ -144,48 +200,48 @@ __global__ __launch_bounds__(kBlock) void k_leg_syn(int lmax, int mmax, int nslo
             q1[u] = q;
         }
     };
-    auto rescale = [&]() {
+    auto acc_e = [&](double2 c) {
 #pragma unroll
         for (int u = 0; u < T; ++u) {
-            if (sc[u] < 0 && fabs(q1[u]) > kThresh) {
-                q1[u] *= kDown;
-                q2[u] *= kDown;
-                ++sc[u];
-                cf[u] = (sc[u] == 0) ? 1.0 : 0.0;
+            er[u] = fma(c.x, q1[u], er[u]);
+            ei[u] = fma(c.y, q1[u], ei[u]);
+        }
+    };
+    auto acc_o = [&](double2 c) {
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            orr[u] = fma(c.x, q1[u], orr[u]);
+            oi[u] = fma(c.y, q1[u], oi[u]);
+        }
+    };
+    auto inject = [&](int l) {
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            if (ls[u] == l) {
+                q2[u] = st[u].x;
+                q1[u] = st[u].y;
             }
         }
     };
 
-    int l = m;
-    // (A0) every value below range: recurrence only
-    while (l + 1 <= lmax && __all(all_scaled())) {
-        rec(al[l]);
-        rec(al[l + 1]);
-        rescale();
-        l += 2;
-    }
-    // (A) some value below range: terms weighted by cf (0 or 1)
-    while (l + 1 <= lmax && __any(any_scaled())) {
-        const double2 c0 = a[l], c1 = a[l + 1];
-        rec(al[l]);
+    // start positions are m + kStartStep k: walk whole blocks while lanes join
+    int l = lo;
+    for (; l <= hi && l + kStartStep - 1 <= lmax; l += kStartStep) {
+        inject(l);
 #pragma unroll
-        for (int u = 0; u < T; ++u) {
-            const double p = cf[u] * q1[u];
-            er[u] = fma(c0.x, p, er[u]);
-            ei[u] = fma(c0.y, p, ei[u]);
+        for (int i = 0; i < kStartStep; i += 2) {
+            rec(al[l + i]);
+            acc_e(a[l + i]);
+            rec(al[l + i + 1]);
+            acc_o(a[l + i + 1]);
         }
-        rec(al[l + 1]);
-#pragma unroll
-        for (int u = 0; u < T; ++u) {
-            const double p = cf[u] * q1[u];
-            orr[u] = fma(c1.x, p, orr[u]);
-            oi[u] = fma(c1.y, p, oi[u]);
-        }
-        rescale();
-        l += 2;
     }
-    // (B) all values in range: four steps per iteration, next block's
-    // coefficients loaded one iteration ahead
+    if (l <= hi) inject(l);  // the last start lies in the ragged tail
+    // l is uniform; restate it so that the compiler does not carry the lane
+    // value it equals inside inject() into the loops below
+    l = __builtin_amdgcn_readfirstlane(l);
+    // every started slot is running: four steps per iteration, the next
+    // iteration's coefficients loaded one ahead
     if (l + 3 <= lmax) {
         double a0 = al[l], a1 = al[l + 1], a2 = al[l + 2], a3 = al[l + 3];
         double2 c0 = a[l], c1 = a[l + 1], c2 = a[l + 2], c3 = a[l + 3];
@@ -198,56 +254,34 @@ __global__ __launch_bounds__(kBlock) void k_leg_syn(int lmax, int mmax, int nslo
                 d0 = a[l + 4]; d1 = a[l + 5]; d2 = a[l + 6]; d3 = a[l + 7];
             }
             rec(a0);
-#pragma unroll
-            for (int u = 0; u < T; ++u) { er[u] = fma(c0.x, q1[u], er[u]); ei[u] = fma(c0.y, q1[u], ei[u]); }
+            acc_e(c0);
             rec(a1);
-#pragma unroll
-            for (int u = 0; u < T; ++u) { orr[u] = fma(c1.x, q1[u], orr[u]); oi[u] = fma(c1.y, q1[u], oi[u]); }
+            acc_o(c1);
             rec(a2);
-#pragma unroll
-            for (int u = 0; u < T; ++u) { er[u] = fma(c2.x, q1[u], er[u]); ei[u] = fma(c2.y, q1[u], ei[u]); }
+            acc_e(c2);
             rec(a3);
-#pragma unroll
-            for (int u = 0; u < T; ++u) { orr[u] = fma(c3.x, q1[u], orr[u]); oi[u] = fma(c3.y, q1[u], oi[u]); }
+            acc_o(c3);
             l += 4;
             if (!more) break;
             a0 = n0; a1 = n1; a2 = n2; a3 = n3;
             c0 = d0; c1 = d1; c2 = d2; c3 = d3;
         }
     }
-    // remaining steps (fewer than four), weighted by cf in case phase (A) ran out of l
     for (; l + 1 <= lmax; l += 2) {
-        const double2 c0 = a[l], c1 = a[l + 1];
         rec(al[l]);
-#pragma unroll
-        for (int u = 0; u < T; ++u) {
-            const double p = cf[u] * q1[u];
-            er[u] = fma(c0.x, p, er[u]);
-            ei[u] = fma(c0.y, p, ei[u]);
-        }
+        acc_e(a[l]);
         rec(al[l + 1]);
-#pragma unroll
-        for (int u = 0; u < T; ++u) {
-            const double p = cf[u] * q1[u];
-            orr[u] = fma(c1.x, p, orr[u]);
-            oi[u] = fma(c1.y, p, oi[u]);
-        }
+        acc_o(a[l + 1]);
     }
     if (l == lmax) {  // one trailing step with even (l - m)
-        const double2 c0 = a[l];
         rec(al[l]);
-#pragma unroll
-        for (int u = 0; u < T; ++u) {
-            const double p = cf[u] * q1[u];
-            er[u] = fma(c0.x, p, er[u]);
-            ei[u] = fma(c0.y, p, ei[u]);
-        }
+        acc_e(a[l]);
     }
 
     double2 *d = delta + (int64_t)map * nrings * (mmax + 1);
 #pragma unroll
     for (int u = 0; u < T; ++u) {
-        const int slot = tile * kBlock * T + u * kBlock + threadIdx.x;
+        const int slot = (tile * kBlock + (int)threadIdx.x) * T + u;
         if (slot < nslots) {
             d[(int64_t)rn[slot] * (mmax + 1) + m] = make_double2(er[u] + orr[u], ei[u] + oi[u]);
             const int r2 = rsouth[slot];
@@ -256,18 +290,17 @@ __global__ __launch_bounds__(kBlock) void k_leg_syn(int lmax, int mmax, int nslo
     }
 }
 
-constexpr int kChunk = 8;   // l values per in-wave reduction in analysis
-constexpr int kFlush = 8;   // chunks between cross-wave flushes (one barrier each)
-constexpr int kTPad = 65;   // padded row (doubles) of the wave-private transpose buffer
+constexpr int kChunk = kStartStep;  // l values per in-wave reduction in analysis
+constexpr int kFlush = 8;           // chunks between cross-wave flushes (one barrier each)
+constexpr int kTPad = 65;           // padded row (doubles) of the wave-private transpose buffer
 
 // One chunk of kChunk recurrence steps for the T slots of a lane, accumulating
-// sum_slots q_l * D(parity) per l, with the chunk's alpha_l in av.  SLOW:
-// terms of slots still below range (sc < 0) are dropped and carriers rescaled;
-// FULL: no l <= lmax guard.
-template <int T, bool SLOW, bool FULL>
+// sum_slots q_l * D(parity) per l, with the chunk's alpha_l in av.  FULL: no
+// l <= lmax guard.
+template <int T, bool FULL>
 __device__ __forceinline__ void ana_chunk(int l0, int lmax, const double (&av)[kChunk],
                                           const double (&x)[T], double (&q1)[T], double (&q2)[T],
-                                          int (&sc)[T], const double (&pr)[T], const double (&pi)[T],
+                                          const double (&pr)[T], const double (&pi)[T],
                                           const double (&mr)[T], const double (&mi)[T],
                                           double (&accr)[kChunk], double (&acci)[kChunk]) {
 #pragma unroll
@@ -281,19 +314,8 @@ __device__ __forceinline__ void ana_chunk(int l0, int lmax, const double (&av)[k
                 const double q = fma(av[i], x[t] * q1[t], -q2[t]);
                 q2[t] = q1[t];
                 q1[t] = q;
-                const double p = SLOW ? (sc[t] == 0 ? q : 0.0) : q;
-                accr[i] = fma(p, (i & 1) ? mr[t] : pr[t], accr[i]);
-                acci[i] = fma(p, (i & 1) ? mi[t] : pi[t], acci[i]);
-            }
-            if (SLOW && (i & 1)) {
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    if (sc[t] < 0 && fabs(q1[t]) > kThresh) {
-                        q1[t] *= kDown;
-                        q2[t] *= kDown;
-                        ++sc[t];
-                    }
-                }
+                accr[i] = fma(q, (i & 1) ? mr[t] : pr[t], accr[i]);
+                acci[i] = fma(q, (i & 1) ? mi[t] : pi[t], acci[i]);
             }
         }
     }
@@ -313,21 +335,22 @@ __device__ __forceinline__ double quad_sum(double v) {
 }
 
 // Analysis: workgroups of 4 waves; wave w of group g of m owns slots
-// (g*4 + w) * 64T + lane*T + t.  Per chunk of kChunk l values each lane sums
-// its T slots; the wave sums its 64 lanes through its own LDS rows (no
+// ((g*4 + w) * 64 + lane) * T + t.  Per chunk of kChunk l values each lane
+// sums its T slots; the wave sums its 64 lanes through its own LDS rows (no
 // barrier); every kFlush chunks the 4 wave sums are added in wave order after
-// one barrier.  With one group the finished a_lm (times c_lm) is written;
-// otherwise the group's partial goes to part[(map * groups + group) * nalm + idx]
-// for k_ana_combine.
+// one barrier.  The workgroup starts at the earliest start of its slots (a_lm
+// before it get no term); a wave adds zeros until its own first start.  With
+// one group the finished a_lm (times c_lm) is written; otherwise the group's
+// partial goes to part[(map * groups + group) * nalm + idx] for k_ana_combine.
 template <int T>
 __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslots, int nrings,
                                                     int64_t nalm, int groups,
                                                     const double2 *__restrict__ delta,
                                                     const double *__restrict__ alpha,
                                                     const double *__restrict__ cfac,
-                                                    const double *__restrict__ mu,
+                                                    const int32_t *__restrict__ lstart,
+                                                    const double2 *__restrict__ state,
                                                     const double *__restrict__ sx,
-                                                    const double *__restrict__ ss,
                                                     const int32_t *__restrict__ rn,
                                                     const int32_t *__restrict__ rsouth,
                                                     double2 *__restrict__ alm,
@@ -336,6 +359,7 @@ __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslo
     constexpr int kWaves = kBlock / 64;
     __shared__ double tbuf[kWaves][kVals][kTPad];     // wave-private transpose rows
     __shared__ double ring[2][kFlush][kWaves][kVals]; // per-wave chunk sums awaiting the flush
+    __shared__ int wstart[kWaves];
     static_assert(kFlush * kVals <= kBlock, "one thread per flushed value");
     const int m = blockIdx.x / groups;
     const int grp = blockIdx.x - m * groups;
@@ -344,17 +368,22 @@ __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslo
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     const double *__restrict__ al = alpha + base;
     const double2 *__restrict__ d = delta + (int64_t)map * nrings * (mmax + 1);
+    double2 *__restrict__ dst = (groups == 1) ? alm + (int64_t)map * nalm + base
+                                              : part + ((int64_t)map * groups + grp) * nalm + base;
 
     double x[T], q1[T], q2[T], pr[T], pi[T], mr[T], mi[T];
-    int sc[T];
+    int ls[T];
+    double2 st[T];
+    int lo = lmax + 1, hi = m;
 #pragma unroll
     for (int t = 0; t < T; ++t) {
-        const int slot = (grp * kWaves + wave) * 64 * T + lane * T + t;
+        const int slot = ((grp * kWaves + wave) * 64 + lane) * T + t;
         const bool act = slot < nslots;
         x[t] = act ? sx[slot] : 0.0;
-        const double s = act ? ss[slot] : 1.0;
+        ls[t] = act ? lstart[(int64_t)m * nslots + slot] : lmax + 1;
+        st[t] = act ? state[(int64_t)m * nslots + slot] : make_double2(0.0, 0.0);
         double2 dn = make_double2(0.0, 0.0), ds = make_double2(0.0, 0.0);
-        if (act) {
+        if (ls[t] <= lmax) {
             dn = d[(int64_t)rn[slot] * (mmax + 1) + m];
             const int r2 = rsouth[slot];
             if (r2 >= 0) ds = d[(int64_t)r2 * (mmax + 1) + m];
@@ -364,10 +393,20 @@ __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslo
         pi[t] = dn.y + ds.y;
         mr[t] = dn.x - ds.x;
         mi[t] = dn.y - ds.y;
-        const double seed = seed_carrier(m, s, mu[m], sc[t]);
-        q2[t] = -seed;
-        q1[t] = 0.0;
+        q1[t] = q2[t] = 0.0;  // a slot carries zeros until it starts
+        lo = min(lo, ls[t]);
+        if (ls[t] <= lmax) hi = max(hi, ls[t]);
     }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+    if (lane == 0) wstart[wave] = lo;
+    __syncthreads();
+    int l0s = lmax + 1;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) l0s = min(l0s, wstart[w]);
+    l0s = __builtin_amdgcn_readfirstlane(l0s);  // the same in every lane
+
+    for (int l = m + tid; l < l0s; l += kBlock) dst[l] = make_double2(0.0, 0.0);
 
     // flush bookkeeping: thread f < kFlush*kVals owns value (chunk f/kVals, j = f%kVals)
     const int fk = tid / kVals, fj = tid - fk * kVals;
@@ -378,14 +417,8 @@ __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslo
             for (int w = 0; w < kWaves; ++w) v += ring[par][fk][w][fj];
             const int l = lbase + fk * kChunk + (fj >> 1);
             if (l <= lmax) {
-                double *dst;
-                if (groups == 1) {
-                    dst = reinterpret_cast<double *>(alm + (int64_t)map * nalm + base + l) + (fj & 1);
-                    v = (m == 0 && (fj & 1)) ? 0.0 : v * cval;
-                } else {
-                    dst = reinterpret_cast<double *>(part + ((int64_t)map * groups + grp) * nalm + base + l) + (fj & 1);
-                }
-                *dst = v;
+                if (groups == 1) v = (m == 0 && (fj & 1)) ? 0.0 : v * cval;
+                reinterpret_cast<double *>(dst + l)[fj & 1] = v;
             }
         }
     };
@@ -394,27 +427,38 @@ __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslo
         return (groups == 1 && tid < kFlush * kVals && l <= lmax) ? cfac[base + l] : 0.0;
     };
 
+    // alpha is read in whole chunks: entries past lmax belong to the next
+    // column or the padding and are never used
+    static_assert(2 * kChunk <= kCoefPad, "alpha padding too short");
     double av[kChunk];
 #pragma unroll
-    for (int i = 0; i < kChunk; ++i) av[i] = (m + i <= lmax) ? al[m + i] : 0.0;
-    int par = 0, kc = 0, lbase = m;
+    for (int i = 0; i < kChunk; ++i) av[i] = al[l0s + i];
+    int par = 0, kc = 0, lbase = l0s;
     double cval = cfac_for(lbase);
-    for (int l0 = m; l0 <= lmax; l0 += kChunk) {
+    for (int l0 = l0s; l0 <= lmax; l0 += kChunk) {
         double avn[kChunk];  // next chunk's alpha, loaded while this one computes
 #pragma unroll
-        for (int i = 0; i < kChunk; ++i) avn[i] = (l0 + kChunk + i <= lmax) ? al[l0 + kChunk + i] : 0.0;
+        for (int i = 0; i < kChunk; ++i) avn[i] = al[l0 + kChunk + i];
         double accr[kChunk], acci[kChunk];
-        bool scaled = false;
+        if (l0 < lo) {
+            // no slot of this wave has started
 #pragma unroll
-        for (int t = 0; t < T; ++t) scaled |= (sc[t] < 0);
-        const bool slow = __any(scaled);
-        const bool full = (l0 + kChunk - 1 <= lmax);
-        if (full && !slow)
-            ana_chunk<T, false, true>(l0, lmax, av, x, q1, q2, sc, pr, pi, mr, mi, accr, acci);
-        else if (full)
-            ana_chunk<T, true, true>(l0, lmax, av, x, q1, q2, sc, pr, pi, mr, mi, accr, acci);
-        else
-            ana_chunk<T, true, false>(l0, lmax, av, x, q1, q2, sc, pr, pi, mr, mi, accr, acci);
+            for (int i = 0; i < kChunk; ++i) accr[i] = acci[i] = 0.0;
+        } else {
+            if (l0 <= hi) {
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    if (ls[t] == l0) {
+                        q2[t] = st[t].x;
+                        q1[t] = st[t].y;
+                    }
+                }
+            }
+            if (l0 + kChunk - 1 <= lmax)
+                ana_chunk<T, true>(l0, lmax, av, x, q1, q2, pr, pi, mr, mi, accr, acci);
+            else
+                ana_chunk<T, false>(l0, lmax, av, x, q1, q2, pr, pi, mr, mi, accr, acci);
+        }
         // wave sum: each lane writes its 16 values as one column of the wave's
         // rows; lane (j = lane/4, q = lane%4) adds lanes 16q..16q+15 of row j,
         // and the quad of lanes 4j..4j+3 combines by DPP (lane 4j holds the sum)
@@ -471,6 +515,15 @@ __global__ __launch_bounds__(kBlock) void k_ana_combine(int64_t nalm, int lmax, 
 
 static int grid_ok(int64_t n) { return n > 0 && n < (int64_t)INT32_MAX; }
 
+int launch_leg_start(const CoefTables &c, const GeomPlan &p, int32_t *lstart, void *state, hipStream_t st) {
+    const int tiles = (p.nslots + kBlock - 1) / kBlock;
+    if (c.mmax + 1 > 65535) return SHT_EUNSUPPORTED;
+    hipLaunchKernelGGL(k_leg_start, dim3((unsigned)tiles, (unsigned)(c.mmax + 1)), dim3(kBlock), 0, st, c.lmax,
+                       p.nslots, c.alpha, c.mu, p.slot_x, p.slot_s, lstart, static_cast<double2 *>(state));
+    SHT_HIP(hipGetLastError());
+    return SHT_OK;
+}
+
 int launch_prescale(const CoefTables &c, const void *alm, void *aprime, int nmaps, hipStream_t st) {
     const int64_t total = c.nalm * nmaps;
     const int64_t blocks = std::min<int64_t>((total + kBlock - 1) / kBlock, 1 << 16);
@@ -482,40 +535,39 @@ int launch_prescale(const CoefTables &c, const void *alm, void *aprime, int nmap
 
 constexpr int kSynSlotsPerLane = 2;
 
-int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const void *aprime, void *delta, int nmaps,
-                   hipStream_t st) {
+int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *aprime, void *delta,
+                   int nmaps, hipStream_t st) {
     constexpr int T = kSynSlotsPerLane;
     const int tiles = (p.nslots + kBlock * T - 1) / (kBlock * T);
     const int64_t gx = (int64_t)tiles * (c.mmax + 1);
     if (!grid_ok(gx) || nmaps > 65535) return SHT_EUNSUPPORTED;
-    hipLaunchKernelGGL(k_leg_syn<T>, dim3((unsigned)gx, (unsigned)nmaps), dim3(kBlock), 0, st, c.lmax,
-                       c.mmax, p.nslots, tiles, p.nrings, c.nalm, static_cast<const double2 *>(aprime),
-                       c.alpha, c.mu, p.slot_x, p.slot_s, p.slot_north, p.slot_south,
-                       static_cast<double2 *>(delta));
+    hipLaunchKernelGGL(k_leg_syn<T>, dim3((unsigned)gx, (unsigned)nmaps), dim3(kBlock), 0, st, c.lmax, c.mmax,
+                       p.nslots, tiles, p.nrings, c.nalm, static_cast<const double2 *>(aprime), c.alpha, s.lstart,
+                       s.state, p.slot_x, p.slot_north, p.slot_south, static_cast<double2 *>(delta));
     SHT_HIP(hipGetLastError());
     return SHT_OK;
 }
 
 template <int T>
-static void launch_ana_t(const CoefTables &c, const GeomPlan &p, int groups, const void *delta, void *alm,
-                         void *part, int nmaps, hipStream_t st) {
-    hipLaunchKernelGGL(k_leg_ana<T>, dim3((unsigned)((c.mmax + 1) * groups), (unsigned)nmaps), dim3(kBlock),
-                       0, st, c.lmax, c.mmax, p.nslots, p.nrings, c.nalm, groups,
-                       static_cast<const double2 *>(delta), c.alpha, c.cfac, c.mu, p.slot_x, p.slot_s,
-                       p.slot_north, p.slot_south, static_cast<double2 *>(alm), static_cast<double2 *>(part));
+static void launch_ana_t(const CoefTables &c, const GeomPlan &p, const StartTable &s, int groups,
+                         const void *delta, void *alm, void *part, int nmaps, hipStream_t st) {
+    hipLaunchKernelGGL(k_leg_ana<T>, dim3((unsigned)((c.mmax + 1) * groups), (unsigned)nmaps), dim3(kBlock), 0,
+                       st, c.lmax, c.mmax, p.nslots, p.nrings, c.nalm, groups, static_cast<const double2 *>(delta),
+                       c.alpha, c.cfac, s.lstart, s.state, p.slot_x, p.slot_north, p.slot_south,
+                       static_cast<double2 *>(alm), static_cast<double2 *>(part));
 }
 
-int launch_leg_ana(const CoefTables &c, const GeomPlan &p, const void *delta, void *alm, int nmaps,
-                   void *partials, hipStream_t st) {
+int launch_leg_ana(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *delta, void *alm,
+                   int nmaps, void *partials, hipStream_t st) {
     if (nmaps > 65535) return SHT_EUNSUPPORTED;
     const int T = ana_slots_per_thread(p.nslots);
     const int groups = ana_groups(p.nslots);
     if (!grid_ok((int64_t)(c.mmax + 1) * groups)) return SHT_EUNSUPPORTED;
     if (groups > 1 && !partials) return SHT_EWORKSPACE;
     switch (T) {
-        case 1: launch_ana_t<1>(c, p, groups, delta, alm, partials, nmaps, st); break;
-        case 2: launch_ana_t<2>(c, p, groups, delta, alm, partials, nmaps, st); break;
-        default: launch_ana_t<kAnaSlotsPerThread>(c, p, groups, delta, alm, partials, nmaps, st); break;
+        case 1: launch_ana_t<1>(c, p, s, groups, delta, alm, partials, nmaps, st); break;
+        case 2: launch_ana_t<2>(c, p, s, groups, delta, alm, partials, nmaps, st); break;
+        default: launch_ana_t<kAnaSlotsPerThread>(c, p, s, groups, delta, alm, partials, nmaps, st); break;
     }
     SHT_HIP(hipGetLastError());
     if (groups > 1) {

@@ -80,8 +80,10 @@ int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *
     const CoefTables *c;
     const GeomPlan *p;
     if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p))) return rc;
+    const StartTable *s;
+    if ((rc = get_start(*c, *p, as_stream(stream), &s))) return rc;
     if ((rc = launch_prescale(*c, alm, workspace, nmaps, as_stream(stream)))) return rc;
-    return launch_leg_syn(*c, *p, workspace, delta, nmaps, as_stream(stream));
+    return launch_leg_syn(*c, *p, *s, workspace, delta, nmaps, as_stream(stream));
 }
 
 int sht_delta2map(int mmax, const sht_geom *g, const void *delta, double *map, int nmaps,
@@ -124,8 +126,11 @@ int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void
         return SHT_EINVAL;
     const CoefTables *c;
     const GeomPlan *p;
-    if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p))) return rc;
-    return launch_leg_ana(*c, *p, delta, alm, nmaps, workspace, as_stream(stream));
+    const StartTable *s;
+    if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p)) ||
+        (rc = get_start(*c, *p, as_stream(stream), &s)))
+        return rc;
+    return launch_leg_ana(*c, *p, *s, delta, alm, nmaps, workspace, as_stream(stream));
 }
 
 int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *map, int nmaps,
@@ -147,8 +152,10 @@ int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *
     char *ws = static_cast<char *>(workspace);
     void *delta = ws, *aprime = ws + round256(db);
     hipStream_t st = as_stream(stream);
+    const StartTable *s;
+    if ((rc = get_start(*c, *p, st, &s))) return rc;
     if ((rc = launch_prescale(*c, alm, aprime, nmaps, st))) return rc;
-    if ((rc = launch_leg_syn(*c, *p, aprime, delta, nmaps, st))) return rc;
+    if ((rc = launch_leg_syn(*c, *p, *s, aprime, delta, nmaps, st))) return rc;
     return launch_fft_syn(*p, mmax, delta, map, nmaps, st);
 }
 
@@ -171,8 +178,10 @@ int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *
     hipStream_t st = as_stream(stream);
     char *ws = static_cast<char *>(workspace);
     void *delta = ws, *partials = ws + round256(db);
+    const StartTable *s;
+    if ((rc = get_start(*c, *p, st, &s))) return rc;
     if ((rc = launch_fft_ana(*p, mmax, map, delta, nmaps, st))) return rc;
-    return launch_leg_ana(*c, *p, delta, alm, nmaps, partials, st);
+    return launch_leg_ana(*c, *p, *s, delta, alm, nmaps, partials, st);
 }
 
 const char *sht_strerror(int code) {

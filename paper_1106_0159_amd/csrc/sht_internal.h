@@ -30,19 +30,25 @@ inline int ana_groups(int nslots) {
     return (nslots + per - 1) / per;
 }
 
-// Rescaling of the Legendre recurrence (exponent tracking).  A value is kept
-// as q * 2^(kScaleBits * sc) with sc <= 0.  While sc < 0 a value is below
-// 2^-(kScaleBits+60) in magnitude and its contribution is dropped; when the
-// carrier exceeds kRescaleThresh it is multiplied by 2^-kScaleBits and sc
-// incremented.  At sc == 0 the carrier is the value itself.
+// Rescaling of the Legendre recurrence (exponent tracking) in the plan
+// kernel that finds where each recurrence enters double range.  A value is
+// kept as q * 2^(kScaleBits * sc) with sc <= 0; when the carrier of a scaled
+// value exceeds 2^-60 it is multiplied by 2^-kScaleBits and sc incremented.
+// At sc == 0 the carrier is the value itself.
 constexpr int kScaleBits = 600;
+// Recurrence start positions are l = m + kStartStep * k.
+constexpr int kStartStep = 8;
+
+// Zeros after the last alpha column: kernels read whole blocks of alpha up to
+// 2 kStartStep entries past lmax of a column without a guard.
+constexpr int kCoefPad = 16;
 
 // Coefficient tables for one (lmax, mmax) on one device.  Packed (l, m)
 // index as for a_lm.  p_lm = cfac_lm * q_lm, q_lm = alpha_lm x q_{l-1,m} - q_{l-2,m}.
 struct CoefTables {
     int lmax = -1, mmax = -1;
     int64_t nalm = 0;
-    double *alpha = nullptr;  // [nalm]; alpha at l = m is 0, at l = m+1 sqrt(2m+3)
+    double *alpha = nullptr;  // [nalm + kCoefPad]; alpha at l = m is 0, at l = m+1 sqrt(2m+3)
     double *cfac = nullptr;   // [nalm]
     double *mu = nullptr;     // [mmax+1]
 };
@@ -59,6 +65,18 @@ struct FftDesc {
     const double2 *tw;     // W_L[t] = exp(-2 pi i t / L), t < L
     const double2 *chirp;  // b_t = exp(i pi t^2 / n), t < n          (Bluestein)
     const double2 *kern;   // FFT_L of the extended chirp, divided by L (Bluestein)
+};
+
+// Where each (m, slot) recurrence starts, for one coefficient set on one
+// geometry plan: lstart[m * nslots + slot] is the first l of the block of
+// kStartStep steps in which |q_lm| first reaches 2^-100 (lmax + 1 if it never
+// does) and state[m * nslots + slot] = (q_{l-2}, q_{l-1}) before that step.
+// A table built for (lmax', mmax') serves every lmax <= lmax', mmax <= mmax'.
+struct StartTable {
+    int lmax = -1, mmax = -1;
+    int32_t *lstart = nullptr;
+    double2 *state = nullptr;
+    uint64_t last_use = 0;
 };
 
 // Geometry plan for one (ring set) on one device.
@@ -84,6 +102,7 @@ struct GeomPlan {
     int class_count[4] = {0, 0, 0, 0};
     int2 *class_jobs[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<void *> owned;       // device allocations to free
+    std::vector<StartTable> starts;  // built on first use by get_start
 };
 
 struct DeviceContext;
@@ -106,6 +125,8 @@ int validate_sizes(int lmax, int mmax, int nmaps);
 // Plan lookup (builds on first use).  Thread safe.
 int get_coef(int lmax, int mmax, const CoefTables **out);
 int get_geom(const HostGeom &hg, int mmax_for_fft, const GeomPlan **out);
+// Start table of (c, p), built on the stream st and waited for on first use.
+int get_start(const CoefTables &c, const GeomPlan &p, hipStream_t st, const StartTable **out);
 
 void set_hip_error(hipError_t e, const char *where);
 #define SHT_HIP(call)                                        \
@@ -118,11 +139,12 @@ void set_hip_error(hipError_t e, const char *where);
     } while (0)
 
 // Kernel launchers (k_legendre.hip, k_ring_fft.hip).  They enqueue only.
+int launch_leg_start(const CoefTables &c, const GeomPlan &p, int32_t *lstart, void *state, hipStream_t st);
 int launch_prescale(const CoefTables &c, const void *alm, void *aprime, int nmaps, hipStream_t st);
-int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const void *aprime, void *delta,
-                   int nmaps, hipStream_t st);
-int launch_leg_ana(const CoefTables &c, const GeomPlan &p, const void *delta, void *alm, int nmaps,
-                   void *partials, hipStream_t st);
+int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *aprime,
+                   void *delta, int nmaps, hipStream_t st);
+int launch_leg_ana(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *delta,
+                   void *alm, int nmaps, void *partials, hipStream_t st);
 int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, double *map, int nmaps,
                    hipStream_t st);
 int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, int nmaps,

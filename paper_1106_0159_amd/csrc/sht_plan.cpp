@@ -156,6 +156,7 @@ int get_coef(int lmax, int mmax, const CoefTables **out) {
     e->t.lmax = lmax;
     e->t.mmax = mmax;
     e->t.nalm = na;
+    alpha.resize(na + kCoefPad, 0.0);  // kernels may read past the last column
     if ((rc = upload(alpha, &e->t.alpha, e->owned)) || (rc = upload(cfac, &e->t.cfac, e->owned)) ||
         (rc = upload(mu, &e->t.mu, e->owned))) {
         for (void *p : e->owned) (void)hipFree(p);
@@ -298,9 +299,18 @@ static bool same_geom(const HostGeom &a, const HostGeom &b) {
            a.nphi == b.nphi && a.phi0 == b.phi0 && a.ofs == b.ofs && a.weight == b.weight;
 }
 
+static void free_start(StartTable &t) {
+    (void)hipFree(t.lstart);
+    (void)hipFree(t.state);
+    t.lstart = nullptr;
+    t.state = nullptr;
+}
+
 static void free_plan(GeomPlan &p) {
     for (void *q : p.owned) (void)hipFree(q);
     p.owned.clear();
+    for (StartTable &t : p.starts) free_start(t);
+    p.starts.clear();
 }
 
 // Mirror pairs: rings r, r' with |theta_r + theta_r' - pi| <= tol share one
@@ -461,6 +471,52 @@ int get_geom(const HostGeom &hg, int /*mmax_for_fft*/, const GeomPlan **out) {
     e->last_use = ++g_clock;
     *out = &e->plan;
     g_geom.push_back(std::move(e));
+    return SHT_OK;
+}
+
+constexpr size_t kMaxStartTables = 4;  // per geometry plan
+
+int get_start(const CoefTables &c, const GeomPlan &pc, hipStream_t st, const StartTable **out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    // plans are owned by the cache; their start list is extended under the lock
+    GeomPlan &p = const_cast<GeomPlan &>(pc);
+    for (StartTable &t : p.starts) {
+        if (t.lmax >= c.lmax && t.mmax >= c.mmax) {
+            t.last_use = ++g_clock;
+            *out = &t;
+            return SHT_OK;
+        }
+    }
+    if (p.starts.size() >= kMaxStartTables) {
+        // evict the least recently used table; kernels using it may be in flight
+        auto lru = std::min_element(p.starts.begin(), p.starts.end(),
+                                    [](const StartTable &a, const StartTable &b) { return a.last_use < b.last_use; });
+        SHT_HIP(hipDeviceSynchronize());
+        free_start(*lru);
+        p.starts.erase(lru);
+    }
+    StartTable t;
+    t.lmax = c.lmax;
+    t.mmax = c.mmax;
+    const size_t n = (size_t)(c.mmax + 1) * (size_t)p.nslots;
+    void *a = nullptr, *b = nullptr;
+    if (hipMalloc(&a, n * sizeof(int32_t)) != hipSuccess) return SHT_ENOMEM;
+    if (hipMalloc(&b, n * sizeof(double2)) != hipSuccess) {
+        (void)hipFree(a);
+        return SHT_ENOMEM;
+    }
+    t.lstart = static_cast<int32_t *>(a);
+    t.state = static_cast<double2 *>(b);
+    int rc = launch_leg_start(c, p, t.lstart, t.state, st);
+    if (rc == SHT_OK && hipStreamSynchronize(st) != hipSuccess) rc = SHT_EDEVICE;
+    if (rc) {
+        free_start(t);
+        return rc;
+    }
+    t.last_use = ++g_clock;
+    p.starts.reserve(kMaxStartTables);  // pointers handed out stay valid until eviction
+    p.starts.push_back(t);
+    *out = &p.starts.back();
     return SHT_OK;
 }
 
