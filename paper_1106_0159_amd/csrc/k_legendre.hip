@@ -141,6 +141,32 @@ __global__ __launch_bounds__(kBlock) void k_prescale(int64_t nalm, int lmax, int
     }
 }
 
+// Workgroups are dispatched to the XCDs in turn (workgroup b runs on XCD
+// b mod kXcds).  The launchers round the number of m values up to a multiple
+// of kXcds and give the k-th workgroup of XCD x the m value
+// kXcds * (k / parts) + x and the part k % parts, so that the parts (slot tiles
+// or groups) of one m run on one XCD at about the same time and share its L2
+// for the m-column of the coefficient tables; m still ascends in launch order.
+constexpr int kXcds = 8;
+struct MPart {
+    int m, part;
+};
+__device__ __forceinline__ MPart xcd_m_part(int parts) {
+    const int x = blockIdx.x % kXcds, k = blockIdx.x / kXcds;
+    return {kXcds * (k / parts) + x, k % parts};
+}
+
+// One load from each of the first kBlock 128-byte lines of p[stride * i],
+// i0 <= i <= i1 (addresses clamped to i1, so every load is in bounds).  The
+// workgroup's pass over a coefficient column brings it into this XCD's L2
+// ahead of the wave-uniform loads that use it; the value is only handed to an
+// empty asm at the end of the kernel, so nothing waits for it before then.
+__device__ __forceinline__ double warm_l2(const double *p, int stride, int i0, int i1) {
+    const int per_line = 16 / stride;  // entries per 128 bytes
+    const int i = min(i0 + per_line * (int)threadIdx.x, i1);
+    return p[(int64_t)stride * i];
+}
+
 // Wave-wide min / max, returned as a wave-uniform (scalar) value so that
 // loops bounded by it stay uniform and their coefficient loads scalar.
 __device__ __forceinline__ int wave_min(int v) {
@@ -166,12 +192,15 @@ __global__ __launch_bounds__(kBlock) void k_leg_syn(int lmax, int mmax, int nslo
                                                     const int32_t *__restrict__ rn,
                                                     const int32_t *__restrict__ rsouth,
                                                     double2 *__restrict__ delta) {
-    const int m = blockIdx.x / tiles;
-    const int tile = blockIdx.x - m * tiles;
+    const MPart mp = xcd_m_part(tiles);
+    const int m = mp.m, tile = mp.part;
+    if (m > mmax) return;  // padding of the m range to a multiple of kXcds
     const int map = blockIdx.y;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;  // (l, m) lives at base + l
     const double2 *__restrict__ a = ap + (int64_t)map * nalm + base;
     const double *__restrict__ al = alpha + base;
+    const double warm_a = warm_l2(reinterpret_cast<const double *>(a), 2, m, lmax);
+    const double warm_al = warm_l2(al, 1, m, lmax);
 
     double x[T], q1[T], q2[T], er[T], ei[T], orr[T], oi[T];
     int ls[T];
@@ -288,11 +317,18 @@ __global__ __launch_bounds__(kBlock) void k_leg_syn(int lmax, int mmax, int nslo
             if (r2 >= 0) d[(int64_t)r2 * (mmax + 1) + m] = make_double2(er[u] - orr[u], ei[u] - oi[u]);
         }
     }
+    asm volatile("" ::"v"(warm_a), "v"(warm_al));  // the warming loads are waited for only here
 }
 
 constexpr int kChunk = kStartStep;  // l values per in-wave reduction in analysis
-constexpr int kFlush = 8;           // chunks between cross-wave flushes (one barrier each)
-constexpr int kTPad = 65;           // padded row (doubles) of the wave-private transpose buffer
+// chunks between cross-wave flushes (one barrier each); one thread per flushed value
+constexpr int kFlush = kAnaThreads / (2 * kChunk) < 8 ? kAnaThreads / (2 * kChunk) : 8;
+// Wave-private transpose rows: lane i stores its value at (i/16)*kQStride + i%16;
+// lane (j, q) then reads 16 doubles from row j at q*kQStride.  With these
+// strides the 16 lanes of each 64-bit LDS pass touch 16 distinct bank pairs
+// on both the write and the read side.
+constexpr int kQStride = 20;
+constexpr int kTRow = 4 * kQStride + 1;
 
 // One chunk of kChunk recurrence steps for the T slots of a lane, accumulating
 // sum_slots q_l * D(parity) per l, with the chunk's alpha_l in av.  FULL: no
@@ -343,7 +379,7 @@ __device__ __forceinline__ double quad_sum(double v) {
 // one group the finished a_lm (times c_lm) is written; otherwise the group's
 // partial goes to part[(map * groups + group) * nalm + idx] for k_ana_combine.
 template <int T>
-__global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslots, int nrings,
+__global__ __launch_bounds__(kAnaThreads) void k_leg_ana(int lmax, int mmax, int nslots, int nrings,
                                                     int64_t nalm, int groups,
                                                     const double2 *__restrict__ delta,
                                                     const double *__restrict__ alpha,
@@ -356,13 +392,14 @@ __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslo
                                                     double2 *__restrict__ alm,
                                                     double2 *__restrict__ part) {
     constexpr int kVals = 2 * kChunk;                 // (l, re/im) values per chunk
-    constexpr int kWaves = kBlock / 64;
-    __shared__ double tbuf[kWaves][kVals][kTPad];     // wave-private transpose rows
+    constexpr int kWaves = kAnaThreads / 64;
+    __shared__ double tbuf[kWaves][kVals][kTRow];     // wave-private transpose rows
     __shared__ double ring[2][kFlush][kWaves][kVals]; // per-wave chunk sums awaiting the flush
     __shared__ int wstart[kWaves];
-    static_assert(kFlush * kVals <= kBlock, "one thread per flushed value");
-    const int m = blockIdx.x / groups;
-    const int grp = blockIdx.x - m * groups;
+    static_assert(kFlush * kVals <= kAnaThreads, "one thread per flushed value");
+    const MPart mp = xcd_m_part(groups);
+    const int m = mp.m, grp = mp.part;
+    if (m > mmax) return;  // padding of the m range to a multiple of kXcds (before any barrier)
     const int map = blockIdx.y;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
@@ -406,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslo
     for (int w = 0; w < kWaves; ++w) l0s = min(l0s, wstart[w]);
     l0s = __builtin_amdgcn_readfirstlane(l0s);  // the same in every lane
 
-    for (int l = m + tid; l < l0s; l += kBlock) dst[l] = make_double2(0.0, 0.0);
+    for (int l = m + tid; l < l0s; l += kAnaThreads) dst[l] = make_double2(0.0, 0.0);
 
     // flush bookkeeping: thread f < kFlush*kVals owns value (chunk f/kVals, j = f%kVals)
     const int fk = tid / kVals, fj = tid - fk * kVals;
@@ -428,17 +465,20 @@ __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslo
     };
 
     // alpha is read in whole chunks: entries past lmax belong to the next
-    // column or the padding and are never used
-    static_assert(2 * kChunk <= kCoefPad, "alpha padding too short");
-    double av[kChunk];
+    // column or the padding and are never used.  The chunk after next is
+    // loaded once the wave's LDS traffic of a chunk is done, so that waiting
+    // for that traffic never waits for the load as well.
+    static_assert(3 * kChunk <= kCoefPad, "alpha padding too short");
+    double av[kChunk], avn[kChunk];
 #pragma unroll
-    for (int i = 0; i < kChunk; ++i) av[i] = al[l0s + i];
+    for (int i = 0; i < kChunk; ++i) {
+        av[i] = al[l0s + i];
+        avn[i] = al[l0s + kChunk + i];
+    }
+    const int lane_w = (lane >> 4) * kQStride + (lane & 15);  // this lane's column in tbuf
     int par = 0, kc = 0, lbase = l0s;
     double cval = cfac_for(lbase);
     for (int l0 = l0s; l0 <= lmax; l0 += kChunk) {
-        double avn[kChunk];  // next chunk's alpha, loaded while this one computes
-#pragma unroll
-        for (int i = 0; i < kChunk; ++i) avn[i] = al[l0 + kChunk + i];
         double accr[kChunk], acci[kChunk];
         if (l0 < lo) {
             // no slot of this wave has started
@@ -464,20 +504,25 @@ __global__ __launch_bounds__(kBlock) void k_leg_ana(int lmax, int mmax, int nslo
         // and the quad of lanes 4j..4j+3 combines by DPP (lane 4j holds the sum)
 #pragma unroll
         for (int i = 0; i < kChunk; ++i) {
-            tbuf[wave][2 * i][lane] = accr[i];
-            tbuf[wave][2 * i + 1][lane] = acci[i];
-            av[i] = avn[i];
+            tbuf[wave][2 * i][lane_w] = accr[i];
+            tbuf[wave][2 * i + 1][lane_w] = acci[i];
         }
         __builtin_amdgcn_wave_barrier();
         {
             const int j = lane >> 2, q = lane & 3;
-            double v = 0.0;
+            const double *row = &tbuf[wave][j][q * kQStride];
+            double v = row[0];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) v += tbuf[wave][j][q * 16 + k];
+            for (int k = 1; k < 16; ++k) v += row[k];
             v = quad_sum(v);
             if (q == 0) ring[par][kc][wave][j] = v;
         }
         __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) {
+            av[i] = avn[i];
+            avn[i] = al[l0 + 2 * kChunk + i];
+        }
         ++kc;
         if (kc == kFlush || l0 + kChunk > lmax) {
             __syncthreads();
@@ -514,6 +559,8 @@ __global__ __launch_bounds__(kBlock) void k_ana_combine(int64_t nalm, int lmax, 
 }  // namespace
 
 static int grid_ok(int64_t n) { return n > 0 && n < (int64_t)INT32_MAX; }
+// number of m values launched: mmax + 1 rounded up to a multiple of kXcds
+static int64_t padded_m(int mmax) { return ((int64_t)mmax + kXcds) / kXcds * kXcds; }
 
 int launch_leg_start(const CoefTables &c, const GeomPlan &p, int32_t *lstart, void *state, hipStream_t st) {
     const int tiles = (p.nslots + kBlock - 1) / kBlock;
@@ -539,7 +586,7 @@ int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const StartTable &s, 
                    int nmaps, hipStream_t st) {
     constexpr int T = kSynSlotsPerLane;
     const int tiles = (p.nslots + kBlock * T - 1) / (kBlock * T);
-    const int64_t gx = (int64_t)tiles * (c.mmax + 1);
+    const int64_t gx = (int64_t)tiles * padded_m(c.mmax);
     if (!grid_ok(gx) || nmaps > 65535) return SHT_EUNSUPPORTED;
     hipLaunchKernelGGL(k_leg_syn<T>, dim3((unsigned)gx, (unsigned)nmaps), dim3(kBlock), 0, st, c.lmax, c.mmax,
                        p.nslots, tiles, p.nrings, c.nalm, static_cast<const double2 *>(aprime), c.alpha, s.lstart,
@@ -551,7 +598,7 @@ int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const StartTable &s, 
 template <int T>
 static void launch_ana_t(const CoefTables &c, const GeomPlan &p, const StartTable &s, int groups,
                          const void *delta, void *alm, void *part, int nmaps, hipStream_t st) {
-    hipLaunchKernelGGL(k_leg_ana<T>, dim3((unsigned)((c.mmax + 1) * groups), (unsigned)nmaps), dim3(kBlock), 0,
+    hipLaunchKernelGGL(k_leg_ana<T>, dim3((unsigned)(padded_m(c.mmax) * groups), (unsigned)nmaps), dim3(kAnaThreads), 0,
                        st, c.lmax, c.mmax, p.nslots, p.nrings, c.nalm, groups, static_cast<const double2 *>(delta),
                        c.alpha, c.cfac, s.lstart, s.state, p.slot_x, p.slot_north, p.slot_south,
                        static_cast<double2 *>(alm), static_cast<double2 *>(part));
@@ -562,11 +609,12 @@ int launch_leg_ana(const CoefTables &c, const GeomPlan &p, const StartTable &s, 
     if (nmaps > 65535) return SHT_EUNSUPPORTED;
     const int T = ana_slots_per_thread(p.nslots);
     const int groups = ana_groups(p.nslots);
-    if (!grid_ok((int64_t)(c.mmax + 1) * groups)) return SHT_EUNSUPPORTED;
+    if (!grid_ok((int64_t)padded_m(c.mmax) * groups)) return SHT_EUNSUPPORTED;
     if (groups > 1 && !partials) return SHT_EWORKSPACE;
     switch (T) {
         case 1: launch_ana_t<1>(c, p, s, groups, delta, alm, partials, nmaps, st); break;
         case 2: launch_ana_t<2>(c, p, s, groups, delta, alm, partials, nmaps, st); break;
+        case 4: launch_ana_t<4>(c, p, s, groups, delta, alm, partials, nmaps, st); break;
         default: launch_ana_t<kAnaSlotsPerThread>(c, p, s, groups, delta, alm, partials, nmaps, st); break;
     }
     SHT_HIP(hipGetLastError());

@@ -136,11 +136,37 @@ __device__ __forceinline__ void butterfly(double2 (&v)[R]) {
     }
 }
 
+// Twiddles W_L^t = e^{-2 pi i t / L} come from two small LDS tables,
+// W_L^t = hi[t / 64] * lo[t % 64] with hi[h] = W_L^{64 h} and lo[u] = W_L^u,
+// both copied from the plan's correctly rounded table once per workgroup:
+// one extra complex product per twiddle (about one more rounding) instead of
+// a global load in every stage.
+constexpr int kTwLo = 64;
+template <int MAXL>
+constexpr int tw_entries() { return kTwLo + (MAXL + kTwLo - 1) / kTwLo; }
+
+struct TwLds {
+    const double2 *lo, *hi;
+    __device__ __forceinline__ double2 operator()(int t) const { return cmul(hi[t / kTwLo], lo[t % kTwLo]); }
+};
+
+// fills the two tables for length L from the plan table tw (caller synchronises)
+template <int NT>
+__device__ __forceinline__ void load_twiddles(double2 *lo, double2 *hi, const double2 *__restrict__ tw, int L) {
+    const int nhi = (L + kTwLo - 1) / kTwLo;
+    for (int t = threadIdx.x; t < kTwLo + nhi; t += NT) {
+        if (t < kTwLo)
+            lo[t] = t < L ? tw[t] : make_double2(1.0, 0.0);
+        else
+            hi[t - kTwLo] = tw[(t - kTwLo) * kTwLo];
+    }
+}
+
 // One Stockham stage of radix R on buf[0..L), L <= MAXL, Ns = product of
 // earlier radices.  Each thread holds up to kMaxB twiddled butterflies in
 // registers (NT threads) and writes them back after the barrier.
 template <int R, int MAXL, int NT>
-__device__ void fft_stage(double2 *buf, int L, int Ns, const double2 *__restrict__ tw) {
+__device__ __forceinline__ void fft_stage(double2 *buf, int L, int Ns, TwLds tw) {
     constexpr int kMaxB = (MAXL / R + NT - 1) / NT;
     const int nbf = L / R;
     const int tstep = L / (Ns * R);
@@ -157,7 +183,7 @@ __device__ void fft_stage(double2 *buf, int L, int Ns, const double2 *__restrict
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const double2 xv = buf[j + r * nbf];
-                v[b][r] = (r == 0) ? xv : cmul(xv, tw[r * k * tstep]);
+                v[b][r] = (r == 0) ? xv : cmul(xv, tw(r * k * tstep));
             }
             butterfly<R>(v[b]);
         }
@@ -179,9 +205,8 @@ __device__ void fft_stage(double2 *buf, int L, int Ns, const double2 *__restrict
 
 // Forward FFT of length d->L (<= MAXL) in LDS (natural order in and out).
 template <int MAXL, int NT>
-__device__ void fft_forward(double2 *buf, const FftDesc *__restrict__ d) {
+__device__ __forceinline__ void fft_forward(double2 *buf, const FftDesc *__restrict__ d, TwLds tw) {
     const int L = d->L, nrad = d->nrad;
-    const double2 *tw = d->tw;
     int Ns = 1;
     for (int s = 0; s < nrad; ++s) {
         const int R = d->rad[s];
@@ -198,19 +223,19 @@ __device__ void fft_forward(double2 *buf, const FftDesc *__restrict__ d) {
 // DFT of the n points already placed in buf[0..n) (pre-multiplied by
 // conj(chirp) when Bluestein): afterwards X_k is at_k(buf, d, k).
 template <int MAXL, int NT>
-__device__ void transform(double2 *buf, const FftDesc *__restrict__ d) {
+__device__ __forceinline__ void transform(double2 *buf, const FftDesc *__restrict__ d, TwLds tw) {
     if (!d->bluestein) {
-        fft_forward<MAXL, NT>(buf, d);
+        fft_forward<MAXL, NT>(buf, d, tw);
         return;
     }
     const int L = d->L;
     const double2 *kern = d->kern;
     for (int t = d->n + threadIdx.x; t < L; t += NT) buf[t] = make_double2(0.0, 0.0);
     __syncthreads();
-    fft_forward<MAXL, NT>(buf, d);
+    fft_forward<MAXL, NT>(buf, d, tw);
     for (int t = threadIdx.x; t < L; t += NT) buf[t] = conj2(cmul(buf[t], kern[t]));
     __syncthreads();
-    fft_forward<MAXL, NT>(buf, d);
+    fft_forward<MAXL, NT>(buf, d, tw);
 }
 
 __device__ __forceinline__ double2 result_at(const double2 *buf, const FftDesc *__restrict__ d, int k) {
@@ -265,18 +290,39 @@ __device__ __forceinline__ void phased_terms(const double2 *__restrict__ D, int 
     }
 }
 
-// sum_{m = k mod n} t_m, in increasing m
-__device__ __forceinline__ double2 fold_terms(const double2 *__restrict__ t, int k, int n, int mmax) {
+// sum_{m = k mod n, m <= lim} t_m, in increasing m
+__device__ __forceinline__ double2 fold_terms(const double2 *__restrict__ t, int k, int n, int lim) {
     double cr = 0.0, ci = 0.0;
-    for (int m = k; m <= mmax; m += n) {
+    for (int m = k; m <= lim; m += n) {
         cr += t[m].x;
         ci += t[m].y;
     }
     return make_double2(cr, ci);
 }
 
-// Synthesis.  LDS: buf[L], plus (fold_rows != 0) two rows of mmax+1 phased
-// terms used when the ring folds many m per bin, n < (mmax+1)/2.
+// In-place column sums for a short ring (n <= NT): with S = n * floor(NT / n),
+// thread u < S replaces t_u by sum_{j >= 0} t_{u + jS}.  As S is a multiple of
+// n, the bin sum c_k is then sum_{i < S/n} t_{k + in}: two short sums instead
+// of one of (mmax+1)/n terms.  Only thread u reads t_u for u < S, so the
+// update needs no extra buffer.  Returns the last index to fold.
+template <int NT>
+__device__ __forceinline__ int fold_columns(double2 *__restrict__ t, int n, int mmax) {
+    const int S = n * (NT / n);
+    const int u = threadIdx.x;
+    if (u < S && u <= mmax) {
+        double cr = 0.0, ci = 0.0;
+        for (int m = u; m <= mmax; m += S) {
+            cr += t[m].x;
+            ci += t[m].y;
+        }
+        t[u] = make_double2(cr, ci);
+    }
+    return min(S - 1, mmax);
+}
+
+// Synthesis.  LDS: the twiddle tables, buf[L], plus (fold_rows != 0) two
+// rows of mmax+1 phased terms used when the ring folds many m per bin,
+// n < (mmax+1)/2.
 template <int MAXL, int NT>
 __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t npix, int fold_rows,
                                                 const int2 *__restrict__ jobs,
@@ -286,22 +332,30 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t np
                                                 const int64_t *__restrict__ ofs,
                                                 const double2 *__restrict__ delta,
                                                 double *__restrict__ map) {
-    extern __shared__ double2 buf[];
+    extern __shared__ double2 lds[];
+    double2 *tlo = lds, *thi = lds + kTwLo, *buf = lds + tw_entries<MAXL>();
     const int2 job = jobs[blockIdx.x];
     const int ra = job.x, rb = job.y;
     const int mp = blockIdx.y;
     const FftDesc *d = descs + ring_desc[ra];
     const int N = d->n, L = d->L;
+    load_twiddles<NT>(tlo, thi, d->tw, L);
     const double2 *__restrict__ Da = delta + ((int64_t)mp * nrings + ra) * (mmax + 1);
     const double2 *__restrict__ Db = delta + ((int64_t)mp * nrings + (rb >= 0 ? rb : ra)) * (mmax + 1);
     const double pa = phi0[ra], pb = rb >= 0 ? phi0[rb] : 0.0;
     const bool lds_fold = fold_rows && (2 * N < mmax + 1);
+    int lim = mmax;  // last index of the phased-term rows that the bins fold
     if (lds_fold) {
-        // all threads evaluate phases, then each bin sums its terms in m order
+        // all threads evaluate phases; short rings first sum the rows in columns
         double2 *ta = buf + L, *tb = buf + L + (mmax + 1);
         phased_terms<NT>(Da, mmax, pa, ta);
         if (rb >= 0) phased_terms<NT>(Db, mmax, pb, tb);
         __syncthreads();
+        if (N <= NT) {
+            lim = fold_columns<NT>(ta, N, mmax);
+            if (rb >= 0) fold_columns<NT>(tb, N, mmax);
+            __syncthreads();
+        }
     }
     // thread handles the bin pair (k, n-k), k = 0..n/2
     for (int k = threadIdx.x; 2 * k <= N; k += NT) {
@@ -309,11 +363,11 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t np
         double2 a0, a1, b0 = make_double2(0.0, 0.0), b1 = make_double2(0.0, 0.0);
         if (lds_fold) {
             const double2 *ta = buf + L, *tb = buf + L + (mmax + 1);
-            a0 = fold_terms(ta, k, N, mmax);
-            a1 = fold_terms(ta, kn, N, mmax);
+            a0 = fold_terms(ta, k, N, lim);
+            a1 = fold_terms(ta, kn, N, lim);
             if (rb >= 0) {
-                b0 = fold_terms(tb, k, N, mmax);
-                b1 = fold_terms(tb, kn, N, mmax);
+                b0 = fold_terms(tb, k, N, lim);
+                b1 = fold_terms(tb, kn, N, lim);
             }
         } else {
             a0 = fold_bin(Da, k, N, mmax, pa);
@@ -333,7 +387,7 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t np
         if (kn != k) buf[kn] = input_point(conj2(gn), d, kn);
     }
     __syncthreads();
-    transform<MAXL, NT>(buf, d);
+    transform<MAXL, NT>(buf, d, TwLds{tlo, thi});
     double *outa = map + (int64_t)mp * npix + ofs[ra];
     double *outb = map + (int64_t)mp * npix + (rb >= 0 ? ofs[rb] : 0);
     for (int j = threadIdx.x; j < N; j += NT) {
@@ -353,18 +407,20 @@ __global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t np
                                                 const int64_t *__restrict__ ofs,
                                                 const double *__restrict__ map,
                                                 double2 *__restrict__ delta) {
-    extern __shared__ double2 buf[];
+    extern __shared__ double2 lds[];
+    double2 *tlo = lds, *thi = lds + kTwLo, *buf = lds + tw_entries<MAXL>();
     const int2 job = jobs[blockIdx.x];
     const int ra = job.x, rb = job.y;
     const int mp = blockIdx.y;
     const FftDesc *d = descs + ring_desc[ra];
     const int N = d->n;
+    load_twiddles<NT>(tlo, thi, d->tw, d->L);
     const double *ina = map + (int64_t)mp * npix + ofs[ra];
     const double *inb = map + (int64_t)mp * npix + (rb >= 0 ? ofs[rb] : 0);
     for (int j = threadIdx.x; j < N; j += NT)
         buf[j] = input_point(make_double2(ina[j], rb >= 0 ? inb[j] : 0.0), d, j);
     __syncthreads();
-    transform<MAXL, NT>(buf, d);
+    transform<MAXL, NT>(buf, d, TwLds{tlo, thi});
     const double pa = phi0[ra], wa = weight[ra];
     const double pb = rb >= 0 ? phi0[rb] : 0.0, wb = rb >= 0 ? weight[rb] : 0.0;
     double2 *Da = delta + ((int64_t)mp * nrings + ra) * (mmax + 1);
@@ -389,29 +445,42 @@ __global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t np
 template <int MAXL>
 constexpr int fft_threads() { return MAXL / 4 < 1024 ? MAXL / 4 : 1024; }
 
+constexpr int kMaxLds = 160 * 1024;  // LDS bytes per workgroup on gfx950
+
+template <int MAXL>
+int allow_max_lds() {
+    constexpr int NT = fft_threads<MAXL>();
+    SHT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_syn<MAXL, NT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds));
+    SHT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_ana<MAXL, NT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds));
+    return SHT_OK;
+}
+
 bool g_attr_set = false;
 
+// every class may use up to the whole LDS (the 4096 class needs more than the
+// 64 KB default: twiddle tables plus 4096 points)
 int set_lds_attr() {
     if (g_attr_set) return SHT_OK;
-    const int bytes = kMaxFftLen * (int)sizeof(double2);
-    SHT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_syn<8192, fft_threads<8192>()>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-    SHT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_ana<8192, fft_threads<8192>()>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes));
-    SHT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_syn<1024, fft_threads<1024>()>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    int rc;
+    if ((rc = allow_max_lds<1024>()) || (rc = allow_max_lds<2048>()) || (rc = allow_max_lds<4096>()) ||
+        (rc = allow_max_lds<8192>()))
+        return rc;
     g_attr_set = true;
     return SHT_OK;
 }
+
+static_assert((tw_entries<kMaxFftLen>() + kMaxFftLen) * sizeof(double2) <= kMaxLds, "largest class fits LDS");
 
 template <int MAXL>
 int launch_syn_class(const GeomPlan &p, int c, int mmax, const void *delta, double *map, int nmaps,
                      hipStream_t st) {
     constexpr int NT = fft_threads<MAXL>();
-    const size_t base = (size_t)std::min(MAXL, p.max_L) * sizeof(double2);
+    const size_t base = (size_t)(tw_entries<MAXL>() + std::min(MAXL, p.max_L)) * sizeof(double2);
     const size_t rows = 2 * (size_t)(mmax + 1) * sizeof(double2);
     // the small-length class keeps the phased terms in LDS when they fit
-    const int fold_rows = (MAXL <= 1024 && base + rows <= 160 * 1024) ? 1 : 0;
+    const int fold_rows = (MAXL <= 1024 && base + rows <= kMaxLds) ? 1 : 0;
     const size_t lds = base + (fold_rows ? rows : 0);
     hipLaunchKernelGGL((k_fft_syn<MAXL, NT>), dim3((unsigned)p.class_count[c], (unsigned)nmaps), dim3(NT), lds,
                        st, mmax, p.nrings, p.npix, fold_rows, p.class_jobs[c], p.ring_desc, p.descs, p.phi0,
@@ -423,7 +492,7 @@ template <int MAXL>
 void launch_ana_class(const GeomPlan &p, int c, int mmax, const double *map, void *delta, int nmaps,
                       hipStream_t st) {
     constexpr int NT = fft_threads<MAXL>();
-    const size_t lds = (size_t)std::min(MAXL, p.max_L) * sizeof(double2);
+    const size_t lds = (size_t)(tw_entries<MAXL>() + std::min(MAXL, p.max_L)) * sizeof(double2);
     hipLaunchKernelGGL((k_fft_ana<MAXL, NT>), dim3((unsigned)p.class_count[c], (unsigned)nmaps), dim3(NT), lds,
                        st, mmax, p.nrings, p.npix, p.class_jobs[c], p.ring_desc, p.descs, p.phi0, p.weight,
                        p.ofs, map, static_cast<double2 *>(delta));

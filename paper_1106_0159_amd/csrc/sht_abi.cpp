@@ -27,13 +27,15 @@ size_t delta_bytes(int nrings, int mmax, int nmaps) {
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
 // Workspace layout: [Delta (synthesis/analysis)][aux], aux holding either the
-// c-scaled a_lm of synthesis or the per-group partial a_lm of analysis.
+// c-scaled a_lm of synthesis (followed by kCoefPad entries that the synthesis
+// kernel may read ahead) or the per-group partial a_lm of analysis.
 size_t partial_bytes(int lmax, int mmax, int nslots, int nmaps) {
     const int G = ana_groups(nslots);
     return G > 1 ? (size_t)G * alm_bytes(lmax, mmax, nmaps) : 0;
 }
 size_t aux_bytes(int lmax, int mmax, int nslots, int nmaps) {
-    return std::max(round256(alm_bytes(lmax, mmax, nmaps)), round256(partial_bytes(lmax, mmax, nslots, nmaps)));
+    return std::max(round256(alm_bytes(lmax, mmax, nmaps) + 16u * kCoefPad),
+                    round256(partial_bytes(lmax, mmax, nslots, nmaps)));
 }
 size_t ws_need(int lmax, int mmax, const HostGeom &h, int nmaps) {
     return round256(delta_bytes(h.nrings, mmax, nmaps)) + aux_bytes(lmax, mmax, count_slots(h), nmaps);

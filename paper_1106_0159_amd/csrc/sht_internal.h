@@ -17,16 +17,17 @@ constexpr int kMaxFftLen = 8192;     // complex points one workgroup holds in LD
 constexpr int kMaxRadices = 16;
 constexpr int kFftClasses = 4;
 constexpr int kFftClassLen[kFftClasses] = {1024, 2048, 4096, 8192};
-// Analysis: a workgroup of kBlock threads holds up to kAnaSlotsPerThread ring
-// slots per thread; an m whose slots need several workgroups writes one
+// Analysis: a workgroup of kAnaThreads threads holds up to kAnaSlotsPerThread
+// ring slots per thread; an m whose slots need several workgroups writes one
 // partial a_lm per group to the workspace, summed afterwards in group order.
-constexpr int kAnaSlotsPerThread = 4;
+constexpr int kAnaThreads = 256;
+constexpr int kAnaSlotsPerThread = 8;
 
 inline int ana_slots_per_thread(int nslots) {
-    return nslots <= kBlock ? 1 : nslots <= 2 * kBlock ? 2 : nslots <= 4 * kBlock ? 4 : kAnaSlotsPerThread;
+    return nslots <= kAnaThreads ? 1 : nslots <= 2 * kAnaThreads ? 2 : nslots <= 4 * kAnaThreads ? 4 : kAnaSlotsPerThread;
 }
 inline int ana_groups(int nslots) {
-    const int per = kBlock * ana_slots_per_thread(nslots);
+    const int per = kAnaThreads * ana_slots_per_thread(nslots);
     return (nslots + per - 1) / per;
 }
 
@@ -39,9 +40,10 @@ constexpr int kScaleBits = 600;
 // Recurrence start positions are l = m + kStartStep * k.
 constexpr int kStartStep = 8;
 
-// Zeros after the last alpha column: kernels read whole blocks of alpha up to
-// 2 kStartStep entries past lmax of a column without a guard.
-constexpr int kCoefPad = 16;
+// Entries after the last column of alpha (zeros) and of the c-scaled a_lm in
+// the workspace: kernels read blocks of coefficients up to 3 kStartStep - 1
+// entries past lmax of a column without a guard.
+constexpr int kCoefPad = 32;
 
 // Coefficient tables for one (lmax, mmax) on one device.  Packed (l, m)
 // index as for a_lm.  p_lm = cfac_lm * q_lm, q_lm = alpha_lm x q_{l-1,m} - q_{l-2,m}.

@@ -57,12 +57,17 @@ def test_workspace_bytes_values_and_monotonic():
     lmax = 16
     na = si.nalm(lmax, lmax)
     r256 = lambda b: (b + 255) // 256 * 256
-    # [Delta][aux]; 16 slots need one analysis group, so aux holds the scaled a_lm
-    assert _ws(lmax, lmax, g) == r256(na * 16) + r256(g.nrings * (lmax + 1) * 16)
-    assert _ws(lmax, lmax, g, 3) == r256(3 * na * 16) + r256(3 * g.nrings * (lmax + 1) * 16)
-    # HEALPix nside=1024: 2048 slots -> two analysis groups of 1024 slots
-    big = si.healpix(1024)
+    # [Delta][aux]; 16 slots need one analysis group, so aux holds the scaled
+    # a_lm and 32 padding entries that synthesis may read ahead
+    pad = 32 * 16
+    assert _ws(lmax, lmax, g) == r256(na * 16 + pad) + r256(g.nrings * (lmax + 1) * 16)
+    assert _ws(lmax, lmax, g, 3) == r256(3 * na * 16 + pad) + r256(3 * g.nrings * (lmax + 1) * 16)
+    # HEALPix nside=1024: 2048 slots fit one analysis workgroup; nside=2048:
+    # 4096 slots -> two groups of 2048, whose partial a_lm fill aux
     na2 = si.nalm(64, 64)
+    big = si.healpix(1024)
+    assert _ws(64, 64, big) == r256(big.nrings * 65 * 16) + r256(na2 * 16 + pad)
+    big = si.healpix(2048)
     assert _ws(64, 64, big) == r256(big.nrings * 65 * 16) + r256(2 * na2 * 16)
     prev = 0
     for l in range(0, 40, 3):
