@@ -37,18 +37,21 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def stored_traffic(kernel: str):
-    """HBM bytes per launch from committed counter runs, if the kernel source is unchanged."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+def stored_counters(stage: str) -> dict:
+    """Per-launch figures from committed rocprofv3 counter runs of a Legendre stage
+    (HBM bytes from FETCH_SIZE/WRITE_SIZE scaled by a plain-copy calibration, and
+    executed FP64 flops from the SQ FP64 instruction counters), or {} when the
+    kernel source has changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "counters.json")
     try:
         with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
-        return None
-    ent = rec.get(kernel)
+        return {}
+    ent = rec.get(stage)
     if not ent or ent.get("source_hash") != kernel_source_hash():
-        return None
-    return ent.get("bytes_per_launch")
+        return {}
+    return ent
 
 
 def count_triples(geom_handle_slots: int, lmax: int, mmax: int) -> int:
@@ -201,6 +204,8 @@ def main():
     flops = FLOPS_PER_TRIPLE * triples
     dom = max(("leg_syn", "leg_ana"), key=lambda n: stage_ms[n])
     achieved = flops / (stage_ms[dom] * 1e-3) / 1e12
+    counters = stored_counters(dom)
+    executed = counters.get("fp64_flops_per_launch")
     rec = {
         "metric": "maps/s at lmax=2048 (plain FP64 vs batched mixed); p50/p99 solve latency",
         "value": 1000.0 / ms_per_step,
@@ -224,14 +229,17 @@ def main():
         "alm2map_maps_per_s": 1000.0 / (stage_ms["leg_syn"] + stage_ms["fft_syn"]),
         "map2alm_maps_per_s": 1000.0 / (stage_ms["fft_ana"] + stage_ms["leg_ana"]),
         "roofline": {
-            "kernel": {"leg_syn": "k_prescale + k_leg_syn", "leg_ana": "k_leg_ana + k_ana_combine"}[dom],
+            "kernel": {"leg_syn": "k_prescale + k_leg_syn",
+                       "leg_ana": "k_leg_ana (+ k_ana_combine above 2048 slots)"}[dom],
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP64_VALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP64_VALU_TFLOPS,
-            "traffic": stored_traffic(dom),
+            "traffic": counters.get("bytes_per_launch"),
             "flops_per_launch": flops,
+            "executed_fp64_flops_per_launch": executed,
+            "executed_tflops": None if executed is None else executed / (stage_ms[dom] * 1e-3) / 1e12,
         },
     }
     if not args.no_cpu_baseline:

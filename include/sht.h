@@ -34,8 +34,11 @@
  * returns without waiting.  A failed validation returns an error before
  * anything is enqueued and leaves all outputs untouched.  Kernel faults
  * surface at the caller's next synchronisation of the stream.  The first call
- * for a (lmax, mmax, geometry) builds and caches device tables (coefficients
- * and FFT plans); that call synchronises the device once.
+ * for a (lmax, mmax, geometry) builds and caches device tables (recurrence
+ * coefficients, FFT plans, and for the Legendre stage the start table: where
+ * each (m, ring pair) recurrence enters double range, 20 bytes per (m, pair),
+ * built by a kernel on `stream`); that call synchronises the device.  The
+ * library owns these tables and frees them on eviction or sht_shutdown().
  *
  * Thread safety: all functions may be called from several host threads.
  * Buffers passed to concurrent calls must not overlap (outputs), and inputs

@@ -31,8 +31,8 @@
 // rings loop outermost; here a workgroup owns one m for a tile of ring
 // pairs, so the loop over l is uniform across a wave and a_lm, alpha are
 // wave-uniform scalar operands):
-//   synthesis  grid.x = (m, 512-slot tile), m ascending (longest first),
-//              grid.y = map; two adjacent slots per lane, no reduction.
+//   synthesis  grid.x = (m, 1024-slot tile), m ascending (longest first),
+//              grid.y = map; four adjacent slots per lane, no reduction.
 //   analysis   grid.x = (m, slot group), grid.y = map; a workgroup owns up
 //              to 256T slots of its m (T adjacent slots per lane); each wave
 //              sums its lanes through its own LDS rows, the four waves are
@@ -143,17 +143,24 @@ __global__ __launch_bounds__(kBlock) void k_prescale(int64_t nalm, int lmax, int
 
 // Workgroups are dispatched to the XCDs in turn (workgroup b runs on XCD
 // b mod kXcds).  The launchers round the number of m values up to a multiple
-// of kXcds and give the k-th workgroup of XCD x the m value
-// kXcds * (k / parts) + x and the part k % parts, so that the parts (slot tiles
-// or groups) of one m run on one XCD at about the same time and share its L2
-// for the m-column of the coefficient tables; m still ascends in launch order.
+// of kMBlock * kXcds, and the k-th workgroup of XCD x takes part k % parts of
+// the m value 64 j + 8 x' + r, with (j, r, part) counted out of k (r fastest
+// after the part) and x' = x on even j, 7 - x on odd j.  So the parts (slot
+// tiles or groups) of one m share one XCD's L2 for its coefficient column,
+// the 8 consecutive m whose entries fill one 128-byte line of a Delta row are
+// written (read) through the same L2, m still ascends in launch order, and
+// the snake order keeps the XCDs' shares of the work equal.
 constexpr int kXcds = 8;
+constexpr int kMBlock = 8;  // m values per 128-byte line of a Delta row
 struct MPart {
     int m, part;
 };
 __device__ __forceinline__ MPart xcd_m_part(int parts) {
     const int x = blockIdx.x % kXcds, k = blockIdx.x / kXcds;
-    return {kXcds * (k / parts) + x, k % parts};
+    const int per = kMBlock * parts;
+    const int j = k / per, rem = k - j * per;
+    const int xs = (j & 1) ? kXcds - 1 - x : x;
+    return {(j * kXcds + xs) * kMBlock + rem / parts, rem % parts};
 }
 
 // One load from each of the first kBlock 128-byte lines of p[stride * i],
@@ -194,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_leg_syn(int lmax, int mmax, int nslo
                                                     double2 *__restrict__ delta) {
     const MPart mp = xcd_m_part(tiles);
     const int m = mp.m, tile = mp.part;
-    if (m > mmax) return;  // padding of the m range to a multiple of kXcds
+    if (m > mmax) return;  // padding of the m range
     const int map = blockIdx.y;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;  // (l, m) lives at base + l
     const double2 *__restrict__ a = ap + (int64_t)map * nalm + base;
@@ -399,7 +406,7 @@ __global__ __launch_bounds__(kAnaThreads) void k_leg_ana(int lmax, int mmax, int
     static_assert(kFlush * kVals <= kAnaThreads, "one thread per flushed value");
     const MPart mp = xcd_m_part(groups);
     const int m = mp.m, grp = mp.part;
-    if (m > mmax) return;  // padding of the m range to a multiple of kXcds (before any barrier)
+    if (m > mmax) return;  // padding of the m range (before any barrier)
     const int map = blockIdx.y;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
@@ -559,8 +566,11 @@ __global__ __launch_bounds__(kBlock) void k_ana_combine(int64_t nalm, int lmax, 
 }  // namespace
 
 static int grid_ok(int64_t n) { return n > 0 && n < (int64_t)INT32_MAX; }
-// number of m values launched: mmax + 1 rounded up to a multiple of kXcds
-static int64_t padded_m(int mmax) { return ((int64_t)mmax + kXcds) / kXcds * kXcds; }
+// number of m values launched: mmax + 1 rounded up to a multiple of kMBlock * kXcds
+static int64_t padded_m(int mmax) {
+    constexpr int64_t q = (int64_t)kMBlock * kXcds;
+    return ((int64_t)mmax + q) / q * q;
+}
 
 int launch_leg_start(const CoefTables &c, const GeomPlan &p, int32_t *lstart, void *state, hipStream_t st) {
     const int tiles = (p.nslots + kBlock - 1) / kBlock;
@@ -580,7 +590,7 @@ int launch_prescale(const CoefTables &c, const void *alm, void *aprime, int nmap
     return SHT_OK;
 }
 
-constexpr int kSynSlotsPerLane = 2;
+constexpr int kSynSlotsPerLane = 4;
 
 int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *aprime, void *delta,
                    int nmaps, hipStream_t st) {

@@ -14,7 +14,7 @@
 //   Delta^S_m = w_r e^{-i m phi0} S_{m mod N},  S = FFT_forward(s).
 //
 // The FFT is an in-place Stockham decimation-in-time over the radices of the
-// length (4, 2, 3, 5); each stage reads its butterflies into registers,
+// length (8, 4, 2, 3, 5); each stage reads its butterflies into registers,
 // synchronises, and writes them back.  Lengths with a larger prime factor use
 // Bluestein's chirp-z identity
 //   X_k = conj(b_k) sum_n (x_n conj(b_n)) b_{k-n},  b_t = e^{i pi t^2/N},
@@ -88,9 +88,10 @@ __device__ __forceinline__ double2 phase_exp(int m, double phi0) {
     return make_double2(cs, sn);
 }
 
-// Forward-sign butterflies of radix 2, 3, 4, 5 in registers, with the roots
-// of unity as constants: cos(2pi/5) = (sqrt5-1)/4, cos(4pi/5) = -(sqrt5+1)/4,
-// sin(2pi/5), sin(4pi/5) and sqrt(3)/2, each rounded to double.
+// Forward-sign butterflies of radix 2, 3, 4, 5, 8 in registers, with the
+// roots of unity as constants: cos(2pi/5) = (sqrt5-1)/4, cos(4pi/5) =
+// -(sqrt5+1)/4, sin(2pi/5), sin(4pi/5), sqrt(3)/2 and 1/sqrt(2), each rounded
+// to double.
 __device__ __forceinline__ double2 add2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 sub2(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
 // a - i b and a + i b
@@ -118,6 +119,25 @@ __device__ __forceinline__ void butterfly(double2 (&v)[R]) {
         v[2] = sub2(s0, s2);
         v[1] = sub_i(s1, s3);
         v[3] = add_i(s1, s3);
+    } else if constexpr (R == 8) {
+        // pairs (n, n+4), then the odd half turned by W8^n, then two radix-4 DFTs
+        const double kR = 0.70710678118654752;  // 1/sqrt(2)
+        double2 a[4], b[4];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            a[n] = add2(v[n], v[n + 4]);
+            b[n] = sub2(v[n], v[n + 4]);
+        }
+        b[1] = make_double2((b[1].x + b[1].y) * kR, (b[1].y - b[1].x) * kR);
+        b[2] = make_double2(b[2].y, -b[2].x);
+        b[3] = make_double2((b[3].y - b[3].x) * kR, -(b[3].x + b[3].y) * kR);
+        butterfly<4>(a);
+        butterfly<4>(b);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[2 * k] = a[k];
+            v[2 * k + 1] = b[k];
+        }
     } else if constexpr (R == 5) {
         const double kC1 = 0.30901699437494745, kC2 = -0.8090169943749475;
         const double kS1 = 0.9510565162951535, kS2 = 0.5877852522924731;
@@ -142,6 +162,11 @@ __device__ __forceinline__ void butterfly(double2 (&v)[R]) {
 // one extra complex product per twiddle (about one more rounding) instead of
 // a global load in every stage.
 constexpr int kTwLo = 64;
+// LDS index of point x: one unused slot after every 8 points, so that the
+// strided Stockham writes of the early stages spread over the banks
+__device__ __forceinline__ int pd(int x) { return x + (x >> 3); }
+template <int L>
+constexpr int padded_len() { return L + (L >> 3); }
 template <int MAXL>
 constexpr int tw_entries() { return kTwLo + (MAXL + kTwLo - 1) / kTwLo; }
 
@@ -182,7 +207,7 @@ __device__ __forceinline__ void fft_stage(double2 *buf, int L, int Ns, TwLds tw)
             const int k = j - jq * Ns;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const double2 xv = buf[j + r * nbf];
+                const double2 xv = buf[pd(j + r * nbf)];
                 v[b][r] = (r == 0) ? xv : cmul(xv, tw(r * k * tstep));
             }
             butterfly<R>(v[b]);
@@ -197,7 +222,7 @@ __device__ __forceinline__ void fft_stage(double2 *buf, int L, int Ns, TwLds tw)
             const int k = j - jq * Ns;
             const int o = jq * Ns * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[o + r * Ns] = v[b][r];
+            for (int r = 0; r < R; ++r) buf[pd(o + r * Ns)] = v[b][r];
         }
     }
     __syncthreads();
@@ -211,6 +236,7 @@ __device__ __forceinline__ void fft_forward(double2 *buf, const FftDesc *__restr
     for (int s = 0; s < nrad; ++s) {
         const int R = d->rad[s];
         switch (R) {
+            case 8: fft_stage<8, MAXL, NT>(buf, L, Ns, tw); break;
             case 4: fft_stage<4, MAXL, NT>(buf, L, Ns, tw); break;
             case 2: fft_stage<2, MAXL, NT>(buf, L, Ns, tw); break;
             case 3: fft_stage<3, MAXL, NT>(buf, L, Ns, tw); break;
@@ -230,18 +256,18 @@ __device__ __forceinline__ void transform(double2 *buf, const FftDesc *__restric
     }
     const int L = d->L;
     const double2 *kern = d->kern;
-    for (int t = d->n + threadIdx.x; t < L; t += NT) buf[t] = make_double2(0.0, 0.0);
+    for (int t = d->n + threadIdx.x; t < L; t += NT) buf[pd(t)] = make_double2(0.0, 0.0);
     __syncthreads();
     fft_forward<MAXL, NT>(buf, d, tw);
-    for (int t = threadIdx.x; t < L; t += NT) buf[t] = conj2(cmul(buf[t], kern[t]));
+    for (int t = threadIdx.x; t < L; t += NT) buf[pd(t)] = conj2(cmul(buf[pd(t)], kern[t]));
     __syncthreads();
     fft_forward<MAXL, NT>(buf, d, tw);
 }
 
 __device__ __forceinline__ double2 result_at(const double2 *buf, const FftDesc *__restrict__ d, int k) {
-    if (!d->bluestein) return buf[k];
+    if (!d->bluestein) return buf[pd(k)];
     // X_k = conj(b_k) * conj(y_k), y = conj(second transform)
-    return conj2(cmul(d->chirp[k], buf[k]));
+    return conj2(cmul(d->chirp[k], buf[pd(k)]));
 }
 
 __device__ __forceinline__ double2 input_point(double2 v, const FftDesc *__restrict__ d, int t) {
@@ -347,7 +373,7 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t np
     int lim = mmax;  // last index of the phased-term rows that the bins fold
     if (lds_fold) {
         // all threads evaluate phases; short rings first sum the rows in columns
-        double2 *ta = buf + L, *tb = buf + L + (mmax + 1);
+        double2 *ta = buf + pd(L), *tb = buf + pd(L) + (mmax + 1);
         phased_terms<NT>(Da, mmax, pa, ta);
         if (rb >= 0) phased_terms<NT>(Db, mmax, pb, tb);
         __syncthreads();
@@ -362,7 +388,7 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t np
         const int kn = (N - k) % N;
         double2 a0, a1, b0 = make_double2(0.0, 0.0), b1 = make_double2(0.0, 0.0);
         if (lds_fold) {
-            const double2 *ta = buf + L, *tb = buf + L + (mmax + 1);
+            const double2 *ta = buf + pd(L), *tb = buf + pd(L) + (mmax + 1);
             a0 = fold_terms(ta, k, N, lim);
             a1 = fold_terms(ta, kn, N, lim);
             if (rb >= 0) {
@@ -383,8 +409,8 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t np
         // g = h_a + i h_b; the transform input is conj(g)
         const double2 gk = make_double2(ha.x - hb.y, ha.y + hb.x);
         const double2 gn = make_double2(ha.x + hb.y, -ha.y + hb.x);  // h_a* + i h_b* at n-k
-        buf[k] = input_point(conj2(gk), d, k);
-        if (kn != k) buf[kn] = input_point(conj2(gn), d, kn);
+        buf[pd(k)] = input_point(conj2(gk), d, k);
+        if (kn != k) buf[pd(kn)] = input_point(conj2(gn), d, kn);
     }
     __syncthreads();
     transform<MAXL, NT>(buf, d, TwLds{tlo, thi});
@@ -418,7 +444,7 @@ __global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t np
     const double *ina = map + (int64_t)mp * npix + ofs[ra];
     const double *inb = map + (int64_t)mp * npix + (rb >= 0 ? ofs[rb] : 0);
     for (int j = threadIdx.x; j < N; j += NT)
-        buf[j] = input_point(make_double2(ina[j], rb >= 0 ? inb[j] : 0.0), d, j);
+        buf[pd(j)] = input_point(make_double2(ina[j], rb >= 0 ? inb[j] : 0.0), d, j);
     __syncthreads();
     transform<MAXL, NT>(buf, d, TwLds{tlo, thi});
     const double pa = phi0[ra], wa = weight[ra];
@@ -471,13 +497,13 @@ int set_lds_attr() {
     return SHT_OK;
 }
 
-static_assert((tw_entries<kMaxFftLen>() + kMaxFftLen) * sizeof(double2) <= kMaxLds, "largest class fits LDS");
+static_assert((tw_entries<kMaxFftLen>() + padded_len<kMaxFftLen>()) * sizeof(double2) <= kMaxLds, "largest class fits LDS");
 
 template <int MAXL>
 int launch_syn_class(const GeomPlan &p, int c, int mmax, const void *delta, double *map, int nmaps,
                      hipStream_t st) {
     constexpr int NT = fft_threads<MAXL>();
-    const size_t base = (size_t)(tw_entries<MAXL>() + std::min(MAXL, p.max_L)) * sizeof(double2);
+    const size_t base = (size_t)(tw_entries<MAXL>() + padded_len<MAXL>()) * sizeof(double2);
     const size_t rows = 2 * (size_t)(mmax + 1) * sizeof(double2);
     // the small-length class keeps the phased terms in LDS when they fit
     const int fold_rows = (MAXL <= 1024 && base + rows <= kMaxLds) ? 1 : 0;
@@ -492,7 +518,7 @@ template <int MAXL>
 void launch_ana_class(const GeomPlan &p, int c, int mmax, const double *map, void *delta, int nmaps,
                       hipStream_t st) {
     constexpr int NT = fft_threads<MAXL>();
-    const size_t lds = (size_t)(tw_entries<MAXL>() + std::min(MAXL, p.max_L)) * sizeof(double2);
+    const size_t lds = (size_t)(tw_entries<MAXL>() + padded_len<MAXL>()) * sizeof(double2);
     hipLaunchKernelGGL((k_fft_ana<MAXL, NT>), dim3((unsigned)p.class_count[c], (unsigned)nmaps), dim3(NT), lds,
                        st, mmax, p.nrings, p.npix, p.class_jobs[c], p.ring_desc, p.descs, p.phi0, p.weight,
                        p.ofs, map, static_cast<double2 *>(delta));

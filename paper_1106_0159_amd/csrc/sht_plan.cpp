@@ -173,6 +173,7 @@ static const long double kPiL = 3.141592653589793238462643383279502884L;
 
 static bool factor_small(int n, std::vector<int> &rad) {
     rad.clear();
+    while (n % 8 == 0) { rad.push_back(8); n /= 8; }
     while (n % 4 == 0) { rad.push_back(4); n /= 4; }
     while (n % 2 == 0) { rad.push_back(2); n /= 2; }
     for (int p : {3, 5}) {

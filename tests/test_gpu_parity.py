@@ -77,6 +77,9 @@ SMALL_CASES = [
                                       np.ones(6), "poles"), 12, 12),
     ("gl_bluestein", lambda: si.gauss_legendre(70, 139), 69, 69),   # 139 is prime
     ("gl_radix13", lambda: si.gauss_legendre(40, 2 * 3 * 5 * 7 * 11 * 13 // 30), 39, 39),
+    # more than 2048 unpaired rings: analysis needs two slot groups (partial a_lm
+    # summed by the combine kernel); synthesis a ragged fifth tile
+    ("random_many", lambda: random_geometry(2300, 11, nphi_max=12), 24, 24),
 ]
 
 
