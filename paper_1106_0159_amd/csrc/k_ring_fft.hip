@@ -467,9 +467,11 @@ __global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t np
     }
 }
 
-// threads per workgroup for each length class: about four points per thread
+// threads per workgroup for each length class: four points per thread up to
+// 2048 points, eight (one radix-8 butterfly) above, so that two 4096-point
+// workgroups fit a CU's registers
 template <int MAXL>
-constexpr int fft_threads() { return MAXL / 4 < 1024 ? MAXL / 4 : 1024; }
+constexpr int fft_threads() { return MAXL <= 2048 ? MAXL / 4 : MAXL / 8; }
 
 constexpr int kMaxLds = 160 * 1024;  // LDS bytes per workgroup on gfx950
 
@@ -529,16 +531,25 @@ static_assert(kFftClasses == 4 && kFftClassLen[0] == 1024 && kFftClassLen[3] == 
 
 }  // namespace
 
+// The length classes are independent: they run concurrently, the largest on
+// the caller's stream and the others on side streams (fork_join).
 int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, double *map, int nmaps, hipStream_t st) {
     if (nmaps > 65535) return SHT_EUNSUPPORTED;
     int rc = set_lds_attr();
     if (rc) return rc;
-    if (p.class_count[0] && (rc = launch_syn_class<1024>(p, 0, mmax, delta, map, nmaps, st))) return rc;
-    if (p.class_count[1] && (rc = launch_syn_class<2048>(p, 1, mmax, delta, map, nmaps, st))) return rc;
-    if (p.class_count[2] && (rc = launch_syn_class<4096>(p, 2, mmax, delta, map, nmaps, st))) return rc;
-    if (p.class_count[3] && (rc = launch_syn_class<8192>(p, 3, mmax, delta, map, nmaps, st))) return rc;
-    SHT_HIP(hipGetLastError());
-    return SHT_OK;
+    int cls[kFftClasses], n = 0;
+    for (int c = kFftClasses - 1; c >= 0; --c)
+        if (p.class_count[c]) cls[n++] = c;
+    return fork_join(st, n, [&](int i, hipStream_t s) {
+        switch (cls[i]) {
+            case 0: launch_syn_class<1024>(p, 0, mmax, delta, map, nmaps, s); break;
+            case 1: launch_syn_class<2048>(p, 1, mmax, delta, map, nmaps, s); break;
+            case 2: launch_syn_class<4096>(p, 2, mmax, delta, map, nmaps, s); break;
+            default: launch_syn_class<8192>(p, 3, mmax, delta, map, nmaps, s); break;
+        }
+        SHT_HIP(hipGetLastError());
+        return SHT_OK;
+    });
 }
 
 int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, int nmaps, hipStream_t st) {
@@ -546,12 +557,19 @@ int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, 
     if (!p.weight) return SHT_EINVAL;
     int rc = set_lds_attr();
     if (rc) return rc;
-    if (p.class_count[0]) launch_ana_class<1024>(p, 0, mmax, map, delta, nmaps, st);
-    if (p.class_count[1]) launch_ana_class<2048>(p, 1, mmax, map, delta, nmaps, st);
-    if (p.class_count[2]) launch_ana_class<4096>(p, 2, mmax, map, delta, nmaps, st);
-    if (p.class_count[3]) launch_ana_class<8192>(p, 3, mmax, map, delta, nmaps, st);
-    SHT_HIP(hipGetLastError());
-    return SHT_OK;
+    int cls[kFftClasses], n = 0;
+    for (int c = kFftClasses - 1; c >= 0; --c)
+        if (p.class_count[c]) cls[n++] = c;
+    return fork_join(st, n, [&](int i, hipStream_t s) {
+        switch (cls[i]) {
+            case 0: launch_ana_class<1024>(p, 0, mmax, map, delta, nmaps, s); break;
+            case 1: launch_ana_class<2048>(p, 1, mmax, map, delta, nmaps, s); break;
+            case 2: launch_ana_class<4096>(p, 2, mmax, map, delta, nmaps, s); break;
+            default: launch_ana_class<8192>(p, 3, mmax, map, delta, nmaps, s); break;
+        }
+        SHT_HIP(hipGetLastError());
+        return SHT_OK;
+    });
 }
 
 }  // namespace sht

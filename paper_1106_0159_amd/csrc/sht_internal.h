@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -129,6 +130,13 @@ int get_coef(int lmax, int mmax, const CoefTables **out);
 int get_geom(const HostGeom &hg, int mmax_for_fft, const GeomPlan **out);
 // Start table of (c, p), built on the stream st and waited for on first use.
 int get_start(const CoefTables &c, const GeomPlan &p, hipStream_t st, const StartTable **out);
+
+// Runs launch(i, stream_i) for i < n (n <= kSideStreams + 1): piece 0 on st,
+// the others on the library's side streams of the current device (default
+// priority), each ordered after the work already enqueued on st; st then
+// waits for all of them, so the caller sees one ordered stream.
+constexpr int kSideStreams = 3;
+int fork_join(hipStream_t st, int n, const std::function<int(int, hipStream_t)> &launch);
 
 void set_hip_error(hipError_t e, const char *where);
 #define SHT_HIP(call)                                        \

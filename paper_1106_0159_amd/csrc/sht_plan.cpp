@@ -521,6 +521,55 @@ int get_start(const CoefTables &c, const GeomPlan &pc, hipStream_t st, const Sta
     return SHT_OK;
 }
 
+// ------------------------------------------------------------------ side streams
+struct SideStreams {
+    hipStream_t s[kSideStreams] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSideStreams] = {};
+};
+static std::mutex g_side_mu;
+static std::map<int, std::unique_ptr<SideStreams>> g_side;  // by device
+
+static void free_side(SideStreams &p) {
+    for (int i = 0; i < kSideStreams; ++i) {
+        if (p.s[i]) (void)hipStreamDestroy(p.s[i]);
+        if (p.join[i]) (void)hipEventDestroy(p.join[i]);
+    }
+    if (p.fork) (void)hipEventDestroy(p.fork);
+}
+
+int fork_join(hipStream_t st, int n, const std::function<int(int, hipStream_t)> &launch) {
+    if (n <= 1) return n == 1 ? launch(0, st) : SHT_OK;
+    if (n > kSideStreams + 1) return SHT_EUNSUPPORTED;
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc) return rc;
+    // one caller at a time per process: the fork and join events are shared
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    auto &p = g_side[dev];
+    if (!p) {
+        auto q = std::make_unique<SideStreams>();
+        bool ok = hipEventCreateWithFlags(&q->fork, hipEventDisableTiming) == hipSuccess;
+        for (int i = 0; ok && i < kSideStreams; ++i)
+            ok = hipStreamCreateWithFlags(&q->s[i], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&q->join[i], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            free_side(*q);
+            return SHT_EDEVICE;
+        }
+        p = std::move(q);
+    }
+    SHT_HIP(hipEventRecord(p->fork, st));
+    for (int i = 1; i < n; ++i) SHT_HIP(hipStreamWaitEvent(p->s[i - 1], p->fork, 0));
+    for (int i = 0; i < n && rc == SHT_OK; ++i) rc = launch(i, i == 0 ? st : p->s[i - 1]);
+    // join even after a failed launch, so that st never runs ahead of side work
+    for (int i = 1; i < n; ++i) {
+        SHT_HIP(hipEventRecord(p->join[i - 1], p->s[i - 1]));
+        SHT_HIP(hipStreamWaitEvent(st, p->join[i - 1], 0));
+    }
+    return rc;
+}
+
 void shutdown_all() {
     std::lock_guard<std::mutex> lk(g_mu);
     (void)hipDeviceSynchronize();
@@ -532,6 +581,9 @@ void shutdown_all() {
     for (auto &kv : g_fft)
         for (void *p : kv.second->owned) (void)hipFree(p);
     g_fft.clear();
+    std::lock_guard<std::mutex> lk2(g_side_mu);
+    for (auto &kv : g_side) free_side(*kv.second);
+    g_side.clear();
 }
 
 }  // namespace sht
