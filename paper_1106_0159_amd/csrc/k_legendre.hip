@@ -189,7 +189,7 @@ __device__ __forceinline__ int wave_max(int v) {
 
 // Synthesis: lane i of tile t owns slots (t*256 + i)*T + u, u < T.
 template <int T>
-__global__ __launch_bounds__(kBlock) void k_leg_syn(int lmax, int mmax, int nslots, int tiles,
+__global__ __launch_bounds__(kBlock, 4) void k_leg_syn(int lmax, int mmax, int nslots, int tiles,
                                                     int nrings, int64_t nalm,
                                                     const double2 *__restrict__ ap,
                                                     const double *__restrict__ alpha,
