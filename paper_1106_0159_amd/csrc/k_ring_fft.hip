@@ -160,7 +160,9 @@ __device__ __forceinline__ void butterfly(double2 (&v)[R]) {
 // W_L^t = hi[t / 64] * lo[t % 64] with hi[h] = W_L^{64 h} and lo[u] = W_L^u,
 // both copied from the plan's correctly rounded table once per workgroup:
 // one extra complex product per twiddle (about one more rounding) instead of
-// a global load in every stage.
+// a global load in every stage.  A radix-R butterfly takes W^{k tstep} from
+// the tables and its other twiddles as powers of it (at most R - 2 further
+// products, a few ulp for R <= 8).
 constexpr int kTwLo = 64;
 // LDS index of point x: one unused slot after every 8 points, so that the
 // strided Stockham writes of the early stages spread over the banks
@@ -205,10 +207,18 @@ __device__ __forceinline__ void fft_stage(double2 *buf, int L, int Ns, TwLds tw)
         if (j < nbf) {
             const int jq = (int)(((float)j + 0.5f) * inv_ns);
             const int k = j - jq * Ns;
+            // twiddles W^{r k tstep} as powers of W^{k tstep}
+            const double2 w1 = tw(k * tstep);
+            double2 wr = w1;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
                 const double2 xv = buf[pd(j + r * nbf)];
-                v[b][r] = (r == 0) ? xv : cmul(xv, tw(r * k * tstep));
+                if (r == 0) {
+                    v[b][r] = xv;
+                } else {
+                    v[b][r] = cmul(xv, wr);
+                    if (r + 1 < R) wr = cmul(wr, w1);
+                }
             }
             butterfly<R>(v[b]);
         }
