@@ -485,46 +485,12 @@ __global__ __launch_bounds__(kAnaThreads) void k_leg_ana(int lmax, int mmax, int
     const int lane_w = (lane >> 4) * kQStride + (lane & 15);  // this lane's column in tbuf
     int par = 0, kc = 0, lbase = l0s;
     double cval = cfac_for(lbase);
-    for (int l0 = l0s; l0 <= lmax; l0 += kChunk) {
-        double accr[kChunk], acci[kChunk];
-        if (l0 < lo) {
-            // no slot of this wave has started
-#pragma unroll
-            for (int i = 0; i < kChunk; ++i) accr[i] = acci[i] = 0.0;
-        } else {
-            if (l0 <= hi) {
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    if (ls[t] == l0) {
-                        q2[t] = st[t].x;
-                        q1[t] = st[t].y;
-                    }
-                }
-            }
-            if (l0 + kChunk - 1 <= lmax)
-                ana_chunk<T, true>(l0, lmax, av, x, q1, q2, pr, pi, mr, mi, accr, acci);
-            else
-                ana_chunk<T, false>(l0, lmax, av, x, q1, q2, pr, pi, mr, mi, accr, acci);
-        }
-        // wave sum: each lane writes its 16 values as one column of the wave's
-        // rows; lane (j = lane/4, q = lane%4) adds lanes 16q..16q+15 of row j,
-        // and the quad of lanes 4j..4j+3 combines by DPP (lane 4j holds the sum)
-#pragma unroll
-        for (int i = 0; i < kChunk; ++i) {
-            tbuf[wave][2 * i][lane_w] = accr[i];
-            tbuf[wave][2 * i + 1][lane_w] = acci[i];
-        }
-        __builtin_amdgcn_wave_barrier();
-        {
-            const int j = lane >> 2, q = lane & 3;
-            const double *row = &tbuf[wave][j][q * kQStride];
-            double v = row[0];
-#pragma unroll
-            for (int k = 1; k < 16; ++k) v += row[k];
-            v = quad_sum(v);
-            if (q == 0) ring[par][kc][wave][j] = v;
-        }
-        __builtin_amdgcn_wave_barrier();
+
+    // After each chunk: the wave's sums go to the ring buffer, the alpha
+    // registers advance, and every kFlush chunks (or at the last) the four
+    // waves' sums are added and written.  Every wave runs this once per chunk
+    // from l0s on, whichever phase below it is in, so the barriers match.
+    auto next_chunk = [&](int l0) {
 #pragma unroll
         for (int i = 0; i < kChunk; ++i) {
             av[i] = avn[i];
@@ -539,6 +505,60 @@ __global__ __launch_bounds__(kAnaThreads) void k_leg_ana(int lmax, int mmax, int
             par ^= 1;
             kc = 0;
         }
+    };
+    // wave sum: each lane writes its 16 values as one column of the wave's
+    // rows; lane (j = lane/4, q = lane%4) adds lanes 16q..16q+15 of row j,
+    // and the quad of lanes 4j..4j+3 combines by DPP (lane 4j holds the sum)
+    auto wave_sum = [&](const double (&accr)[kChunk], const double (&acci)[kChunk]) {
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) {
+            tbuf[wave][2 * i][lane_w] = accr[i];
+            tbuf[wave][2 * i + 1][lane_w] = acci[i];
+        }
+        __builtin_amdgcn_wave_barrier();
+        const int j = lane >> 2, q = lane & 3;
+        const double *row = &tbuf[wave][j][q * kQStride];
+        double v = row[0];
+#pragma unroll
+        for (int k = 1; k < 16; ++k) v += row[k];
+        v = quad_sum(v);
+        if (q == 0) ring[par][kc][wave][j] = v;
+        __builtin_amdgcn_wave_barrier();
+    };
+    auto inject = [&](int l0) {
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const bool now = (ls[t] == l0);
+            q2[t] = now ? st[t].x : q2[t];
+            q1[t] = now ? st[t].y : q1[t];
+        }
+    };
+
+    // Three phases, each a loop without branches between chunk kinds, so the
+    // recurrence registers stay in place from chunk to chunk:
+    // (1) no slot of this wave has started: zero sums, no transpose
+    int l0 = l0s;
+#pragma unroll 1
+    for (; l0 < lo && l0 <= lmax; l0 += kChunk) {
+        if ((lane & 3) == 0) ring[par][kc][wave][lane >> 2] = 0.0;
+        next_chunk(l0);
+    }
+    // (2) whole chunks; slots join at their tabulated start
+#pragma unroll 1
+    for (; l0 + kChunk - 1 <= lmax; l0 += kChunk) {
+        if (l0 <= hi) inject(l0);
+        double accr[kChunk], acci[kChunk];
+        ana_chunk<T, true>(l0, lmax, av, x, q1, q2, pr, pi, mr, mi, accr, acci);
+        wave_sum(accr, acci);
+        next_chunk(l0);
+    }
+    // (3) the ragged last chunk
+    if (l0 <= lmax) {
+        if (l0 <= hi) inject(l0);
+        double accr[kChunk], acci[kChunk];
+        ana_chunk<T, false>(l0, lmax, av, x, q1, q2, pr, pi, mr, mi, accr, acci);
+        wave_sum(accr, acci);
+        next_chunk(l0);
     }
 }
 
