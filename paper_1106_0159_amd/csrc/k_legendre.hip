@@ -276,31 +276,41 @@ __global__ __launch_bounds__(kBlock, 4) void k_leg_syn(int lmax, int mmax, int n
     // l is uniform; restate it so that the compiler does not carry the lane
     // value it equals inside inject() into the loops below
     l = __builtin_amdgcn_readfirstlane(l);
-    // every started slot is running: four steps per iteration, the next
-    // iteration's coefficients loaded one ahead
-    if (l + 3 <= lmax) {
-        double a0 = al[l], a1 = al[l + 1], a2 = al[l + 2], a3 = al[l + 3];
-        double2 c0 = a[l], c1 = a[l + 1], c2 = a[l + 2], c3 = a[l + 3];
-        for (;;) {
-            const bool more = (l + 7 <= lmax);
-            double n0 = 0, n1 = 0, n2 = 0, n3 = 0;
-            double2 d0 = c0, d1 = c1, d2 = c2, d3 = c3;
-            if (more) {
-                n0 = al[l + 4]; n1 = al[l + 5]; n2 = al[l + 6]; n3 = al[l + 7];
-                d0 = a[l + 4]; d1 = a[l + 5]; d2 = a[l + 6]; d3 = a[l + 7];
+    // every started slot is running: pairs of four-step halves with two
+    // coefficient sets in turn, each loaded one half ahead (a and alpha are
+    // padded, so the loads past lmax stay in bounds); the trip count is fixed
+    // up front so that no exit separates a load from its use
+    if (l + 7 <= lmax) {
+        auto load4 = [&](int l4, double (&av)[4], double2 (&cv)[4]) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                av[i] = al[l4 + i];
+                cv[i] = a[l4 + i];
             }
-            rec(a0);
-            acc_e(c0);
-            rec(a1);
-            acc_o(c1);
-            rec(a2);
-            acc_e(c2);
-            rec(a3);
-            acc_o(c3);
-            l += 4;
-            if (!more) break;
-            a0 = n0; a1 = n1; a2 = n2; a3 = n3;
-            c0 = d0; c1 = d1; c2 = d2; c3 = d3;
+            // compiler-only fence: keeps the loads here instead of letting
+            // them sink to their first use in the next half
+            asm volatile("" ::: "memory");
+        };
+        auto step4 = [&](const double (&av)[4], const double2 (&cv)[4]) {
+            rec(av[0]);
+            acc_e(cv[0]);
+            rec(av[1]);
+            acc_o(cv[1]);
+            rec(av[2]);
+            acc_e(cv[2]);
+            rec(av[3]);
+            acc_o(cv[3]);
+        };
+        const int npairs = (lmax + 1 - l) / 8;
+        double avA[4], avB[4];
+        double2 cvA[4], cvB[4];
+        load4(l, avA, cvA);
+        for (int b = 0; b < npairs; ++b) {
+            load4(l + 4, avB, cvB);
+            step4(avA, cvA);
+            load4(l + 8, avA, cvA);
+            step4(avB, cvB);
+            l += 8;
         }
     }
     for (; l + 1 <= lmax; l += 2) {
