@@ -235,3 +235,99 @@ def test_workspace_too_small_raises(sht):
     with pytest.raises(sht.ShtError) as e:
         sht.alm2map(a, g, 8, ws=ws)
     assert e.value.code == sht.SHT_EWORKSPACE
+
+
+def test_plan_cache_eviction_and_shutdown(sht):
+    """More geometries than the plan cache holds (LRU eviction of plans and
+    their start tables), then sht_shutdown and a fresh start: results stay
+    equal to the oracle throughout."""
+    lmax = 12
+    a = si.uniform_alm(lmax, lmax, 41)
+    geoms = [si.gauss_legendre(13, 25 + k) for k in range(36)]  # 36 distinct plans (cache holds 32)
+    say("plan cache: 36 geometries")
+    for k, g in enumerate(geoms):
+        got = host(sht.alm2map(dev(a), g, lmax))
+        ref = oracle.alm2map(lmax, lmax, g, a)
+        assert relrms(got, ref) <= TOL, k
+    say("plan cache: first geometry again after eviction")
+    got = host(sht.alm2map(dev(a), geoms[0], lmax))
+    assert relrms(got, oracle.alm2map(lmax, lmax, geoms[0], a)) <= TOL
+    say("shutdown and re-initialise")
+    sht.shutdown()
+    got = host(sht.alm2map(dev(a), geoms[1], lmax))
+    assert relrms(got, oracle.alm2map(lmax, lmax, geoms[1], a)) <= TOL
+    s = si.random_map(geoms[2], 42)
+    got = host(sht.map2alm(dev(s), geoms[2], lmax))
+    assert relrms(got, oracle.map2alm(lmax, lmax, geoms[2], s)) <= TOL
+
+
+def test_start_table_serves_smaller_sizes(sht):
+    """A start table built for (lmax, mmax) is reused for smaller lmax and mmax
+    on the same geometry."""
+    g = si.healpix(8)
+    for lmax, mmax in ((30, 30), (20, 20), (30, 12), (17, 5)):
+        a = si.powerlaw_alm(lmax, mmax, 50 + lmax + mmax)
+        say(f"start-table reuse lmax={lmax} mmax={mmax}")
+        got = host(sht.alm2map(dev(a), g, lmax, mmax))
+        assert relrms(got, oracle.alm2map(lmax, mmax, g, a)) <= TOL
+        s = si.random_map(g, 60 + lmax)
+        got = host(sht.map2alm(dev(s), g, lmax, mmax))
+        assert relrms(got, oracle.map2alm(lmax, mmax, g, s)) <= TOL
+
+
+def test_concurrent_host_threads_and_streams(sht):
+    """Two host threads, each on its own stream and geometry, call the library
+    at the same time (plan builds included); each result equals its serial run."""
+    import threading
+    import torch
+    cases = [(si.healpix(16), 40, 71), (si.gauss_legendre(41, 81), 40, 72)]
+    serial = []
+    for g, lmax, seed in cases:
+        a = dev(si.powerlaw_alm(lmax, lmax, seed))
+        serial.append(host(sht.alm2map(a, g, lmax)))
+    sht.shutdown()  # both threads build their plans concurrently
+    out = [None, None]
+    errs = []
+
+    def run(i):
+        try:
+            g, lmax, seed = cases[i]
+            st = torch.cuda.Stream()
+            with torch.cuda.stream(st):
+                a = dev(si.powerlaw_alm(lmax, lmax, seed))
+                for _ in range(3):
+                    m = sht.alm2map(a, g, lmax, stream=st)
+                st.synchronize()
+                out[i] = m.cpu().numpy()
+        except Exception as e:  # reported below
+            errs.append(e)
+
+    say("two host threads")
+    ts = [threading.Thread(target=run, args=(i,)) for i in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join(timeout=120)
+    assert not errs, errs
+    for i in range(2):
+        assert np.array_equal(out[i], serial[i]), i
+
+
+def test_stage_entry_points_several_maps(sht):
+    lmax = 20
+    g = si.healpix(8)
+    al = np.stack([si.uniform_alm(lmax, lmax, 80 + i) for i in range(2)])
+    say("alm2delta / delta2alm with nmaps=2")
+    d = host(sht.alm2delta(dev(al), g, lmax))
+    for i in range(2):
+        assert relrms(d[i], oracle.delta_syn(lmax, lmax, g, al[i])) <= TOL
+    back = host(sht.delta2alm(dev(d), g, lmax))
+    for i in range(2):
+        assert relrms(back[i], oracle.delta2alm(lmax, lmax, g, d[i])) <= TOL
+    say("delta2map / map2delta with nmaps=2")
+    mp = host(sht.delta2map(dev(d), g, lmax))
+    for i in range(2):
+        assert relrms(mp[i], oracle.delta2map(lmax, g, d[i])) <= TOL
+    dd = host(sht.map2delta(dev(mp), g, lmax))
+    for i in range(2):
+        assert relrms(dd[i], oracle.map2delta(lmax, g, mp[i])) <= TOL
