@@ -79,11 +79,12 @@ int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *
     if (overlap(alm, ab, delta, db) || overlap(workspace, ws_bytes, alm, ab) ||
         overlap(workspace, ws_bytes, delta, db))
         return SHT_EINVAL;
-    const CoefTables *c;
-    const GeomPlan *p;
-    if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p))) return rc;
-    const StartTable *s;
-    if ((rc = get_start(*c, *p, as_stream(stream), &s))) return rc;
+    CoefRef c;
+    GeomRef p;
+    StartRef s;
+    if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p)) ||
+        (rc = get_start(*c, p, as_stream(stream), &s)))
+        return rc;
     if ((rc = launch_prescale(*c, alm, workspace, nmaps, as_stream(stream)))) return rc;
     return launch_leg_syn(*c, *p, *s, workspace, delta, nmaps, as_stream(stream));
 }
@@ -96,7 +97,7 @@ int sht_delta2map(int mmax, const sht_geom *g, const void *delta, double *map, i
     if (!delta || !map || !aligned(delta, 16) || !aligned(map, 8)) return SHT_EINVAL;
     if (overlap(delta, delta_bytes(h.nrings, mmax, nmaps), map, (size_t)h.npix * 8u * nmaps))
         return SHT_EINVAL;
-    const GeomPlan *p;
+    GeomRef p;
     if ((rc = get_geom(h, mmax, &p))) return rc;
     return launch_fft_syn(*p, mmax, delta, map, nmaps, as_stream(stream));
 }
@@ -109,7 +110,7 @@ int sht_map2delta(int mmax, const sht_geom *g, const double *map, void *delta, i
     if (!delta || !map || !aligned(delta, 16) || !aligned(map, 8)) return SHT_EINVAL;
     if (overlap(delta, delta_bytes(h.nrings, mmax, nmaps), map, (size_t)h.npix * 8u * nmaps))
         return SHT_EINVAL;
-    const GeomPlan *p;
+    GeomRef p;
     if ((rc = get_geom(h, mmax, &p))) return rc;
     return launch_fft_ana(*p, mmax, map, delta, nmaps, as_stream(stream));
 }
@@ -126,11 +127,11 @@ int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void
     if (overlap(delta, db, alm, ab) || overlap(workspace, ws_bytes, alm, ab) ||
         overlap(workspace, ws_bytes, delta, db))
         return SHT_EINVAL;
-    const CoefTables *c;
-    const GeomPlan *p;
-    const StartTable *s;
+    CoefRef c;
+    GeomRef p;
+    StartRef s;
     if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p)) ||
-        (rc = get_start(*c, *p, as_stream(stream), &s)))
+        (rc = get_start(*c, p, as_stream(stream), &s)))
         return rc;
     return launch_leg_ana(*c, *p, *s, delta, alm, nmaps, workspace, as_stream(stream));
 }
@@ -148,14 +149,14 @@ int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *
     if (overlap(alm, ab, map, mb) || overlap(workspace, ws_bytes, alm, ab) ||
         overlap(workspace, ws_bytes, map, mb))
         return SHT_EINVAL;
-    const CoefTables *c;
-    const GeomPlan *p;
-    if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p))) return rc;
+    hipStream_t st = as_stream(stream);
+    CoefRef c;
+    GeomRef p;
+    StartRef s;
+    if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p)) || (rc = get_start(*c, p, st, &s)))
+        return rc;
     char *ws = static_cast<char *>(workspace);
     void *delta = ws, *aprime = ws + round256(db);
-    hipStream_t st = as_stream(stream);
-    const StartTable *s;
-    if ((rc = get_start(*c, *p, st, &s))) return rc;
     if ((rc = launch_prescale(*c, alm, aprime, nmaps, st))) return rc;
     if ((rc = launch_leg_syn(*c, *p, *s, aprime, delta, nmaps, st))) return rc;
     return launch_fft_syn(*p, mmax, delta, map, nmaps, st);
@@ -174,14 +175,14 @@ int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *
     if (overlap(alm, ab, map, mb) || overlap(workspace, ws_bytes, alm, ab) ||
         overlap(workspace, ws_bytes, map, mb))
         return SHT_EINVAL;
-    const CoefTables *c;
-    const GeomPlan *p;
-    if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p))) return rc;
     hipStream_t st = as_stream(stream);
+    CoefRef c;
+    GeomRef p;
+    StartRef s;
+    if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p)) || (rc = get_start(*c, p, st, &s)))
+        return rc;
     char *ws = static_cast<char *>(workspace);
     void *delta = ws, *partials = ws + round256(db);
-    const StartTable *s;
-    if ((rc = get_start(*c, *p, st, &s))) return rc;
     if ((rc = launch_fft_ana(*p, mmax, map, delta, nmaps, st))) return rc;
     return launch_leg_ana(*c, *p, *s, delta, alm, nmaps, partials, st);
 }

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <functional>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -49,11 +50,17 @@ constexpr int kCoefPad = 32;
 // Coefficient tables for one (lmax, mmax) on one device.  Packed (l, m)
 // index as for a_lm.  p_lm = cfac_lm * q_lm, q_lm = alpha_lm x q_{l-1,m} - q_{l-2,m}.
 struct CoefTables {
+    int dev = -1;             // device holding the tables
     int lmax = -1, mmax = -1;
     int64_t nalm = 0;
     double *alpha = nullptr;  // [nalm + kCoefPad]; alpha at l = m is 0, at l = m+1 sqrt(2m+3)
     double *cfac = nullptr;   // [nalm]
     double *mu = nullptr;     // [mmax+1]
+    std::vector<void *> owned;
+    CoefTables() = default;
+    CoefTables(const CoefTables &) = delete;
+    CoefTables &operator=(const CoefTables &) = delete;
+    ~CoefTables();            // waits for the device, then frees
 };
 
 // One FFT length (device view).  Points of length n are transformed in LDS
@@ -76,14 +83,20 @@ struct FftDesc {
 // does) and state[m * nslots + slot] = (q_{l-2}, q_{l-1}) before that step.
 // A table built for (lmax', mmax') serves every lmax <= lmax', mmax <= mmax'.
 struct StartTable {
+    int dev = -1;
     int lmax = -1, mmax = -1;
     int32_t *lstart = nullptr;
     double2 *state = nullptr;
     uint64_t last_use = 0;
+    StartTable() = default;
+    StartTable(const StartTable &) = delete;
+    StartTable &operator=(const StartTable &) = delete;
+    ~StartTable();            // waits for the device, then frees
 };
 
 // Geometry plan for one (ring set) on one device.
 struct GeomPlan {
+    int dev = -1;
     int nrings = 0;
     int nslots = 0;
     int64_t npix = 0;
@@ -105,10 +118,13 @@ struct GeomPlan {
     int class_count[4] = {0, 0, 0, 0};
     int2 *class_jobs[4] = {nullptr, nullptr, nullptr, nullptr};
     std::vector<void *> owned;       // device allocations to free
-    std::vector<StartTable> starts;  // built on first use by get_start
+    // start tables built on first use by get_start; guarded by the cache lock
+    mutable std::vector<std::shared_ptr<StartTable>> starts;
+    GeomPlan() = default;
+    GeomPlan(const GeomPlan &) = delete;
+    GeomPlan &operator=(const GeomPlan &) = delete;
+    ~GeomPlan();                     // waits for the device, then frees
 };
-
-struct DeviceContext;
 
 // Validated, normalised copy of the caller's geometry.
 struct HostGeom {
@@ -125,11 +141,17 @@ int validate_geom(const sht_geom *g, bool need_weight, HostGeom *out);
 int count_slots(const HostGeom &h);
 int validate_sizes(int lmax, int mmax, int nmaps);
 
-// Plan lookup (builds on first use).  Thread safe.
-int get_coef(int lmax, int mmax, const CoefTables **out);
-int get_geom(const HostGeom &hg, int mmax_for_fft, const GeomPlan **out);
+// Plan lookup (builds on first use).  Thread safe.  A call holds the
+// references for as long as it uses the tables: an entry evicted from a cache
+// meanwhile is freed only when its last reference goes (after waiting for the
+// device, so kernels already enqueued with it finish first).
+using CoefRef = std::shared_ptr<const CoefTables>;
+using GeomRef = std::shared_ptr<const GeomPlan>;
+using StartRef = std::shared_ptr<const StartTable>;
+int get_coef(int lmax, int mmax, CoefRef *out);
+int get_geom(const HostGeom &hg, int mmax_for_fft, GeomRef *out);
 // Start table of (c, p), built on the stream st and waited for on first use.
-int get_start(const CoefTables &c, const GeomPlan &p, hipStream_t st, const StartTable **out);
+int get_start(const CoefTables &c, const GeomRef &p, hipStream_t st, StartRef *out);
 
 // Runs launch(i, stream_i) for i < n (n <= kSideStreams + 1): piece 0 on st,
 // the others on the library's side streams of the current device (default

@@ -93,6 +93,33 @@ static int current_device(int *dev) {
     return SHT_OK;
 }
 
+// Frees device allocations of a table on its device once the device is idle:
+// kernels enqueued by other calls may still read the table.
+static void release_device(int dev, std::vector<void *> &ptrs) {
+    if (ptrs.empty()) return;
+    int cur = -1;
+    (void)hipGetDevice(&cur);
+    if (dev >= 0 && cur != dev) (void)hipSetDevice(dev);
+    (void)hipDeviceSynchronize();
+    for (void *q : ptrs) (void)hipFree(q);
+    ptrs.clear();
+    if (dev >= 0 && cur >= 0 && cur != dev) (void)hipSetDevice(cur);
+}
+
+CoefTables::~CoefTables() { release_device(dev, owned); }
+
+StartTable::~StartTable() {
+    std::vector<void *> v;
+    if (lstart) v.push_back(lstart);
+    if (state) v.push_back(state);
+    release_device(dev, v);
+}
+
+GeomPlan::~GeomPlan() {
+    starts.clear();  // each start table frees itself when its last user is done
+    release_device(dev, owned);
+}
+
 // ------------------------------------------------------------------ coefficient tables
 // For one m: beta_l = sqrt((4l^2-1)/(l^2-m^2)) (eq. betaDef), c_m = c_{m+1} = 1,
 // c_l = (beta_l/beta_{l-1}) c_{l-2}, alpha_l = beta_l c_{l-1}/c_l.  Then
@@ -120,15 +147,19 @@ static void coef_column(int lmax, int m, double *alpha, double *cfac) {
     }
 }
 
+// The caches are created on first use and never destroyed at process exit
+// (their destructors would call into the HIP runtime after it has gone);
+// sht_shutdown empties them.
 struct CoefEntry {
-    CoefTables t;
-    std::vector<void *> owned;
+    std::shared_ptr<CoefTables> t;
+    uint64_t last_use = 0;
 };
-
 static std::mutex g_mu;
-static std::map<std::tuple<int, int, int>, std::unique_ptr<CoefEntry>> g_coef;
+static uint64_t g_clock = 0;
+static auto &g_coef = *new std::map<std::tuple<int, int, int>, CoefEntry>();
+constexpr size_t kMaxCoefTables = 8;
 
-int get_coef(int lmax, int mmax, const CoefTables **out) {
+int get_coef(int lmax, int mmax, CoefRef *out) {
     int dev = 0;
     int rc = current_device(&dev);
     if (rc) return rc;
@@ -136,10 +167,18 @@ int get_coef(int lmax, int mmax, const CoefTables **out) {
     auto key = std::make_tuple(dev, lmax, mmax);
     auto it = g_coef.find(key);
     if (it != g_coef.end()) {
-        *out = &it->second->t;
+        it->second.last_use = ++g_clock;
+        *out = it->second.t;
         return SHT_OK;
     }
-    auto e = std::make_unique<CoefEntry>();
+    if (g_coef.size() >= kMaxCoefTables) {
+        auto lru = std::min_element(g_coef.begin(), g_coef.end(), [](const auto &a, const auto &b) {
+            return a.second.last_use < b.second.last_use;
+        });
+        g_coef.erase(lru);  // freed when its last user is done
+    }
+    auto t = std::make_shared<CoefTables>();
+    t->dev = dev;
     const int64_t na = nalm_of(lmax, mmax);
     std::vector<double> alpha(na), cfac(na), mu(mmax + 1);
     for (int m = 0; m <= mmax; ++m) {
@@ -153,17 +192,15 @@ int get_coef(int lmax, int mmax, const CoefTables **out) {
         v *= sqrtl((long double)(2 * m + 1) / (long double)(2 * m));
         mu[m] = (double)v;
     }
-    e->t.lmax = lmax;
-    e->t.mmax = mmax;
-    e->t.nalm = na;
+    t->lmax = lmax;
+    t->mmax = mmax;
+    t->nalm = na;
     alpha.resize(na + kCoefPad, 0.0);  // kernels may read past the last column
-    if ((rc = upload(alpha, &e->t.alpha, e->owned)) || (rc = upload(cfac, &e->t.cfac, e->owned)) ||
-        (rc = upload(mu, &e->t.mu, e->owned))) {
-        for (void *p : e->owned) (void)hipFree(p);
-        return rc;
-    }
-    *out = &e->t;
-    g_coef[key] = std::move(e);
+    if ((rc = upload(alpha, &t->alpha, t->owned)) || (rc = upload(cfac, &t->cfac, t->owned)) ||
+        (rc = upload(mu, &t->mu, t->owned)))
+        return rc;  // t frees what was uploaded
+    g_coef[key] = CoefEntry{t, ++g_clock};
+    *out = t;
     return SHT_OK;
 }
 
@@ -214,7 +251,7 @@ struct FftCache {
     std::map<int, FftDesc> descs;           // by n
     std::vector<void *> owned;
 };
-static std::map<int, std::unique_ptr<FftCache>> g_fft;  // by device
+static auto &g_fft = *new std::map<int, std::unique_ptr<FftCache>>();  // by device
 
 static int twiddle_table(FftCache &fc, int L, const double2 **out) {
     auto it = fc.twiddles.find(L);
@@ -288,30 +325,15 @@ static int fft_desc(FftCache &fc, int n, FftDesc *out) {
 struct GeomEntry {
     int dev;
     HostGeom key;
-    GeomPlan plan;
+    std::shared_ptr<GeomPlan> plan;
     uint64_t last_use;
 };
-static std::vector<std::unique_ptr<GeomEntry>> g_geom;
-static uint64_t g_clock = 0;
+static auto &g_geom = *new std::vector<GeomEntry>();
 constexpr size_t kMaxGeomPlans = 32;
 
 static bool same_geom(const HostGeom &a, const HostGeom &b) {
     return a.nrings == b.nrings && a.has_weight == b.has_weight && a.theta == b.theta &&
            a.nphi == b.nphi && a.phi0 == b.phi0 && a.ofs == b.ofs && a.weight == b.weight;
-}
-
-static void free_start(StartTable &t) {
-    (void)hipFree(t.lstart);
-    (void)hipFree(t.state);
-    t.lstart = nullptr;
-    t.state = nullptr;
-}
-
-static void free_plan(GeomPlan &p) {
-    for (void *q : p.owned) (void)hipFree(q);
-    p.owned.clear();
-    for (StartTable &t : p.starts) free_start(t);
-    p.starts.clear();
 }
 
 // Mirror pairs: rings r, r' with |theta_r + theta_r' - pi| <= tol share one
@@ -365,35 +387,29 @@ int count_slots(const HostGeom &h) {
     return (int)sx.size();
 }
 
-int get_geom(const HostGeom &hg, int /*mmax_for_fft*/, const GeomPlan **out) {
+int get_geom(const HostGeom &hg, int /*mmax_for_fft*/, GeomRef *out) {
     int dev = 0;
     int rc = current_device(&dev);
     if (rc) return rc;
     std::lock_guard<std::mutex> lk(g_mu);
     for (auto &e : g_geom) {
-        if (e->dev == dev && same_geom(e->key, hg)) {
-            e->last_use = ++g_clock;
-            *out = &e->plan;
+        if (e.dev == dev && same_geom(e.key, hg)) {
+            e.last_use = ++g_clock;
+            *out = e.plan;
             return SHT_OK;
         }
     }
     if (g_geom.size() >= kMaxGeomPlans) {
-        // evict the least recently used plan; kernels using it may be in flight
+        // drop the least recently used plan; it is freed when its last user is done
         auto lru = std::min_element(g_geom.begin(), g_geom.end(),
-                                    [](const auto &a, const auto &b) { return a->last_use < b->last_use; });
-        int cur = dev;
-        SHT_HIP(hipSetDevice((*lru)->dev));
-        SHT_HIP(hipDeviceSynchronize());
-        free_plan((*lru)->plan);
-        SHT_HIP(hipSetDevice(cur));
+                                    [](const GeomEntry &a, const GeomEntry &b) { return a.last_use < b.last_use; });
         g_geom.erase(lru);
     }
     auto &fcp = g_fft[dev];
     if (!fcp) fcp = std::make_unique<FftCache>();
-    auto e = std::make_unique<GeomEntry>();
-    e->dev = dev;
-    e->key = hg;
-    GeomPlan &p = e->plan;
+    auto plan = std::make_shared<GeomPlan>();
+    GeomPlan &p = *plan;  // on an error return below, plan frees what was uploaded
+    p.dev = dev;
     p.nrings = hg.nrings;
     p.npix = hg.npix;
     std::vector<double> sx, ss;
@@ -453,71 +469,53 @@ int get_geom(const HostGeom &hg, int /*mmax_for_fft*/, const GeomPlan **out) {
     for (int c = 0; c < kFftClasses; ++c) {
         p.class_count[c] = (int)cls[c].size();
         if (cls[c].empty()) continue;
-        if ((rc = upload(cls[c], &p.class_jobs[c], p.owned))) {
-            free_plan(p);
-            return rc;
-        }
+        if ((rc = upload(cls[c], &p.class_jobs[c], p.owned))) return rc;
     }
     if ((rc = upload(sx, &p.slot_x, p.owned)) || (rc = upload(ss, &p.slot_s, p.owned)) ||
         (rc = upload(sn, &p.slot_north, p.owned)) || (rc = upload(sso, &p.slot_south, p.owned)) ||
         (rc = upload(hg.phi0, &p.phi0, p.owned)) || (rc = upload(hg.ofs, &p.ofs, p.owned)) ||
-        (rc = upload(ring_desc, &p.ring_desc, p.owned)) || (rc = upload(descs, &p.descs, p.owned))) {
-        free_plan(p);
+        (rc = upload(ring_desc, &p.ring_desc, p.owned)) || (rc = upload(descs, &p.descs, p.owned)))
         return rc;
-    }
-    if (hg.has_weight && (rc = upload(hg.weight, &p.weight, p.owned))) {
-        free_plan(p);
-        return rc;
-    }
-    e->last_use = ++g_clock;
-    *out = &e->plan;
-    g_geom.push_back(std::move(e));
+    if (hg.has_weight && (rc = upload(hg.weight, &p.weight, p.owned))) return rc;
+    g_geom.push_back(GeomEntry{dev, hg, plan, ++g_clock});
+    *out = plan;
     return SHT_OK;
 }
 
 constexpr size_t kMaxStartTables = 4;  // per geometry plan
 
-int get_start(const CoefTables &c, const GeomPlan &pc, hipStream_t st, const StartTable **out) {
+int get_start(const CoefTables &c, const GeomRef &pref, hipStream_t st, StartRef *out) {
     std::lock_guard<std::mutex> lk(g_mu);
-    // plans are owned by the cache; their start list is extended under the lock
-    GeomPlan &p = const_cast<GeomPlan &>(pc);
-    for (StartTable &t : p.starts) {
-        if (t.lmax >= c.lmax && t.mmax >= c.mmax) {
-            t.last_use = ++g_clock;
-            *out = &t;
+    const GeomPlan &p = *pref;  // its start list is only touched under the lock
+    for (const auto &t : p.starts) {
+        if (t->lmax >= c.lmax && t->mmax >= c.mmax) {
+            t->last_use = ++g_clock;
+            *out = t;
             return SHT_OK;
         }
     }
     if (p.starts.size() >= kMaxStartTables) {
-        // evict the least recently used table; kernels using it may be in flight
+        // drop the least recently used table; it is freed when its last user is done
         auto lru = std::min_element(p.starts.begin(), p.starts.end(),
-                                    [](const StartTable &a, const StartTable &b) { return a.last_use < b.last_use; });
-        SHT_HIP(hipDeviceSynchronize());
-        free_start(*lru);
+                                    [](const auto &a, const auto &b) { return a->last_use < b->last_use; });
         p.starts.erase(lru);
     }
-    StartTable t;
-    t.lmax = c.lmax;
-    t.mmax = c.mmax;
+    auto t = std::make_shared<StartTable>();
+    t->dev = p.dev;
+    t->lmax = c.lmax;
+    t->mmax = c.mmax;
     const size_t n = (size_t)(c.mmax + 1) * (size_t)p.nslots;
     void *a = nullptr, *b = nullptr;
     if (hipMalloc(&a, n * sizeof(int32_t)) != hipSuccess) return SHT_ENOMEM;
-    if (hipMalloc(&b, n * sizeof(double2)) != hipSuccess) {
-        (void)hipFree(a);
-        return SHT_ENOMEM;
-    }
-    t.lstart = static_cast<int32_t *>(a);
-    t.state = static_cast<double2 *>(b);
-    int rc = launch_leg_start(c, p, t.lstart, t.state, st);
+    t->lstart = static_cast<int32_t *>(a);
+    if (hipMalloc(&b, n * sizeof(double2)) != hipSuccess) return SHT_ENOMEM;  // t frees lstart
+    t->state = static_cast<double2 *>(b);
+    int rc = launch_leg_start(c, p, t->lstart, t->state, st);
     if (rc == SHT_OK && hipStreamSynchronize(st) != hipSuccess) rc = SHT_EDEVICE;
-    if (rc) {
-        free_start(t);
-        return rc;
-    }
-    t.last_use = ++g_clock;
-    p.starts.reserve(kMaxStartTables);  // pointers handed out stay valid until eviction
+    if (rc) return rc;
+    t->last_use = ++g_clock;
     p.starts.push_back(t);
-    *out = &p.starts.back();
+    *out = t;
     return SHT_OK;
 }
 
@@ -528,7 +526,7 @@ struct SideStreams {
     hipEvent_t join[kSideStreams] = {};
 };
 static std::mutex g_side_mu;
-static std::map<int, std::unique_ptr<SideStreams>> g_side;  // by device
+static auto &g_side = *new std::map<int, std::unique_ptr<SideStreams>>();  // by device
 
 static void free_side(SideStreams &p) {
     for (int i = 0; i < kSideStreams; ++i) {
@@ -573,10 +571,7 @@ int fork_join(hipStream_t st, int n, const std::function<int(int, hipStream_t)> 
 void shutdown_all() {
     std::lock_guard<std::mutex> lk(g_mu);
     (void)hipDeviceSynchronize();
-    for (auto &e : g_geom) free_plan(e->plan);
-    g_geom.clear();
-    for (auto &kv : g_coef)
-        for (void *p : kv.second->owned) (void)hipFree(p);
+    g_geom.clear();  // plans and their start tables free themselves
     g_coef.clear();
     for (auto &kv : g_fft)
         for (void *p : kv.second->owned) (void)hipFree(p);
