@@ -55,10 +55,12 @@ int validate_geom(const sht_geom *g, bool need_weight, HostGeom *out) {
             acc += h.nphi[r];
         }
     }
-    // ring pixel ranges must not overlap
+    // ring pixel ranges must not overlap (checked in offset order; rings are
+    // usually given in that order already, which needs no sort)
     std::vector<int> ord(n);
     for (int r = 0; r < n; ++r) ord[r] = r;
-    std::sort(ord.begin(), ord.end(), [&](int a, int b) { return h.ofs[a] < h.ofs[b]; });
+    if (!std::is_sorted(h.ofs.begin(), h.ofs.end()))
+        std::sort(ord.begin(), ord.end(), [&](int a, int b) { return h.ofs[a] < h.ofs[b]; });
     int64_t npix = 0;
     for (int i = 0; i < n; ++i) {
         const int r = ord[i];
@@ -380,11 +382,24 @@ static void build_slots(const HostGeom &h, std::vector<double> &sx, std::vector<
     }
 }
 
+// The slot count depends on the colatitudes only; the last few results are
+// remembered so that sizing the workspace does not pair the rings each call.
 int count_slots(const HostGeom &h) {
+    static std::mutex mu;
+    static auto &memo = *new std::vector<std::pair<std::vector<double>, int>>();
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const auto &e : memo)
+            if (e.first == h.theta) return e.second;
+    }
     std::vector<double> sx, ss;
     std::vector<int32_t> sn, sso;
     build_slots(h, sx, ss, sn, sso);
-    return (int)sx.size();
+    const int n = (int)sx.size();
+    std::lock_guard<std::mutex> lk(mu);
+    if (memo.size() >= 8) memo.erase(memo.begin());
+    memo.emplace_back(h.theta, n);
+    return n;
 }
 
 int get_geom(const HostGeom &hg, int /*mmax_for_fft*/, GeomRef *out) {
