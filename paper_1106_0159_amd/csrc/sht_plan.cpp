@@ -562,10 +562,13 @@ int fork_join(hipStream_t st, int n, const std::function<int(int, hipStream_t)> 
     auto &p = g_side[dev];
     if (!p) {
         auto q = std::make_unique<SideStreams>();
-        bool ok = hipEventCreateWithFlags(&q->fork, hipEventDisableTiming) == hipSuccess;
+        // the events only order kernels of one device: a device-scope release
+        // suffices (no system-scope fence, which would write back for the host)
+        const unsigned ef = hipEventDisableTiming | hipEventDisableSystemFence;
+        bool ok = hipEventCreateWithFlags(&q->fork, ef) == hipSuccess;
         for (int i = 0; ok && i < kSideStreams; ++i)
             ok = hipStreamCreateWithFlags(&q->s[i], hipStreamNonBlocking) == hipSuccess &&
-                 hipEventCreateWithFlags(&q->join[i], hipEventDisableTiming) == hipSuccess;
+                 hipEventCreateWithFlags(&q->join[i], ef) == hipSuccess;
         if (!ok) {
             free_side(*q);
             return SHT_EDEVICE;
