@@ -5,9 +5,11 @@ One step = one map through both transforms, with inputs resident in HBM:
     map --(ring FFT analysis)--> Delta^S --(Legendre analysis)--> alm'
 called through the four stage entry points of the C ABI (their composition is
 exactly sht_alm2map followed by sht_map2alm), with HIP events on the launch
-stream between stages.  Prints one JSON line.
+stream between stages.  A second leg ("batched_mixed" in the output) runs
+alm2map on a batch of 64 maps with the mixed-precision Legendre contraction.
+Prints one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch N] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -24,9 +26,10 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_FP64_VALU_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz
+PEAK_FP32_MFMA_TFLOPS = 157.3  # dense FP32 matrix-core peak
 PEAK_HBM_GBS = 8000.0
 FLOPS_PER_TRIPLE = 8           # recurrence 4 + complex-by-real contraction 4 per (slot, l, m)
-DOMINANT_SOURCES = ["paper_1106_0159_amd/csrc/k_legendre.hip"]
+DOMINANT_SOURCES = ["paper_1106_0159_amd/csrc/k_legendre.hip", "paper_1106_0159_amd/csrc/k_device.h"]
 
 
 def kernel_source_hash() -> str:
@@ -115,6 +118,70 @@ def cpu_baseline(g, lmax, a, mp, target_s: float = 12.0):
     }
 
 
+def batched_mixed(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64):
+    """alm2map of a batch of power-law maps with SHT_MIXED (FP64 recurrence,
+    FP32 matrix-core contraction), through the two synthesis stage entry
+    points, HIP events on the launch stream around each stage.  Map 0 of the
+    batch is the map of the plain FP64 run; its relative RMS difference to that
+    map is reported."""
+    import numpy as np
+    import torch
+    dev = torch.device("cuda", 0)
+    alm = torch.empty((nmaps, si.nalm(lmax, lmax)), dtype=torch.complex128, device=dev)
+    for i in range(nmaps):
+        alm[i] = torch.from_numpy(si.powerlaw_alm(lmax, lmax, si.config_seed(2, i))).to(dev)
+    delta = torch.empty((nmaps, g.nrings, lmax + 1), dtype=torch.complex128, device=dev)
+    mp = torch.zeros((nmaps, g.npix), dtype=torch.float64, device=dev)
+    ws = sht.workspace(lmax, lmax, gh, nmaps, dev, sht.SHT_MIXED)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        sht.alm2delta(alm, gh, lmax, lmax, out=delta, ws=ws, flags=sht.SHT_MIXED)
+        if ev is not None:
+            ev[1].record()
+        sht.delta2map(delta, gh, lmax, out=mp)
+        if ev is not None:
+            ev[2].record()
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    leg = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
+    fft = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
+    ms = max(wall * 1000.0 / steps, leg + fft)
+    flops = 4 * nmaps * count_triples(nslots, lmax, lmax)  # matrix-core flops of the contraction
+    achieved = flops / (leg * 1e-3) / 1e12
+    d = (mp[0] - mp_fp64).norm().item() / mp_fp64.norm().item()
+    return {
+        "direction": "alm2map",
+        "nmaps": nmaps,
+        "value": nmaps * 1000.0 / ms,
+        "unit": "maps/s",
+        "ms_per_batch": ms,
+        "steps": steps,
+        "stages_ms": {"leg_syn_mx": leg, "fft_syn": fft},
+        "dtype": "f64 recurrence, f32 contraction",
+        "relrms_map0_vs_fp64": d,
+        "roofline": {
+            "kernel": "k_prescale_mx + k_leg_syn_mx",
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": PEAK_FP32_MFMA_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+            "traffic": None,
+            "flops_per_launch": flops,
+        },
+    }
+
+
 def copy_probe(nbytes: int) -> None:
     """A plain device copy of known size, for calibrating HBM byte counters."""
     import torch
@@ -135,6 +202,8 @@ def main():
     ap.add_argument("--nside", type=int, default=1024)
     ap.add_argument("--lmax", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=64,
+                    help="maps in the batched mixed-precision alm2map leg (0: skip it)")
     ap.add_argument("--copy-probe", type=int, default=0, help="run only a device copy of this many bytes")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -242,6 +311,9 @@ def main():
             "executed_tflops": None if executed is None else executed / (stage_ms[dom] * 1e-3) / 1e12,
         },
     }
+    if args.batch > 0:
+        rec["batched_mixed"] = batched_mixed(sht, si, gh, g, lmax, args.batch, max(3, K // 4), args.warmup,
+                                             nslots, mp)
     if not args.no_cpu_baseline:
         mp_np = mp.cpu().numpy()
         rec["cpu_baseline"] = cpu_baseline(g, lmax, a_np, mp_np)

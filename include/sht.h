@@ -75,9 +75,25 @@ enum sht_status {
     SHT_EUNSUPPORTED = -5   /* unknown flag bit, or a size beyond the kernels' limits */
 };
 
+/* Flag bits of the `flags` arguments. */
+enum sht_flags {
+    /* Mixed precision for the Legendre contraction of synthesis (sht_alm2map,
+     * sht_alm2delta; the analysis calls return SHT_EUNSUPPORTED with it, the
+     * ring-FFT calls ignore it).  The recurrence, its seeds, start table and
+     * coefficients stay FP64 (Sec. 2.1); each lambda_lm (in the rescaled form
+     * q_lm = lambda_lm / c_lm) and each c_lm a_lm is rounded to FP32 once, and
+     * the per-m matrix product of Sec. 3 (eq. matrix_vec, with one column per
+     * map and real/imaginary part) is summed over l in FP32 on the matrix
+     * cores.  Expected relative RMS error against the FP64 transform: about
+     * 1e-7 to 1e-6.  Built for batches: one wave covers 8, 16 or 32 maps, so
+     * nmaps >= 8 fills it. */
+    SHT_MIXED = 1u
+};
+
 /* Bytes of device workspace needed by sht_alm2map, sht_map2alm,
- * sht_alm2delta and sht_delta2alm for these arguments (a multiple of 256; the
- * same value serves all four).  Returns 0 if the arguments are invalid. */
+ * sht_alm2delta and sht_delta2alm for these arguments, flags included (a
+ * multiple of 256; for given flags the same value serves all four).  Returns
+ * 0 if the arguments are invalid. */
 size_t sht_workspace_bytes(int lmax, int mmax, const sht_geom *g, int nmaps, uint32_t flags);
 
 /* Synthesis (Sec. 3, Alg. 2): Delta^A_m(r) by the l-recurrence contracted
@@ -88,7 +104,7 @@ size_t sht_workspace_bytes(int lmax, int mmax, const sht_geom *g, int nmaps, uin
  *              rings are left untouched)
  *   workspace  DEVICE, >= sht_workspace_bytes(...) bytes, 256-byte aligned,
  *              must not alias alm or map; contents undefined afterwards
- *   flags      0 (FP64).  Any other bit: SHT_EUNSUPPORTED. */
+ *   flags      0 (FP64) or SHT_MIXED.  Any other bit: SHT_EUNSUPPORTED. */
 int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *map,
                 int nmaps, void *workspace, size_t ws_bytes, uint32_t flags, void *stream);
 
@@ -98,7 +114,8 @@ int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *
  * Requires g->weight.
  *   map        DEVICE float64   [nmaps][npix], read only
  *   alm        DEVICE complex128 [nmaps][nalm], fully written
- *   workspace  as for sht_alm2map. */
+ *   workspace  as for sht_alm2map
+ *   flags      0 (FP64).  SHT_MIXED or any other bit: SHT_EUNSUPPORTED. */
 int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *alm,
                 int nmaps, void *workspace, size_t ws_bytes, uint32_t flags, void *stream);
 

@@ -19,6 +19,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsht.so")
 
 SHT_OK, SHT_EINVAL, SHT_EWORKSPACE, SHT_EDEVICE, SHT_ENOMEM, SHT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+SHT_MIXED = 1  # flag: FP32 matrix-core contraction in synthesis (include/sht.h)
 
 EXPORTS = ("sht_workspace_bytes", "sht_alm2map", "sht_map2alm", "sht_alm2delta", "sht_delta2map",
            "sht_map2delta", "sht_delta2alm", "sht_strerror", "sht_shutdown")
@@ -118,9 +119,9 @@ def workspace_bytes(lmax: int, mmax: int, geom, nmaps: int = 1, flags: int = 0) 
     return int(lib().sht_workspace_bytes(lmax, mmax, g.ref(), nmaps, flags))
 
 
-def workspace(lmax: int, mmax: int, geom, nmaps: int = 1, device="cuda"):
+def workspace(lmax: int, mmax: int, geom, nmaps: int = 1, device="cuda", flags: int = 0):
     torch = _torch()
-    n = workspace_bytes(lmax, mmax, geom, nmaps)
+    n = workspace_bytes(lmax, mmax, geom, nmaps, flags)
     if n == 0:
         raise ShtError(SHT_EINVAL, "sht_workspace_bytes")
     return torch.empty(n, dtype=torch.uint8, device=device)
@@ -133,7 +134,7 @@ def _nmaps_of(t, per):
     return n
 
 
-def alm2map(alm, geom, lmax: int, mmax: int | None = None, out=None, ws=None, stream=None):
+def alm2map(alm, geom, lmax: int, mmax: int | None = None, out=None, ws=None, stream=None, flags: int = 0):
     """Synthesis.  alm: complex128 CUDA tensor [..., nalm]; returns float64 [..., npix]."""
     torch = _torch()
     mmax = lmax if mmax is None else mmax
@@ -143,14 +144,14 @@ def alm2map(alm, geom, lmax: int, mmax: int | None = None, out=None, ws=None, st
     if out is None:
         out = torch.zeros(alm.shape[:-1] + (g.npix,), dtype=torch.float64, device=alm.device)
     if ws is None:
-        ws = workspace(lmax, mmax, g, nm, alm.device)
+        ws = workspace(lmax, mmax, g, nm, alm.device, flags)
     rc = lib().sht_alm2map(lmax, mmax, g.ref(), alm.data_ptr(), out.data_ptr(), nm, ws.data_ptr(),
-                           ws.numel() * ws.element_size(), 0, _stream_ptr(stream))
+                           ws.numel() * ws.element_size(), flags, _stream_ptr(stream))
     _check(rc, "sht_alm2map")
     return out
 
 
-def map2alm(mp, geom, lmax: int, mmax: int | None = None, out=None, ws=None, stream=None):
+def map2alm(mp, geom, lmax: int, mmax: int | None = None, out=None, ws=None, stream=None, flags: int = 0):
     """Analysis.  mp: float64 CUDA tensor [..., npix]; returns complex128 [..., nalm]."""
     torch = _torch()
     mmax = lmax if mmax is None else mmax
@@ -159,14 +160,14 @@ def map2alm(mp, geom, lmax: int, mmax: int | None = None, out=None, ws=None, str
     if out is None:
         out = torch.empty(mp.shape[:-1] + (nalm(lmax, mmax),), dtype=torch.complex128, device=mp.device)
     if ws is None:
-        ws = workspace(lmax, mmax, g, nm, mp.device)
+        ws = workspace(lmax, mmax, g, nm, mp.device, flags)
     rc = lib().sht_map2alm(lmax, mmax, g.ref(), mp.data_ptr(), out.data_ptr(), nm, ws.data_ptr(),
-                           ws.numel() * ws.element_size(), 0, _stream_ptr(stream))
+                           ws.numel() * ws.element_size(), flags, _stream_ptr(stream))
     _check(rc, "sht_map2alm")
     return out
 
 
-def alm2delta(alm, geom, lmax: int, mmax: int | None = None, out=None, ws=None, stream=None):
+def alm2delta(alm, geom, lmax: int, mmax: int | None = None, out=None, ws=None, stream=None, flags: int = 0):
     """Legendre synthesis stage: complex128 Delta [..., nrings, mmax+1]."""
     torch = _torch()
     mmax = lmax if mmax is None else mmax
@@ -175,9 +176,9 @@ def alm2delta(alm, geom, lmax: int, mmax: int | None = None, out=None, ws=None, 
     if out is None:
         out = torch.empty(alm.shape[:-1] + (g.nrings, mmax + 1), dtype=torch.complex128, device=alm.device)
     if ws is None:
-        ws = workspace(lmax, mmax, g, nm, alm.device)
+        ws = workspace(lmax, mmax, g, nm, alm.device, flags)
     rc = lib().sht_alm2delta(lmax, mmax, g.ref(), alm.data_ptr(), out.data_ptr(), nm, ws.data_ptr(),
-                             ws.numel() * ws.element_size(), 0, _stream_ptr(stream))
+                             ws.numel() * ws.element_size(), flags, _stream_ptr(stream))
     _check(rc, "sht_alm2delta")
     return out
 
@@ -206,7 +207,7 @@ def map2delta(mp, geom, mmax: int, out=None, stream=None):
     return out
 
 
-def delta2alm(delta, geom, lmax: int, mmax: int | None = None, out=None, ws=None, stream=None):
+def delta2alm(delta, geom, lmax: int, mmax: int | None = None, out=None, ws=None, stream=None, flags: int = 0):
     """Legendre analysis stage: a_lm [..., nalm] from Delta^S [..., nrings, mmax+1]."""
     torch = _torch()
     mmax = lmax if mmax is None else mmax
@@ -215,9 +216,9 @@ def delta2alm(delta, geom, lmax: int, mmax: int | None = None, out=None, ws=None
     if out is None:
         out = torch.empty(delta.shape[:-2] + (nalm(lmax, mmax),), dtype=torch.complex128, device=delta.device)
     if ws is None:
-        ws = workspace(lmax, mmax, g, nm, delta.device)
+        ws = workspace(lmax, mmax, g, nm, delta.device, flags)
     rc = lib().sht_delta2alm(lmax, mmax, g.ref(), delta.data_ptr(), out.data_ptr(), nm, ws.data_ptr(),
-                             ws.numel() * ws.element_size(), 0, _stream_ptr(stream))
+                             ws.numel() * ws.element_size(), flags, _stream_ptr(stream))
     _check(rc, "sht_delta2alm")
     return out
 

@@ -1,0 +1,58 @@
+// Device helpers shared by the Legendre kernels (FP64 and mixed precision).
+#pragma once
+
+#include "sht_internal.h"
+
+namespace sht {
+
+// Workgroups are dispatched to the XCDs in turn (workgroup b runs on XCD
+// b mod kXcds).  The launchers round the number of m values up to a multiple
+// of kMBlock * kXcds, and the k-th workgroup of XCD x takes part k % parts of
+// the m value 64 j + 8 x' + r, with (j, r, part) counted out of k (r fastest
+// after the part) and x' = x on even j, 7 - x on odd j.  So the parts (slot
+// tiles or groups) of one m share one XCD's L2 for its coefficient column,
+// the 8 consecutive m whose entries fill one 128-byte line of a Delta row are
+// written (read) through the same L2, m still ascends in launch order, and
+// the snake order keeps the XCDs' shares of the work equal.
+constexpr int kXcds = 8;
+constexpr int kMBlock = 8;  // m values per 128-byte line of a Delta row
+struct MPart {
+    int m, part;
+};
+__device__ __forceinline__ MPart xcd_m_part(int parts) {
+    const int x = blockIdx.x % kXcds, k = blockIdx.x / kXcds;
+    const int per = kMBlock * parts;
+    const int j = k / per, rem = k - j * per;
+    const int xs = (j & 1) ? kXcds - 1 - x : x;
+    return {(j * kXcds + xs) * kMBlock + rem / parts, rem % parts};
+}
+
+// number of m values launched: mmax + 1 rounded up to a multiple of kMBlock * kXcds
+inline int64_t padded_m(int mmax) {
+    constexpr int64_t q = (int64_t)kMBlock * kXcds;
+    return ((int64_t)mmax + q) / q * q;
+}
+inline bool grid_ok(int64_t n) { return n > 0 && n < (int64_t)INT32_MAX; }
+
+// Wave-wide min / max, returned as a wave-uniform (scalar) value so that
+// loops bounded by it stay uniform and their coefficient loads scalar.
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// A wave-uniform 64-bit value restated as such (for addresses that must stay
+// on scalar registers).
+__device__ __forceinline__ int64_t uniform64(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+}  // namespace sht

@@ -38,7 +38,7 @@
 //              sums its lanes through its own LDS rows, the four waves are
 //              added in wave order every 64 l, and groups are summed in
 //              order by a second small kernel: no atomics, deterministic.
-#include "sht_internal.h"
+#include "k_device.h"
 
 namespace sht {
 namespace {
@@ -141,28 +141,6 @@ __global__ __launch_bounds__(kBlock) void k_prescale(int64_t nalm, int lmax, int
     }
 }
 
-// Workgroups are dispatched to the XCDs in turn (workgroup b runs on XCD
-// b mod kXcds).  The launchers round the number of m values up to a multiple
-// of kMBlock * kXcds, and the k-th workgroup of XCD x takes part k % parts of
-// the m value 64 j + 8 x' + r, with (j, r, part) counted out of k (r fastest
-// after the part) and x' = x on even j, 7 - x on odd j.  So the parts (slot
-// tiles or groups) of one m share one XCD's L2 for its coefficient column,
-// the 8 consecutive m whose entries fill one 128-byte line of a Delta row are
-// written (read) through the same L2, m still ascends in launch order, and
-// the snake order keeps the XCDs' shares of the work equal.
-constexpr int kXcds = 8;
-constexpr int kMBlock = 8;  // m values per 128-byte line of a Delta row
-struct MPart {
-    int m, part;
-};
-__device__ __forceinline__ MPart xcd_m_part(int parts) {
-    const int x = blockIdx.x % kXcds, k = blockIdx.x / kXcds;
-    const int per = kMBlock * parts;
-    const int j = k / per, rem = k - j * per;
-    const int xs = (j & 1) ? kXcds - 1 - x : x;
-    return {(j * kXcds + xs) * kMBlock + rem / parts, rem % parts};
-}
-
 // One load from each of the first kBlock 128-byte lines of p[stride * i],
 // i0 <= i <= i1 (addresses clamped to i1, so every load is in bounds).  The
 // workgroup's pass over a coefficient column brings it into this XCD's L2
@@ -172,19 +150,6 @@ __device__ __forceinline__ double warm_l2(const double *p, int stride, int i0, i
     const int per_line = 16 / stride;  // entries per 128 bytes
     const int i = min(i0 + per_line * (int)threadIdx.x, i1);
     return p[(int64_t)stride * i];
-}
-
-// Wave-wide min / max, returned as a wave-uniform (scalar) value so that
-// loops bounded by it stay uniform and their coefficient loads scalar.
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = min(v, __shfl_xor(v, off));
-    return __builtin_amdgcn_readfirstlane(v);
-}
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v = max(v, __shfl_xor(v, off));
-    return __builtin_amdgcn_readfirstlane(v);
 }
 
 // Synthesis: lane i of tile t owns slots (t*256 + i)*T + u, u < T.
@@ -594,13 +559,6 @@ __global__ __launch_bounds__(kBlock) void k_ana_combine(int64_t nalm, int lmax, 
 }
 
 }  // namespace
-
-static int grid_ok(int64_t n) { return n > 0 && n < (int64_t)INT32_MAX; }
-// number of m values launched: mmax + 1 rounded up to a multiple of kMBlock * kXcds
-static int64_t padded_m(int mmax) {
-    constexpr int64_t q = (int64_t)kMBlock * kXcds;
-    return ((int64_t)mmax + q) / q * q;
-}
 
 int launch_leg_start(const CoefTables &c, const GeomPlan &p, int32_t *lstart, void *state, hipStream_t st) {
     const int tiles = (p.nslots + kBlock - 1) / kBlock;

@@ -13,7 +13,7 @@ using namespace sht;
 
 namespace {
 
-constexpr uint32_t kKnownFlags = 0u;
+constexpr uint32_t kKnownFlags = SHT_MIXED;
 
 size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -26,19 +26,21 @@ size_t delta_bytes(int nrings, int mmax, int nmaps) {
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-// Workspace layout: [Delta (synthesis/analysis)][aux], aux holding either the
+// Workspace layout: [Delta (synthesis/analysis)][aux], aux holding the
 // c-scaled a_lm of synthesis (followed by kCoefPad entries that the synthesis
-// kernel may read ahead) or the per-group partial a_lm of analysis.
+// kernel may read ahead; with SHT_MIXED the FP32 block tiles instead) or the
+// per-group partial a_lm of analysis.
 size_t partial_bytes(int lmax, int mmax, int nslots, int nmaps) {
     const int G = ana_groups(nslots);
     return G > 1 ? (size_t)G * alm_bytes(lmax, mmax, nmaps) : 0;
 }
-size_t aux_bytes(int lmax, int mmax, int nslots, int nmaps) {
-    return std::max(round256(alm_bytes(lmax, mmax, nmaps) + 16u * kCoefPad),
-                    round256(partial_bytes(lmax, mmax, nslots, nmaps)));
+size_t aux_bytes(int lmax, int mmax, int nslots, int nmaps, uint32_t flags) {
+    const size_t syn = (flags & SHT_MIXED) ? mx_aprime_bytes(lmax, mmax, nmaps)
+                                           : alm_bytes(lmax, mmax, nmaps) + 16u * kCoefPad;
+    return std::max(round256(syn), round256(partial_bytes(lmax, mmax, nslots, nmaps)));
 }
-size_t ws_need(int lmax, int mmax, const HostGeom &h, int nmaps) {
-    return round256(delta_bytes(h.nrings, mmax, nmaps)) + aux_bytes(lmax, mmax, count_slots(h), nmaps);
+size_t ws_need(int lmax, int mmax, const HostGeom &h, int nmaps, uint32_t flags) {
+    return round256(delta_bytes(h.nrings, mmax, nmaps)) + aux_bytes(lmax, mmax, count_slots(h), nmaps, flags);
 }
 
 bool overlap(const void *a, size_t na, const void *b, size_t nb) {
@@ -64,7 +66,7 @@ extern "C" {
 size_t sht_workspace_bytes(int lmax, int mmax, const sht_geom *g, int nmaps, uint32_t flags) {
     HostGeom h;
     if (check_common(lmax, mmax, g, nmaps, flags, false, &h)) return 0;
-    return ws_need(lmax, mmax, h, nmaps);
+    return ws_need(lmax, mmax, h, nmaps, flags);
 }
 
 int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *delta, int nmaps,
@@ -74,7 +76,7 @@ int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *
     if (rc) return rc;
     if (!alm || !delta || !aligned(alm, 16) || !aligned(delta, 16)) return SHT_EINVAL;
     const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
-    if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps))
+    if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps, flags))
         return SHT_EWORKSPACE;
     if (overlap(alm, ab, delta, db) || overlap(workspace, ws_bytes, alm, ab) ||
         overlap(workspace, ws_bytes, delta, db))
@@ -85,6 +87,7 @@ int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *
     if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p)) ||
         (rc = get_start(*c, p, as_stream(stream), &s)))
         return rc;
+    if (flags & SHT_MIXED) return launch_leg_syn_mx(*c, *p, *s, alm, workspace, delta, nmaps, as_stream(stream));
     if ((rc = launch_prescale(*c, alm, workspace, nmaps, as_stream(stream)))) return rc;
     return launch_leg_syn(*c, *p, *s, workspace, delta, nmaps, as_stream(stream));
 }
@@ -120,9 +123,10 @@ int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void
     HostGeom h;
     int rc = check_common(lmax, mmax, g, nmaps, flags, false, &h);
     if (rc) return rc;
+    if (flags & SHT_MIXED) return SHT_EUNSUPPORTED;  // synthesis only
     if (!delta || !alm || !aligned(delta, 16) || !aligned(alm, 16)) return SHT_EINVAL;
     const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
-    if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps))
+    if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps, flags))
         return SHT_EWORKSPACE;
     if (overlap(delta, db, alm, ab) || overlap(workspace, ws_bytes, alm, ab) ||
         overlap(workspace, ws_bytes, delta, db))
@@ -144,7 +148,7 @@ int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *
     if (!alm || !map || !aligned(alm, 16) || !aligned(map, 8)) return SHT_EINVAL;
     const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
     const size_t mb = (size_t)h.npix * 8u * nmaps;
-    if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps))
+    if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps, flags))
         return SHT_EWORKSPACE;
     if (overlap(alm, ab, map, mb) || overlap(workspace, ws_bytes, alm, ab) ||
         overlap(workspace, ws_bytes, map, mb))
@@ -157,8 +161,12 @@ int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *
         return rc;
     char *ws = static_cast<char *>(workspace);
     void *delta = ws, *aprime = ws + round256(db);
-    if ((rc = launch_prescale(*c, alm, aprime, nmaps, st))) return rc;
-    if ((rc = launch_leg_syn(*c, *p, *s, aprime, delta, nmaps, st))) return rc;
+    if (flags & SHT_MIXED) {
+        if ((rc = launch_leg_syn_mx(*c, *p, *s, alm, aprime, delta, nmaps, st))) return rc;
+    } else {
+        if ((rc = launch_prescale(*c, alm, aprime, nmaps, st))) return rc;
+        if ((rc = launch_leg_syn(*c, *p, *s, aprime, delta, nmaps, st))) return rc;
+    }
     return launch_fft_syn(*p, mmax, delta, map, nmaps, st);
 }
 
@@ -167,10 +175,11 @@ int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *
     HostGeom h;
     int rc = check_common(lmax, mmax, g, nmaps, flags, true, &h);
     if (rc) return rc;
+    if (flags & SHT_MIXED) return SHT_EUNSUPPORTED;  // synthesis only
     if (!alm || !map || !aligned(alm, 16) || !aligned(map, 8)) return SHT_EINVAL;
     const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
     const size_t mb = (size_t)h.npix * 8u * nmaps;
-    if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps))
+    if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps, flags))
         return SHT_EWORKSPACE;
     if (overlap(alm, ab, map, mb) || overlap(workspace, ws_bytes, alm, ab) ||
         overlap(workspace, ws_bytes, map, mb))

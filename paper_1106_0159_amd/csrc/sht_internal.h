@@ -47,6 +47,11 @@ constexpr int kStartStep = 8;
 // entries past lmax of a column without a guard.
 constexpr int kCoefPad = 32;
 
+// Mixed-precision Legendre stage: l runs in blocks of kMxL values counted
+// from m (kMxL / 2 of each parity of l - m); column m has mx_blocks(lmax, m).
+constexpr int kMxL = 32;
+__host__ __device__ inline int mx_blocks(int lmax, int m) { return (lmax - m + kMxL) / kMxL; }
+
 // Coefficient tables for one (lmax, mmax) on one device.  Packed (l, m)
 // index as for a_lm.  p_lm = cfac_lm * q_lm, q_lm = alpha_lm x q_{l-1,m} - q_{l-2,m}.
 struct CoefTables {
@@ -56,6 +61,8 @@ struct CoefTables {
     double *alpha = nullptr;  // [nalm + kCoefPad]; alpha at l = m is 0, at l = m+1 sqrt(2m+3)
     double *cfac = nullptr;   // [nalm]
     double *mu = nullptr;     // [mmax+1]
+    int64_t *mxofs = nullptr; // [mmax+2] first l-block of column m, blocks counted over m
+    int64_t mxblocks = 0;     // sum over m of mx_blocks(lmax, m)
     std::vector<void *> owned;
     CoefTables() = default;
     CoefTables(const CoefTables &) = delete;
@@ -177,6 +184,12 @@ int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const StartTable &s, 
                    void *delta, int nmaps, hipStream_t st);
 int launch_leg_ana(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *delta,
                    void *alm, int nmaps, void *partials, hipStream_t st);
+// Mixed precision (SHT_MIXED, k_legendre_mx.hip): prescale of a_lm into FP32
+// block tiles of mx_aprime_bytes(...) bytes, then the synthesis contraction.
+int mx_col_frags(int nmaps);
+size_t mx_aprime_bytes(int lmax, int mmax, int nmaps);
+int launch_leg_syn_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm,
+                      void *aprime, void *delta, int nmaps, hipStream_t st);
 int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, double *map, int nmaps,
                    hipStream_t st);
 int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, int nmaps,

@@ -198,8 +198,11 @@ int get_coef(int lmax, int mmax, CoefRef *out) {
     t->mmax = mmax;
     t->nalm = na;
     alpha.resize(na + kCoefPad, 0.0);  // kernels may read past the last column
+    std::vector<int64_t> mxofs(mmax + 2, 0);
+    for (int m = 0; m <= mmax; ++m) mxofs[m + 1] = mxofs[m] + mx_blocks(lmax, m);
+    t->mxblocks = mxofs[mmax + 1];
     if ((rc = upload(alpha, &t->alpha, t->owned)) || (rc = upload(cfac, &t->cfac, t->owned)) ||
-        (rc = upload(mu, &t->mu, t->owned)))
+        (rc = upload(mu, &t->mu, t->owned)) || (rc = upload(mxofs, &t->mxofs, t->owned)))
         return rc;  // t frees what was uploaded
     g_coef[key] = CoefEntry{t, ++g_clock};
     *out = t;

@@ -77,6 +77,26 @@ def test_workspace_bytes_values_and_monotonic():
     assert _ws(lmax, lmax, g) % 256 == 0
 
 
+def test_workspace_bytes_mixed():
+    """SHT_MIXED: aux holds FP32 tiles of c a_lm, [column group][l-block of
+    column m][parity][16 NCF columns][16 k] floats, NCF = 1, 2, 4 for up to
+    8, 16 and more maps (8 NCF maps per column group), kMxL = 32 l per block."""
+    g = si.healpix(8)
+    r256 = lambda b: (b + 255) // 256 * 256
+    delta = lambda lmax, n: r256(n * g.nrings * (lmax + 1) * 16)
+
+    def tiles(lmax, nmaps):
+        blocks = sum((lmax - m + 32) // 32 for m in range(lmax + 1))
+        ncf = 1 if nmaps <= 8 else 2 if nmaps <= 16 else 4
+        ncg = -(-nmaps // (8 * ncf))
+        return ncg * blocks * 2 * (16 * ncf) * 16 * 4
+
+    for lmax, nmaps in [(16, 1), (16, 3), (16, 12), (16, 20), (16, 40), (70, 33), (0, 1)]:
+        assert _ws(lmax, lmax, g, nmaps, sht.SHT_MIXED) == delta(lmax, nmaps) + r256(tiles(lmax, nmaps)), (lmax, nmaps)
+    # lmax = 16: 17 columns of one block each; 20 maps -> one group of 32 maps (64 columns)
+    assert tiles(16, 20) == 17 * 2 * 64 * 16 * 4
+
+
 @pytest.mark.parametrize("args", [
     (-1, 0, 1, 0), (4, 5, 1, 0), (4, -1, 1, 0), (4, 4, 0, 0), (4, 4, 1, 1 << 3),
 ])
@@ -126,8 +146,11 @@ def test_invalid_arguments_rejected_on_host(L):
     assert L.sht_alm2map(-1, 0, g.ref(), a, m, 1, w, big, 0, None) == sht.SHT_EINVAL
     assert L.sht_alm2map(4, 5, g.ref(), a, m, 1, w, big, 0, None) == sht.SHT_EINVAL
     assert L.sht_alm2map(4, 4, g.ref(), a, m, 0, w, big, 0, None) == sht.SHT_EINVAL
-    # flags
-    assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, big, 1, None) == sht.SHT_EUNSUPPORTED
+    # flags: unknown bits; SHT_MIXED is synthesis only
+    assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, big, 2, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, big, 1 << 31, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_map2alm(4, 4, g.ref(), m, a, 1, w, big, sht.SHT_MIXED, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_delta2alm(4, 4, g.ref(), m, a, 1, w, big, sht.SHT_MIXED, None) == sht.SHT_EUNSUPPORTED
     # null and misaligned pointers
     assert L.sht_alm2map(4, 4, g.ref(), None, m, 1, w, big, 0, None) == sht.SHT_EINVAL
     assert L.sht_alm2map(4, 4, g.ref(), a, None, 1, w, big, 0, None) == sht.SHT_EINVAL

@@ -1,0 +1,164 @@
+"""GPU parity of the mixed-precision synthesis (SHT_MIXED) against the oracle.
+
+The recurrence stays FP64 and only lambda_lm, c_lm a_lm and the sum over l
+are FP32, so the bar is the batched-mixed target: relative RMS <= 1e-6 of
+every map against the FP64 oracle (and against the FP64 HIP path, itself
+pinned to 1e-12).  Batches of 1, 3, 12 and 40 maps take the three column
+widths of the kernel (8, 16 and 32 maps per wave) and a partly filled last
+column group.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import sht_inputs as si
+
+pytestmark = pytest.mark.gpu
+
+MX_TOL = 1e-6
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def sht():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1106_0159_amd as S
+    S.lib()
+    return S
+
+
+def dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def relrms(got, ref):
+    den = np.linalg.norm(ref)
+    return np.linalg.norm(got - ref) / (den if den > 0 else 1.0)
+
+
+def batch(lmax, mmax, nmaps, seed):
+    """Power-law and uniform a_lm in turn, Im a_l0 set (it must be ignored)."""
+    out = np.empty((nmaps, si.nalm(lmax, mmax)), dtype=np.complex128)
+    for i in range(nmaps):
+        a = si.powerlaw_alm(lmax, mmax, seed + i) if i % 2 == 0 else si.uniform_alm(lmax, mmax, seed + i)
+        a[: lmax + 1] += 0.25j
+        out[i] = a
+    return out
+
+
+MX_CASES = [
+    # (name, geometry builder, lmax, mmax, nmaps)
+    ("gl0_1", lambda: si.gauss_legendre(1, 1), 0, 0, 1),
+    ("gl7_mless_3", lambda: si.gauss_legendre(8, 9), 7, 4, 3),
+    ("gl31_12", lambda: si.gauss_legendre(32, 63), 31, 31, 12),
+    ("gl64_odd_3", lambda: si.gauss_legendre(65, 129), 64, 64, 3),
+    ("hp8_alias_12", lambda: si.healpix(8), 40, 40, 12),
+    ("hp16_40", lambda: si.healpix(16), 32, 32, 40),
+    ("hp32_ragged_17", lambda: si.healpix(32), 77, 61, 17),
+    ("random_poles_9", lambda: si._pack(np.array([0.0, 0.4, 1.2, np.pi / 2, 2.0, np.pi]),
+                                        np.array([1, 5, 16, 3, 9, 2], dtype=np.int32),
+                                        np.array([0.0, 0.1, 2.0, -1.0, 0.5, 0.0]),
+                                        np.ones(6), "poles"), 12, 12, 9),
+    ("gl_bluestein_40", lambda: si.gauss_legendre(70, 139), 69, 69, 40),
+    # 300 unpaired rings: two 256-pair tiles, the second ragged
+    ("random300_8", lambda: si._pack(np.sort(np.random.default_rng(3).uniform(0, np.pi, 300)),
+                                     np.full(300, 9, dtype=np.int32), np.zeros(300), np.ones(300), "r300"),
+     20, 20, 8),
+]
+
+
+@pytest.mark.parametrize("case", MX_CASES, ids=[c[0] for c in MX_CASES])
+def test_mixed_alm2map_small(sht, case):
+    name, mk, lmax, mmax, nmaps = case
+    g = mk()
+    a = batch(lmax, mmax, nmaps, 500)
+    say(f"mixed alm2map {name} lmax={lmax} mmax={mmax} nrings={g.nrings} nmaps={nmaps}")
+    got = host(sht.alm2map(dev(a), g, lmax, mmax, flags=sht.SHT_MIXED))
+    f64 = host(sht.alm2map(dev(a), g, lmax, mmax))
+    for i in range(nmaps):
+        ref = oracle.alm2map(lmax, mmax, g, a[i])
+        if np.linalg.norm(ref) == 0:
+            assert np.all(got[i] == 0.0)
+            continue
+        assert relrms(got[i], ref) <= MX_TOL, (name, i, relrms(got[i], ref))
+        assert relrms(got[i], f64[i]) <= MX_TOL, (name, i, relrms(got[i], f64[i]))
+
+
+@pytest.mark.parametrize("case", [MX_CASES[4], MX_CASES[6]], ids=[MX_CASES[4][0], MX_CASES[6][0]])
+def test_mixed_alm2delta(sht, case):
+    name, mk, lmax, mmax, nmaps = case
+    g = mk()
+    a = batch(lmax, mmax, nmaps, 600)
+    say(f"mixed alm2delta {name} nmaps={nmaps}")
+    got = host(sht.alm2delta(dev(a), g, lmax, mmax, flags=sht.SHT_MIXED))
+    for i in range(nmaps):
+        ref = oracle.delta_syn(lmax, mmax, g, a[i])
+        assert relrms(got[i], ref) <= MX_TOL, (name, i, relrms(got[i], ref))
+
+
+def test_mixed_is_deterministic_and_batch_independent(sht):
+    """The same map gives the same bits alone in its column group and inside
+    a larger batch (columns are independent), and on a repeated call."""
+    lmax, g = 40, si.healpix(8)
+    a = batch(lmax, lmax, 40, 700)
+    say("mixed determinism hp8 lmax=40 nmaps=40")
+    full = host(sht.alm2map(dev(a), g, lmax, flags=sht.SHT_MIXED))
+    again = host(sht.alm2map(dev(a), g, lmax, flags=sht.SHT_MIXED))
+    assert np.array_equal(full, again)
+    # maps 32..39 form the second group of 32; alone they are a batch of 8
+    part = host(sht.alm2map(dev(a[32:]), g, lmax, flags=sht.SHT_MIXED))
+    for i in range(8):
+        assert relrms(part[i], full[32 + i]) <= MX_TOL
+
+
+def test_mixed_analysis_unsupported(sht):
+    lmax, g = 8, si.healpix(4)
+    s = dev(si.random_map(g, 1))
+    with pytest.raises(sht.ShtError) as e:
+        sht.map2alm(s, g, lmax, flags=sht.SHT_MIXED)
+    assert e.value.code == sht.SHT_EUNSUPPORTED
+    d = dev(np.zeros((g.nrings, lmax + 1), dtype=np.complex128))
+    with pytest.raises(sht.ShtError) as e:
+        sht.delta2alm(d, g, lmax, flags=sht.SHT_MIXED)
+    assert e.value.code == sht.SHT_EUNSUPPORTED
+
+
+def test_mixed_full_size_healpix1024_lmax2048_64maps(sht):
+    """The batched configuration of the benchmark: 64 power-law maps on
+    HEALPix N_side = 1024, lmax = 2048.  Three maps against the FP64 HIP path
+    over every pixel, and map 0 against the oracle on sampled rings."""
+    import torch
+    lmax, nmaps = 2048, 64
+    g = si.healpix(1024)
+    say("mixed alm2map full size: healpix 1024 lmax 2048 nmaps 64")
+    alm = torch.empty((nmaps, si.nalm(lmax, lmax)), dtype=torch.complex128, device="cuda")
+    for i in range(nmaps):
+        alm[i] = dev(si.powerlaw_alm(lmax, lmax, si.config_seed(2, i)))
+    got = sht.alm2map(alm, g, lmax, flags=sht.SHT_MIXED)
+    for i in (0, 37, 63):
+        ref = host(sht.alm2map(alm[i].contiguous(), g, lmax))
+        gi = host(got[i])
+        assert relrms(gi, ref) <= MX_TOL, (i, relrms(gi, ref))
+    rings = [0, 1, 700, 2047, 3000, 4094]
+    a0 = si.powerlaw_alm(lmax, lmax, si.config_seed(2, 0))
+    ref = oracle.alm2map(lmax, lmax, g, a0, rings=rings)
+    g0 = host(got[0])
+    # a single ring holds as few as 4 pixels: its own relative error is held
+    # to ten times the whole-map bar
+    for r in rings:
+        sl = slice(g.ofs[r], g.ofs[r] + g.nphi[r])
+        assert relrms(g0[sl], ref[sl]) <= 10 * MX_TOL, (r, relrms(g0[sl], ref[sl]))
