@@ -6,7 +6,8 @@ One step = one map through both transforms, with inputs resident in HBM:
 called through the four stage entry points of the C ABI (their composition is
 exactly sht_alm2map followed by sht_map2alm), with HIP events on the launch
 stream between stages.  A second leg ("batched_mixed" in the output) runs
-alm2map on a batch of 64 maps with the mixed-precision Legendre contraction.
+the same two transforms on a batch of 64 maps with the mixed-precision
+Legendre contraction.
 Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch N] [--no-cpu-baseline]
@@ -118,12 +119,13 @@ def cpu_baseline(g, lmax, a, mp, target_s: float = 12.0):
     }
 
 
-def batched_mixed(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64):
-    """alm2map of a batch of power-law maps with SHT_MIXED (FP64 recurrence,
-    FP32 matrix-core contraction), through the two synthesis stage entry
-    points, HIP events on the launch stream around each stage.  Map 0 of the
-    batch is the map of the plain FP64 run; its relative RMS difference to that
-    map is reported."""
+def batched_mixed(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a_fp64):
+    """One batch of power-law maps through both transforms with SHT_MIXED
+    (FP64 recurrence, FP32 matrix-core contraction; Delta and FFTs FP64),
+    through the four stage entry points as in the plain step, HIP events on
+    the launch stream around each stage.  Map 0 of the batch is the map of the
+    plain FP64 step: the relative RMS differences of its map and of its
+    analysed a_lm to the FP64 results are reported."""
     import numpy as np
     import torch
     dev = torch.device("cuda", 0)
@@ -131,46 +133,58 @@ def batched_mixed(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64):
     for i in range(nmaps):
         alm[i] = torch.from_numpy(si.powerlaw_alm(lmax, lmax, si.config_seed(2, i))).to(dev)
     delta = torch.empty((nmaps, g.nrings, lmax + 1), dtype=torch.complex128, device=dev)
+    delta_s = torch.empty_like(delta)
     mp = torch.zeros((nmaps, g.npix), dtype=torch.float64, device=dev)
+    a_out = torch.empty_like(alm)
     ws = sht.workspace(lmax, lmax, gh, nmaps, dev, sht.SHT_MIXED)
+    F = sht.SHT_MIXED
 
     def step(ev=None):
-        if ev is not None:
-            ev[0].record()
-        sht.alm2delta(alm, gh, lmax, lmax, out=delta, ws=ws, flags=sht.SHT_MIXED)
-        if ev is not None:
-            ev[1].record()
+        def mark(i):
+            if ev is not None:
+                ev[i].record()
+        mark(0)
+        sht.alm2delta(alm, gh, lmax, lmax, out=delta, ws=ws, flags=F)
+        mark(1)
         sht.delta2map(delta, gh, lmax, out=mp)
-        if ev is not None:
-            ev[2].record()
+        mark(2)
+        sht.map2delta(mp, gh, lmax, out=delta_s)
+        mark(3)
+        sht.delta2alm(delta_s, gh, lmax, lmax, out=a_out, ws=ws, flags=F)
+        mark(4)
 
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
-    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(5)] for _ in range(steps)]
     t0 = time.perf_counter()
     for k in range(steps):
         step(evs[k])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    leg = float(np.mean([e[0].elapsed_time(e[1]) for e in evs]))
-    fft = float(np.mean([e[1].elapsed_time(e[2]) for e in evs]))
-    ms = max(wall * 1000.0 / steps, leg + fft)
-    flops = 4 * nmaps * count_triples(nslots, lmax, lmax)  # matrix-core flops of the contraction
-    achieved = flops / (leg * 1e-3) / 1e12
-    d = (mp[0] - mp_fp64).norm().item() / mp_fp64.norm().item()
+    names = ["leg_syn_mx", "fft_syn", "fft_ana", "leg_ana_mx"]
+    st = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])) for i, n in enumerate(names)}
+    ms = max(wall * 1000.0 / steps, sum(st.values()))
+    flops = 4 * nmaps * count_triples(nslots, lmax, lmax)  # matrix-core flops of one contraction
+    dom = max(("leg_syn_mx", "leg_ana_mx"), key=lambda n: st[n])
+    achieved = flops / (st[dom] * 1e-3) / 1e12
+    rel = lambda x, y: (x - y).norm().item() / y.norm().item()
     return {
-        "direction": "alm2map",
+        "direction": "alm2map+map2alm",
         "nmaps": nmaps,
         "value": nmaps * 1000.0 / ms,
         "unit": "maps/s",
         "ms_per_batch": ms,
         "steps": steps,
-        "stages_ms": {"leg_syn_mx": leg, "fft_syn": fft},
+        "stages_ms": st,
+        "alm2map_maps_per_s": nmaps * 1000.0 / (st["leg_syn_mx"] + st["fft_syn"]),
+        "map2alm_maps_per_s": nmaps * 1000.0 / (st["fft_ana"] + st["leg_ana_mx"]),
         "dtype": "f64 recurrence, f32 contraction",
-        "relrms_map0_vs_fp64": d,
+        "relrms_map0_vs_fp64": rel(mp[0], mp_fp64),
+        "relrms_alm0_vs_fp64": rel(a_out[0], a_fp64),
         "roofline": {
-            "kernel": "k_prescale_mx + k_leg_syn_mx",
+            "kernel": {"leg_syn_mx": "k_prescale_mx + k_leg_syn_mx",
+                       "leg_ana_mx": "k_leg_ana_mx"}[dom],
             "bound": "mfma",
             "achieved": achieved,
             "peak": PEAK_FP32_MFMA_TFLOPS,
@@ -313,7 +327,7 @@ def main():
     }
     if args.batch > 0:
         rec["batched_mixed"] = batched_mixed(sht, si, gh, g, lmax, args.batch, max(3, K // 4), args.warmup,
-                                             nslots, mp)
+                                             nslots, mp, a_out)
     if not args.no_cpu_baseline:
         mp_np = mp.cpu().numpy()
         rec["cpu_baseline"] = cpu_baseline(g, lmax, a_np, mp_np)

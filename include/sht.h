@@ -77,16 +77,19 @@ enum sht_status {
 
 /* Flag bits of the `flags` arguments. */
 enum sht_flags {
-    /* Mixed precision for the Legendre contraction of synthesis (sht_alm2map,
-     * sht_alm2delta; the analysis calls return SHT_EUNSUPPORTED with it, the
-     * ring-FFT calls ignore it).  The recurrence, its seeds, start table and
-     * coefficients stay FP64 (Sec. 2.1); each lambda_lm (in the rescaled form
-     * q_lm = lambda_lm / c_lm) and each c_lm a_lm is rounded to FP32 once, and
-     * the per-m matrix product of Sec. 3 (eq. matrix_vec, with one column per
-     * map and real/imaginary part) is summed over l in FP32 on the matrix
-     * cores.  Expected relative RMS error against the FP64 transform: about
-     * 1e-7 to 1e-6.  Built for batches: one wave covers 8, 16 or 32 maps, so
-     * nmaps >= 8 fills it. */
+    /* Mixed precision for the Legendre contraction (sht_alm2map,
+     * sht_alm2delta, sht_map2alm, sht_delta2alm; the ring-FFT calls ignore
+     * it).  The recurrence, its seeds, start table and coefficients stay FP64
+     * (Sec. 2.1).  Each lambda_lm (in the rescaled form q_lm = lambda_lm / c_lm)
+     * is rounded to FP32 once, as is each c_lm a_lm (synthesis) or each
+     * north +- south Delta_m of a ring pair (analysis), and the per-m matrix
+     * products of Sec. 3 (eq. matrix_vec and its transpose, one column per
+     * map and real/imaginary part) run on the FP32 matrix cores: synthesis
+     * sums over l in FP32; analysis sums 32 l at a time over up to 256 ring
+     * pairs in FP32 and adds those sums in FP64.  The Delta and FFT stages stay
+     * FP64.  Expected relative RMS error against the FP64 transform: about
+     * 1e-7 to 1e-6.  Built for batches: a wave covers 8 to 32 maps in
+     * synthesis and 8 in analysis, so nmaps >= 8 fills it. */
     SHT_MIXED = 1u
 };
 
@@ -115,7 +118,7 @@ int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *
  *   map        DEVICE float64   [nmaps][npix], read only
  *   alm        DEVICE complex128 [nmaps][nalm], fully written
  *   workspace  as for sht_alm2map
- *   flags      0 (FP64).  SHT_MIXED or any other bit: SHT_EUNSUPPORTED. */
+ *   flags      0 (FP64) or SHT_MIXED.  Any other bit: SHT_EUNSUPPORTED. */
 int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *alm,
                 int nmaps, void *workspace, size_t ws_bytes, uint32_t flags, void *stream);
 

@@ -616,13 +616,16 @@ int launch_leg_ana(const CoefTables &c, const GeomPlan &p, const StartTable &s, 
         default: launch_ana_t<kAnaSlotsPerThread>(c, p, s, groups, delta, alm, partials, nmaps, st); break;
     }
     SHT_HIP(hipGetLastError());
-    if (groups > 1) {
-        const int64_t total = c.nalm * nmaps;
-        const int64_t blocks = std::min<int64_t>((total + kBlock - 1) / kBlock, 1 << 16);
-        hipLaunchKernelGGL(k_ana_combine, dim3((unsigned)blocks), dim3(kBlock), 0, st, c.nalm, c.lmax, nmaps,
-                           groups, static_cast<const double2 *>(partials), c.cfac, static_cast<double2 *>(alm));
-        SHT_HIP(hipGetLastError());
-    }
+    return groups > 1 ? launch_ana_combine(c, nmaps, groups, partials, alm, st) : SHT_OK;
+}
+
+int launch_ana_combine(const CoefTables &c, int nmaps, int groups, const void *partials, void *alm,
+                       hipStream_t st) {
+    const int64_t total = c.nalm * nmaps;
+    const int64_t blocks = std::min<int64_t>((total + kBlock - 1) / kBlock, 1 << 16);
+    hipLaunchKernelGGL(k_ana_combine, dim3((unsigned)blocks), dim3(kBlock), 0, st, c.nalm, c.lmax, nmaps, groups,
+                       static_cast<const double2 *>(partials), c.cfac, static_cast<double2 *>(alm));
+    SHT_HIP(hipGetLastError());
     return SHT_OK;
 }
 

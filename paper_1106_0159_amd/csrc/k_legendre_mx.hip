@@ -196,6 +196,174 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
     }
 }
 
+// Analysis: a_lm[col] = c_lm sum_pairs D[pair][col] q_lm(x_pair) with
+// D = D+ = north + south for even l - m and D- = north - south for odd (the
+// mirror identity used by the FP64 kernels), col = 2 map + (re, im).  One
+// workgroup of kAnaMxWaves waves holds kAnaMxGroup ring pairs of one m (a
+// group; more pairs take several groups whose partial sums k_ana_combine
+// adds) and kAnaMxMaps maps.  Wave w owns kAnaMxTiles tiles of 64 pairs; its
+// D+ and D- operands stay in registers for the whole kernel (rounded to FP32
+// once).  Per l-block each wave runs the recurrences of its tiles (one pair
+// per lane), stages q (FP32) in its LDS tile k-major, and contracts over its
+// pairs on the matrix cores with a fresh FP32 accumulator: rows are the 16 l
+// of one parity, columns the 16 columns, K the pairs (in k step j of tile t,
+// lane l takes pair 16 (l / 16) + 4 u + j of the tile for its u-th operand
+// load).  The waves' block sums are added in wave order in FP64 after one
+// barrier (two LDS buffers in turn), scaled by c_lm and written.
+constexpr int kAnaMxWaves = 8;
+constexpr int kAnaMxThreads = 64 * kAnaMxWaves;
+constexpr int kAnaMxTiles = 4;
+constexpr int kAnaMxMaps = 8;   // 16 columns
+constexpr int kQRow = 64 + 4;   // floats per k row of a q tile (padding: conflict-free operand reads)
+static_assert(kAnaMxGroup == kAnaMxWaves * kAnaMxTiles * 64, "pairs per analysis group");
+static_assert(2 * kMxHalf * kAnaMxMaps <= kAnaMxThreads, "one thread per finished (parity, k, map)");
+
+__global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int mmax, int nslots, int nrings,
+                                                              int nmaps, int64_t nalm, int groups,
+                                                              const double2 *__restrict__ delta,
+                                                              const double *__restrict__ alpha,
+                                                              const double *__restrict__ cfac,
+                                                              const int32_t *__restrict__ lstart,
+                                                              const double2 *__restrict__ state,
+                                                              const double *__restrict__ sx,
+                                                              const int32_t *__restrict__ rn,
+                                                              const int32_t *__restrict__ rsouth,
+                                                              double2 *__restrict__ alm,
+                                                              double2 *__restrict__ part) {
+    __shared__ float qs[kAnaMxWaves][2][kMxHalf][kQRow];
+    __shared__ float red[2][kAnaMxWaves][2][kMxHalf][16];
+    __shared__ int wlo[kAnaMxWaves];
+
+    const MPart mp = xcd_m_part(groups);
+    const int m = mp.m, grp = mp.part;
+    if (m > mmax) return;  // padding of the m range (whole workgroup, before any barrier)
+    const int cg = blockIdx.y;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int c16 = lane & 15, kq = lane >> 4;
+    const int map_c = cg * kAnaMxMaps + (c16 >> 1);  // this lane's column: map and part
+    const bool col_ok = map_c < nmaps;
+    const int first = grp * kAnaMxGroup + w * kAnaMxTiles * 64;  // first pair of this wave
+
+    double x[kAnaMxTiles], q1[kAnaMxTiles], q2[kAnaMxTiles];
+    double2 stv[kAnaMxTiles];
+    int ls[kAnaMxTiles], tlo[kAnaMxTiles], thi[kAnaMxTiles];
+    float dp[kAnaMxTiles][16], dm[kAnaMxTiles][16];
+    const double *__restrict__ dcol = reinterpret_cast<const double *>(delta) +
+                                      2 * ((int64_t)(col_ok ? map_c : 0) * nrings * (mmax + 1) + m) + (c16 & 1);
+    int mylo = lmax + 1;
+#pragma unroll
+    for (int t = 0; t < kAnaMxTiles; ++t) {
+        const int slot = first + t * 64 + lane;
+        const bool act = slot < nslots;
+        x[t] = act ? sx[slot] : 0.0;
+        ls[t] = act ? lstart[(int64_t)m * nslots + slot] : lmax + 1;
+        stv[t] = act ? state[(int64_t)m * nslots + slot] : make_double2(0.0, 0.0);
+        q1[t] = q2[t] = 0.0;
+        tlo[t] = wave_min(ls[t]);
+        thi[t] = wave_max(ls[t] <= lmax ? ls[t] : m);
+        mylo = min(mylo, tlo[t]);
+#pragma unroll
+        for (int s = 0; s < 16; ++s) {
+            // branch-free: indices clamped into range, unused values selected away
+            const int sl = first + t * 64 + 16 * kq + s;
+            const bool ok = sl < nslots && col_ok;
+            const int slc = min(sl, nslots - 1);
+            const int r2 = rsouth[slc];
+            const double vn = dcol[2 * (int64_t)rn[slc] * (mmax + 1)];
+            const double vs = dcol[2 * (int64_t)max(r2, 0) * (mmax + 1)];
+            const double dn = ok ? vn : 0.0, ds = (ok && r2 >= 0) ? vs : 0.0;
+            dp[t][s] = (float)(dn + ds);
+            dm[t][s] = (float)(dn - ds);
+            // the FP32 operands exist here, before the barrier below: keeping
+            // the FP64 values live past it instead would need 256 registers
+            asm volatile("" ::"v"(dp[t][s]), "v"(dm[t][s]));
+        }
+    }
+    if (lane == 0) wlo[w] = mylo;
+    __syncthreads();
+    int lo = lmax + 1;
+#pragma unroll
+    for (int i = 0; i < kAnaMxWaves; ++i) lo = min(lo, wlo[i]);
+    lo = __builtin_amdgcn_readfirstlane(lo);
+
+    const int64_t base = uniform64((int64_t)m * (2 * lmax + 1 - m) / 2);  // (l, m) lives at base + l
+    const double *__restrict__ al = alpha + base;
+    const int nb = mx_blocks(lmax, m);
+    const int kb0 = lo <= lmax ? (lo - m) / kMxL : nb;
+    auto out_at = [&](int map, int l) -> double2 * {
+        return groups == 1 ? alm + (int64_t)map * nalm + base + l
+                           : part + ((int64_t)map * groups + grp) * nalm + base + l;
+    };
+    // no pair of the group has started before block kb0: those a_lm get no term
+    for (int i = threadIdx.x; i < kb0 * kMxL * kAnaMxMaps; i += kAnaMxThreads) {
+        const int l = m + i / kAnaMxMaps, map = cg * kAnaMxMaps + i % kAnaMxMaps;
+        if (l <= lmax && map < nmaps) *out_at(map, l) = make_double2(0.0, 0.0);
+    }
+
+    for (int kb = kb0; kb < nb; ++kb) {
+        const int l0 = __builtin_amdgcn_readfirstlane(m + kMxL * kb);
+        const bool tail = l0 + kMxL - 1 > lmax;
+        floatx4 acc[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
+#pragma unroll
+        for (int t = 0; t < kAnaMxTiles; ++t) {
+            if (tlo[t] > l0 + kMxL - 1) continue;  // no pair of the tile has started: all q are 0
+            const bool inj = l0 <= thi[t];
+#pragma unroll
+            for (int g = 0; g < kMxL / 8; ++g) {
+                if (inj && ls[t] == l0 + 8 * g) {
+                    q2[t] = stv[t].x;
+                    q1[t] = stv[t].y;
+                }
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    const int l = l0 + 8 * g + i;
+                    const double q = fma(al[l] * x[t], q1[t], -q2[t]);
+                    q2[t] = q1[t];
+                    q1[t] = q;
+                    qs[w][i & 1][4 * g + (i >> 1)][lane] = (tail && l > lmax) ? 0.f : (float)q;
+                }
+            }
+            // LDS operations of one wave complete in order (no barrier needed)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const floatx4 a4 = *reinterpret_cast<const floatx4 *>(&qs[w][p][c16][16 * kq + 4 * u]);
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[j], p ? dm[t][4 * u + j] : dp[t][4 * u + j],
+                                                                      acc[p], 0, 0, 0);
+                }
+            }
+        }
+        // lane l holds rows (k) 4 (l / 16) + r of column l % 16
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[kb & 1][w][p][4 * kq + r][c16] = acc[p][r];
+        __syncthreads();
+        if (threadIdx.x < 2 * kMxHalf * kAnaMxMaps) {
+            const int p = threadIdx.x / (kMxHalf * kAnaMxMaps);
+            const int k = (threadIdx.x / kAnaMxMaps) % kMxHalf, mm = threadIdx.x % kAnaMxMaps;
+            const int l = l0 + 2 * k + p, map = cg * kAnaMxMaps + mm;
+            if (l <= lmax && map < nmaps) {
+                double sr = 0.0, si = 0.0;
+#pragma unroll
+                for (int v = 0; v < kAnaMxWaves; ++v) {
+                    sr += red[kb & 1][v][p][k][2 * mm];
+                    si += red[kb & 1][v][p][k][2 * mm + 1];
+                }
+                if (groups == 1) {
+                    const double c = cfac[base + l];
+                    *out_at(map, l) = make_double2(sr * c, m == 0 ? 0.0 : si * c);
+                } else {
+                    *out_at(map, l) = make_double2(sr, si);  // scaled and Im a_l0 cleared by k_ana_combine
+                }
+            }
+        }
+    }
+}
+
 template <int NCF>
 int launch_syn_mx_t(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm, void *aprime,
                     void *delta, int nmaps, hipStream_t st) {
@@ -217,6 +385,21 @@ int launch_syn_mx_t(const CoefTables &c, const GeomPlan &p, const StartTable &s,
 }
 
 }  // namespace
+
+int launch_leg_ana_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *delta, void *alm,
+                      int nmaps, void *partials, hipStream_t st) {
+    const int groups = (p.nslots + kAnaMxGroup - 1) / kAnaMxGroup;
+    const int ncg = (nmaps + kAnaMxMaps - 1) / kAnaMxMaps;
+    const int64_t gx = (int64_t)groups * padded_m(c.mmax);
+    if (!grid_ok(gx) || ncg > 65535) return SHT_EUNSUPPORTED;
+    if (groups > 1 && !partials) return SHT_EWORKSPACE;
+    hipLaunchKernelGGL(k_leg_ana_mx, dim3((unsigned)gx, (unsigned)ncg), dim3(kAnaMxThreads), 0, st, c.lmax, c.mmax,
+                       p.nslots, p.nrings, nmaps, c.nalm, groups, static_cast<const double2 *>(delta), c.alpha,
+                       c.cfac, s.lstart, s.state, p.slot_x, p.slot_north, p.slot_south, static_cast<double2 *>(alm),
+                       static_cast<double2 *>(partials));
+    SHT_HIP(hipGetLastError());
+    return groups > 1 ? launch_ana_combine(c, nmaps, groups, partials, alm, st) : SHT_OK;
+}
 
 int mx_col_frags(int nmaps) { return nmaps <= 8 ? 1 : nmaps <= 16 ? 2 : 4; }
 

@@ -123,7 +123,6 @@ int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void
     HostGeom h;
     int rc = check_common(lmax, mmax, g, nmaps, flags, false, &h);
     if (rc) return rc;
-    if (flags & SHT_MIXED) return SHT_EUNSUPPORTED;  // synthesis only
     if (!delta || !alm || !aligned(delta, 16) || !aligned(alm, 16)) return SHT_EINVAL;
     const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
     if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps, flags))
@@ -137,6 +136,7 @@ int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void
     if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p)) ||
         (rc = get_start(*c, p, as_stream(stream), &s)))
         return rc;
+    if (flags & SHT_MIXED) return launch_leg_ana_mx(*c, *p, *s, delta, alm, nmaps, workspace, as_stream(stream));
     return launch_leg_ana(*c, *p, *s, delta, alm, nmaps, workspace, as_stream(stream));
 }
 
@@ -175,7 +175,6 @@ int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *
     HostGeom h;
     int rc = check_common(lmax, mmax, g, nmaps, flags, true, &h);
     if (rc) return rc;
-    if (flags & SHT_MIXED) return SHT_EUNSUPPORTED;  // synthesis only
     if (!alm || !map || !aligned(alm, 16) || !aligned(map, 8)) return SHT_EINVAL;
     const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
     const size_t mb = (size_t)h.npix * 8u * nmaps;
@@ -193,6 +192,7 @@ int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *
     char *ws = static_cast<char *>(workspace);
     void *delta = ws, *partials = ws + round256(db);
     if ((rc = launch_fft_ana(*p, mmax, map, delta, nmaps, st))) return rc;
+    if (flags & SHT_MIXED) return launch_leg_ana_mx(*c, *p, *s, delta, alm, nmaps, partials, st);
     return launch_leg_ana(*c, *p, *s, delta, alm, nmaps, partials, st);
 }
 

@@ -50,6 +50,7 @@ constexpr int kCoefPad = 32;
 // Mixed-precision Legendre stage: l runs in blocks of kMxL values counted
 // from m (kMxL / 2 of each parity of l - m); column m has mx_blocks(lmax, m).
 constexpr int kMxL = 32;
+constexpr int kAnaMxGroup = 2048;  // ring pairs per workgroup of the mixed analysis
 __host__ __device__ inline int mx_blocks(int lmax, int m) { return (lmax - m + kMxL) / kMxL; }
 
 // Coefficient tables for one (lmax, mmax) on one device.  Packed (l, m)
@@ -190,6 +191,11 @@ int mx_col_frags(int nmaps);
 size_t mx_aprime_bytes(int lmax, int mmax, int nmaps);
 int launch_leg_syn_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm,
                       void *aprime, void *delta, int nmaps, hipStream_t st);
+int launch_leg_ana_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *delta, void *alm,
+                      int nmaps, void *partials, hipStream_t st);
+// a_lm = c_lm * (sum of the per-group partials, groups in order); Im a_l0 = 0.
+int launch_ana_combine(const CoefTables &c, int nmaps, int groups, const void *partials, void *alm,
+                       hipStream_t st);
 int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, double *map, int nmaps,
                    hipStream_t st);
 int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, int nmaps,

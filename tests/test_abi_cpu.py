@@ -146,11 +146,11 @@ def test_invalid_arguments_rejected_on_host(L):
     assert L.sht_alm2map(-1, 0, g.ref(), a, m, 1, w, big, 0, None) == sht.SHT_EINVAL
     assert L.sht_alm2map(4, 5, g.ref(), a, m, 1, w, big, 0, None) == sht.SHT_EINVAL
     assert L.sht_alm2map(4, 4, g.ref(), a, m, 0, w, big, 0, None) == sht.SHT_EINVAL
-    # flags: unknown bits; SHT_MIXED is synthesis only
+    # flags: unknown bits
     assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, big, 2, None) == sht.SHT_EUNSUPPORTED
     assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, big, 1 << 31, None) == sht.SHT_EUNSUPPORTED
-    assert L.sht_map2alm(4, 4, g.ref(), m, a, 1, w, big, sht.SHT_MIXED, None) == sht.SHT_EUNSUPPORTED
-    assert L.sht_delta2alm(4, 4, g.ref(), m, a, 1, w, big, sht.SHT_MIXED, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_map2alm(4, 4, g.ref(), m, a, 1, w, big, sht.SHT_MIXED | 4, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_delta2alm(4, 4, g.ref(), m, a, 1, w, big, 8, None) == sht.SHT_EUNSUPPORTED
     # null and misaligned pointers
     assert L.sht_alm2map(4, 4, g.ref(), None, m, 1, w, big, 0, None) == sht.SHT_EINVAL
     assert L.sht_alm2map(4, 4, g.ref(), a, None, 1, w, big, 0, None) == sht.SHT_EINVAL

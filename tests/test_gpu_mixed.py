@@ -1,11 +1,12 @@
-"""GPU parity of the mixed-precision synthesis (SHT_MIXED) against the oracle.
+"""GPU parity of the mixed-precision transforms (SHT_MIXED) against the oracle.
 
-The recurrence stays FP64 and only lambda_lm, c_lm a_lm and the sum over l
-are FP32, so the bar is the batched-mixed target: relative RMS <= 1e-6 of
-every map against the FP64 oracle (and against the FP64 HIP path, itself
-pinned to 1e-12).  Batches of 1, 3, 12 and 40 maps take the three column
-widths of the kernel (8, 16 and 32 maps per wave) and a partly filled last
-column group.
+The recurrence stays FP64 and only lambda_lm, the c-scaled a_lm (synthesis)
+or the pair sums of Delta (analysis), and the matrix-core sums are FP32, so
+the bar is the batched-mixed target: relative RMS <= 1e-6 of every map (or
+a_lm set) against the FP64 oracle and against the FP64 HIP path, itself
+pinned to 1e-12.  Synthesis batches of 1, 3, 12 and 40 maps take the three
+column widths of its kernel (8, 16 and 32 maps per wave) and a partly filled
+last column group; analysis groups 8 maps and 2048 ring pairs per workgroup.
 """
 import sys
 
@@ -125,16 +126,60 @@ def test_mixed_is_deterministic_and_batch_independent(sht):
         assert relrms(part[i], full[32 + i]) <= MX_TOL
 
 
-def test_mixed_analysis_unsupported(sht):
-    lmax, g = 8, si.healpix(4)
-    s = dev(si.random_map(g, 1))
-    with pytest.raises(sht.ShtError) as e:
-        sht.map2alm(s, g, lmax, flags=sht.SHT_MIXED)
-    assert e.value.code == sht.SHT_EUNSUPPORTED
-    d = dev(np.zeros((g.nrings, lmax + 1), dtype=np.complex128))
-    with pytest.raises(sht.ShtError) as e:
-        sht.delta2alm(d, g, lmax, flags=sht.SHT_MIXED)
-    assert e.value.code == sht.SHT_EUNSUPPORTED
+ANA_CASES = [
+    # (name, geometry builder, lmax, mmax, nmaps)
+    ("gl0_1", lambda: si.gauss_legendre(1, 1), 0, 0, 1),
+    ("gl7_mless_3", lambda: si.gauss_legendre(8, 9), 7, 4, 3),
+    ("gl64_odd_9", lambda: si.gauss_legendre(65, 129), 64, 64, 9),
+    ("hp8_alias_8", lambda: si.healpix(8), 40, 40, 8),
+    ("hp32_ragged_17", lambda: si.healpix(32), 77, 61, 17),
+    ("random_poles_5", MX_CASES[7][1], 12, 12, 5),
+    ("gl_bluestein_12", lambda: si.gauss_legendre(70, 139), 69, 69, 12),
+    # 2300 unpaired rings: two groups of 2048 pairs, partial sums combined
+    ("random2300_3", lambda: si._pack(np.sort(np.random.default_rng(11).uniform(0, np.pi, 2300)),
+                                      np.full(2300, 7, dtype=np.int32), np.zeros(2300),
+                                      np.random.default_rng(12).uniform(0.1, 1.0, 2300), "r2300"), 24, 24, 3),
+]
+
+
+@pytest.mark.parametrize("case", ANA_CASES, ids=[c[0] for c in ANA_CASES])
+def test_mixed_map2alm_small(sht, case):
+    name, mk, lmax, mmax, nmaps = case
+    g = mk()
+    maps = np.stack([si.random_map(g, 800 + i) for i in range(nmaps)])
+    say(f"mixed map2alm {name} lmax={lmax} mmax={mmax} nrings={g.nrings} nmaps={nmaps}")
+    got = host(sht.map2alm(dev(maps), g, lmax, mmax, flags=sht.SHT_MIXED))
+    f64 = host(sht.map2alm(dev(maps), g, lmax, mmax))
+    for i in range(nmaps):
+        ref = oracle.map2alm(lmax, mmax, g, maps[i])
+        assert relrms(got[i], ref) <= MX_TOL, (name, i, relrms(got[i], ref))
+        assert relrms(got[i], f64[i]) <= MX_TOL, (name, i, relrms(got[i], f64[i]))
+        assert np.all(got[i][: lmax + 1].imag == 0.0)
+
+
+def test_mixed_delta2alm(sht):
+    lmax, mmax, g, nmaps = 77, 61, si.healpix(32), 10
+    rng = np.random.default_rng(900)
+    d = rng.standard_normal((nmaps, g.nrings, mmax + 1)) + 1j * rng.standard_normal((nmaps, g.nrings, mmax + 1))
+    say(f"mixed delta2alm hp32 lmax={lmax} mmax={mmax} nmaps={nmaps}")
+    got = host(sht.delta2alm(dev(d), g, lmax, mmax, flags=sht.SHT_MIXED))
+    for i in range(nmaps):
+        ref = oracle.delta2alm(lmax, mmax, g, d[i])
+        assert relrms(got[i], ref) <= MX_TOL, (i, relrms(got[i], ref))
+
+
+def test_mixed_round_trip_gl(sht):
+    """On a Gauss-Legendre grid analysis inverts synthesis for band-limited
+    a_lm (exact quadrature): mixed there and back stays within the bar."""
+    lmax, nmaps = 63, 12
+    g = si.gauss_legendre(lmax + 1, 2 * lmax + 1)
+    a = batch(lmax, lmax, nmaps, 950)
+    a[:, : lmax + 1] = a[:, : lmax + 1].real
+    say("mixed round trip GL lmax=63 nmaps=12")
+    mp = sht.alm2map(dev(a), g, lmax, flags=sht.SHT_MIXED)
+    back = host(sht.map2alm(mp, g, lmax, flags=sht.SHT_MIXED))
+    for i in range(nmaps):
+        assert relrms(back[i], a[i]) <= 2 * MX_TOL, (i, relrms(back[i], a[i]))
 
 
 def test_mixed_full_size_healpix1024_lmax2048_64maps(sht):
@@ -162,3 +207,18 @@ def test_mixed_full_size_healpix1024_lmax2048_64maps(sht):
     for r in rings:
         sl = slice(g.ofs[r], g.ofs[r] + g.nphi[r])
         assert relrms(g0[sl], ref[sl]) <= 10 * MX_TOL, (r, relrms(g0[sl], ref[sl]))
+    # analysis of the 64 FP64 maps back: mixed against FP64 on three maps
+    # (all a_lm) and against the oracle on sampled m of map 0
+    say("mixed map2alm full size: healpix 1024 lmax 2048 nmaps 64")
+    maps = sht.alm2map(alm, g, lmax)
+    back = sht.map2alm(maps, g, lmax, flags=sht.SHT_MIXED)
+    for i in (0, 37, 63):
+        ref = host(sht.map2alm(maps[i].contiguous(), g, lmax))
+        bi = host(back[i])
+        assert relrms(bi, ref) <= MX_TOL, (i, relrms(bi, ref))
+    ms = [0, 1, 333, 1024, 2047, 2048]
+    ref = oracle.map2alm(lmax, lmax, g, host(maps[0]), ms=ms)
+    b0 = host(back[0])
+    for m in ms:
+        idx = si.alm_index(np.arange(m, lmax + 1), m, lmax)
+        assert relrms(b0[idx], ref[idx]) <= 10 * MX_TOL, (m, relrms(b0[idx], ref[idx]))
