@@ -360,7 +360,7 @@ __device__ __forceinline__ int fold_columns(double2 *__restrict__ t, int n, int 
 // rows of mmax+1 phased terms used when the ring folds many m per bin,
 // n < (mmax+1)/2.
 template <int MAXL, int NT>
-__global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t npix, int fold_rows,
+__global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t npix, int nmaps, int fold_rows,
                                                 const int2 *__restrict__ jobs,
                                                 const int32_t *__restrict__ ring_desc,
                                                 const FftDesc *__restrict__ descs,
@@ -370,9 +370,11 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t np
                                                 double *__restrict__ map) {
     extern __shared__ double2 lds[];
     double2 *tlo = lds, *thi = lds + kTwLo, *buf = lds + tw_entries<MAXL>();
-    const int2 job = jobs[blockIdx.x];
+    // maps vary fastest: the workgroups of one ring's maps run together and
+    // share its tables (Bluestein chirp and kernel) through L2
+    const int2 job = jobs[blockIdx.x / nmaps];
     const int ra = job.x, rb = job.y;
-    const int mp = blockIdx.y;
+    const int mp = blockIdx.x % nmaps;
     const FftDesc *d = descs + ring_desc[ra];
     const int N = d->n, L = d->L;
     load_twiddles<NT>(tlo, thi, d->tw, L);
@@ -434,7 +436,7 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t np
 }
 
 template <int MAXL, int NT>
-__global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t npix,
+__global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t npix, int nmaps,
                                                 const int2 *__restrict__ jobs,
                                                 const int32_t *__restrict__ ring_desc,
                                                 const FftDesc *__restrict__ descs,
@@ -445,9 +447,11 @@ __global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t np
                                                 double2 *__restrict__ delta) {
     extern __shared__ double2 lds[];
     double2 *tlo = lds, *thi = lds + kTwLo, *buf = lds + tw_entries<MAXL>();
-    const int2 job = jobs[blockIdx.x];
+    // maps vary fastest: the workgroups of one ring's maps run together and
+    // share its tables (Bluestein chirp and kernel) through L2
+    const int2 job = jobs[blockIdx.x / nmaps];
     const int ra = job.x, rb = job.y;
-    const int mp = blockIdx.y;
+    const int mp = blockIdx.x % nmaps;
     const FftDesc *d = descs + ring_desc[ra];
     const int N = d->n;
     load_twiddles<NT>(tlo, thi, d->tw, d->L);
@@ -520,8 +524,8 @@ int launch_syn_class(const GeomPlan &p, int c, int mmax, const void *delta, doub
     // the small-length class keeps the phased terms in LDS when they fit
     const int fold_rows = (MAXL <= 1024 && base + rows <= kMaxLds) ? 1 : 0;
     const size_t lds = base + (fold_rows ? rows : 0);
-    hipLaunchKernelGGL((k_fft_syn<MAXL, NT>), dim3((unsigned)p.class_count[c], (unsigned)nmaps), dim3(NT), lds,
-                       st, mmax, p.nrings, p.npix, fold_rows, p.class_jobs[c], p.ring_desc, p.descs, p.phi0,
+    hipLaunchKernelGGL((k_fft_syn<MAXL, NT>), dim3((unsigned)((int64_t)p.class_count[c] * nmaps)), dim3(NT), lds,
+                       st, mmax, p.nrings, p.npix, nmaps, fold_rows, p.class_jobs[c], p.ring_desc, p.descs, p.phi0,
                        p.ofs, static_cast<const double2 *>(delta), map);
     return SHT_OK;
 }
@@ -531,8 +535,8 @@ void launch_ana_class(const GeomPlan &p, int c, int mmax, const double *map, voi
                       hipStream_t st) {
     constexpr int NT = fft_threads<MAXL>();
     const size_t lds = (size_t)(tw_entries<MAXL>() + padded_len<MAXL>()) * sizeof(double2);
-    hipLaunchKernelGGL((k_fft_ana<MAXL, NT>), dim3((unsigned)p.class_count[c], (unsigned)nmaps), dim3(NT), lds,
-                       st, mmax, p.nrings, p.npix, p.class_jobs[c], p.ring_desc, p.descs, p.phi0, p.weight,
+    hipLaunchKernelGGL((k_fft_ana<MAXL, NT>), dim3((unsigned)((int64_t)p.class_count[c] * nmaps)), dim3(NT), lds,
+                       st, mmax, p.nrings, p.npix, nmaps, p.class_jobs[c], p.ring_desc, p.descs, p.phi0, p.weight,
                        p.ofs, map, static_cast<double2 *>(delta));
 }
 
@@ -541,10 +545,17 @@ static_assert(kFftClasses == 4 && kFftClassLen[0] == 1024 && kFftClassLen[3] == 
 
 }  // namespace
 
+// one workgroup per (job, map) of a class
+static bool grid_fits(const GeomPlan &p, int nmaps) {
+    for (int c = 0; c < kFftClasses; ++c)
+        if ((int64_t)p.class_count[c] * nmaps >= (int64_t)INT32_MAX) return false;
+    return true;
+}
+
 // The length classes are independent: they run concurrently, the largest on
 // the caller's stream and the others on side streams (fork_join).
 int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, double *map, int nmaps, hipStream_t st) {
-    if (nmaps > 65535) return SHT_EUNSUPPORTED;
+    if (nmaps > 65535 || !grid_fits(p, nmaps)) return SHT_EUNSUPPORTED;
     int rc = set_lds_attr();
     if (rc) return rc;
     int cls[kFftClasses], n = 0;
@@ -563,7 +574,7 @@ int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, double *map, 
 }
 
 int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, int nmaps, hipStream_t st) {
-    if (nmaps > 65535) return SHT_EUNSUPPORTED;
+    if (nmaps > 65535 || !grid_fits(p, nmaps)) return SHT_EUNSUPPORTED;
     if (!p.weight) return SHT_EINVAL;
     int rc = set_lds_attr();
     if (rc) return rc;
