@@ -28,6 +28,8 @@
 // one-to-one assignment of k to (lane group, step) gives the same sum), so
 // each operand of four steps is one 16-byte load; k_prescale_mx stores a'
 // tiled to match: [col group][l-block of column m][parity][col][k].
+#include <type_traits>
+
 #include "k_device.h"
 
 namespace sht {
@@ -129,31 +131,40 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
 
         // 32 recurrence steps, written as FP32 to this lane's LDS rows; starts
         // lie at m + kStartStep j, so only the four 8-step boundaries inject
-        const bool inj = l0 <= hi;
-        const bool tail = l0 + kMxL - 1 > lmax;
+        // blocks where pairs start (injection) or that pass lmax take the
+        // general path, all others the one without selects
+        auto steps = [&](auto general) {
 #pragma unroll
-        for (int g = 0; g < kMxL / 8; ++g) {
-            if (inj && ls == l0 + 8 * g) {
-                q2 = stv.x;
-                q1 = stv.y;
-            }
-            float pe[4], po[4];
+            for (int g = 0; g < kMxL / 8; ++g) {
+                if constexpr (decltype(general)::value) {
+                    if (ls == l0 + 8 * g) {
+                        q2 = stv.x;
+                        q1 = stv.y;
+                    }
+                }
+                float pe[4], po[4];
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int l = l0 + 8 * g + i;
-                const double q = fma(al[l] * x, q1, -q2);
-                q2 = q1;
-                q1 = q;
-                // past lmax alpha runs into the next column: those q are not used
-                const float f = (tail && l > lmax) ? 0.f : (float)q;
-                if (i & 1)
-                    po[i >> 1] = f;
-                else
-                    pe[i >> 1] = f;
+                for (int i = 0; i < 8; ++i) {
+                    const int l = l0 + 8 * g + i;
+                    const double q = fma(al[l] * x, q1, -q2);
+                    q2 = q1;
+                    q1 = q;
+                    // past lmax alpha runs into the next column: those q are not used
+                    float f = (float)q;
+                    if constexpr (decltype(general)::value) f = l > lmax ? 0.f : f;
+                    if (i & 1)
+                        po[i >> 1] = f;
+                    else
+                        pe[i >> 1] = f;
+                }
+                pt[w][0][lane][g] = floatx4{pe[0], pe[1], pe[2], pe[3]};
+                pt[w][1][lane][g] = floatx4{po[0], po[1], po[2], po[3]};
             }
-            pt[w][0][lane][g] = floatx4{pe[0], pe[1], pe[2], pe[3]};
-            pt[w][1][lane][g] = floatx4{po[0], po[1], po[2], po[3]};
-        }
+        };
+        if (l0 <= hi || l0 + kMxL - 1 > lmax)
+            steps(std::true_type{});
+        else
+            steps(std::false_type{});
         // LDS operations of one wave complete in order: the reads below see
         // the writes above, and the next block's writes follow these reads
         floatx4 bv[2][4];
@@ -201,7 +212,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
 // mirror identity used by the FP64 kernels), col = 2 map + (re, im).  One
 // workgroup of kAnaMxWaves waves holds kAnaMxGroup ring pairs of one m (a
 // group; more pairs take several groups whose partial sums k_ana_combine
-// adds) and kAnaMxMaps maps.  Wave w owns kAnaMxTiles tiles of 64 pairs; its
+// adds) and kAnaMxMaps maps.  Wave w owns kAnaMxTiles tiles of 64 pairs,
+// spread over the group's latitudes; its
 // D+ and D- operands stay in registers for the whole kernel (rounded to FP32
 // once).  Per l-block each wave runs the recurrences of its tiles (one pair
 // per lane), stages q (FP32) in its LDS tile k-major, and contracts over its
@@ -242,7 +254,10 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
     const int c16 = lane & 15, kq = lane >> 4;
     const int map_c = cg * kAnaMxMaps + (c16 >> 1);  // this lane's column: map and part
     const bool col_ok = map_c < nmaps;
-    const int first = grp * kAnaMxGroup + w * kAnaMxTiles * 64;  // first pair of this wave
+    // tile t of wave w holds pairs from (t * kAnaMxWaves + w) * 64 on: pairs are
+    // sorted by latitude and start late near the poles, so every wave gets
+    // tiles from the whole range and the waves' work per block stays even
+    auto tile0 = [&](int t) { return grp * kAnaMxGroup + (t * kAnaMxWaves + w) * 64; };
 
     double x[kAnaMxTiles], q1[kAnaMxTiles], q2[kAnaMxTiles];
     double2 stv[kAnaMxTiles];
@@ -253,7 +268,7 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
     int mylo = lmax + 1;
 #pragma unroll
     for (int t = 0; t < kAnaMxTiles; ++t) {
-        const int slot = first + t * 64 + lane;
+        const int slot = tile0(t) + lane;
         const bool act = slot < nslots;
         x[t] = act ? sx[slot] : 0.0;
         ls[t] = act ? lstart[(int64_t)m * nslots + slot] : lmax + 1;
@@ -265,7 +280,7 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
             // branch-free: indices clamped into range, unused values selected away
-            const int sl = first + t * 64 + 16 * kq + s;
+            const int sl = tile0(t) + 16 * kq + s;
             const bool ok = sl < nslots && col_ok;
             const int slc = min(sl, nslots - 1);
             const int r2 = rsouth[slc];
@@ -307,22 +322,33 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
 #pragma unroll
         for (int t = 0; t < kAnaMxTiles; ++t) {
             if (tlo[t] > l0 + kMxL - 1) continue;  // no pair of the tile has started: all q are 0
-            const bool inj = l0 <= thi[t];
+            // 32 steps; blocks where pairs start (injection) or that pass lmax
+            // take the general path, all others the one without selects
+            auto steps = [&](auto general) {
 #pragma unroll
-            for (int g = 0; g < kMxL / 8; ++g) {
-                if (inj && ls[t] == l0 + 8 * g) {
-                    q2[t] = stv[t].x;
-                    q1[t] = stv[t].y;
-                }
+                for (int g = 0; g < kMxL / 8; ++g) {
+                    if constexpr (decltype(general)::value) {
+                        if (ls[t] == l0 + 8 * g) {
+                            q2[t] = stv[t].x;
+                            q1[t] = stv[t].y;
+                        }
+                    }
 #pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    const int l = l0 + 8 * g + i;
-                    const double q = fma(al[l] * x[t], q1[t], -q2[t]);
-                    q2[t] = q1[t];
-                    q1[t] = q;
-                    qs[w][i & 1][4 * g + (i >> 1)][lane] = (tail && l > lmax) ? 0.f : (float)q;
+                    for (int i = 0; i < 8; ++i) {
+                        const int l = l0 + 8 * g + i;
+                        const double q = fma(al[l] * x[t], q1[t], -q2[t]);
+                        q2[t] = q1[t];
+                        q1[t] = q;
+                        float f = (float)q;
+                        if constexpr (decltype(general)::value) f = l > lmax ? 0.f : f;
+                        qs[w][i & 1][4 * g + (i >> 1)][lane] = f;
+                    }
                 }
-            }
+            };
+            if (tail || l0 <= thi[t])
+                steps(std::true_type{});
+            else
+                steps(std::false_type{});
             // LDS operations of one wave complete in order (no barrier needed)
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
