@@ -88,6 +88,31 @@ __device__ __forceinline__ double2 phase_exp(int m, double phi0) {
     return make_double2(cs, sn);
 }
 
+// e^{i m phi0} of one ring from two LDS tables filled per workgroup with
+// phase_exp: lo[b] = e^{i b phi0} (b < 64) and hi[h] = e^{i 64 h phi0}, so
+// e^{i m phi0} = hi[m / 64] lo[m % 64] (one complex product, about one more
+// rounding than phase_exp) for m < 64 * kPhHiMax.  With hi == nullptr the
+// phase is evaluated directly.
+constexpr int kPhLo = 64;
+constexpr int kPhHiMax = 64;
+__host__ __device__ constexpr int phase_hi_entries(int mmax) { return mmax / kPhLo + 1; }
+struct Phase {
+    const double2 *lo, *hi;
+    double phi0;
+    __device__ __forceinline__ double2 operator()(int m) const {
+        if (!hi) return phase_exp(m, phi0);
+        const double2 a = hi[m / kPhLo], b = lo[m % kPhLo];
+        return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
+    }
+};
+template <int NT>
+__device__ __forceinline__ Phase load_phases(double2 *tab, int mmax, double phi0) {
+    const int nh = phase_hi_entries(mmax);
+    for (int t = threadIdx.x; t < kPhLo + nh; t += NT)
+        tab[t] = phase_exp(t < kPhLo ? t : (t - kPhLo) * kPhLo, phi0);
+    return Phase{tab, tab + kPhLo, phi0};
+}
+
 // Forward-sign butterflies of radix 2, 3, 4, 5, 8 in registers, with the
 // roots of unity as constants: cos(2pi/5) = (sqrt5-1)/4, cos(4pi/5) =
 // -(sqrt5+1)/4, sin(2pi/5), sin(4pi/5), sqrt(3)/2 and 1/sqrt(2), each rounded
@@ -296,14 +321,14 @@ __device__ __forceinline__ double2 input_point(double2 v, const FftDesc *__restr
 
 // c_k of one ring: sum over m = k mod n (m <= mmax) of w_m Delta_m e^{i m phi0}
 __device__ __forceinline__ double2 fold_bin(const double2 *__restrict__ D, int k, int n, int mmax,
-                                            double ph0) {
+                                            const Phase &ph) {
     double cr = 0.0, ci = 0.0;
     for (int m = k; m <= mmax; m += n) {
         const double2 dv = D[m];
         if (m == 0) {
             cr += dv.x;
         } else {
-            const double2 e = phase_exp(m, ph0);
+            const double2 e = ph(m);
             cr += 2.0 * fma(dv.x, e.x, -dv.y * e.y);
             ci += 2.0 * fma(dv.x, e.y, dv.y * e.x);
         }
@@ -313,14 +338,14 @@ __device__ __forceinline__ double2 fold_bin(const double2 *__restrict__ D, int k
 
 // phased terms of one ring for m = tid, tid+NT, ...: w_m Delta_m e^{i m phi0}
 template <int NT>
-__device__ __forceinline__ void phased_terms(const double2 *__restrict__ D, int mmax, double ph0,
+__device__ __forceinline__ void phased_terms(const double2 *__restrict__ D, int mmax, const Phase &ph,
                                              double2 *__restrict__ out) {
     for (int m = threadIdx.x; m <= mmax; m += NT) {
         const double2 dv = D[m];
         if (m == 0) {
             out[0] = make_double2(dv.x, 0.0);
         } else {
-            const double2 e = phase_exp(m, ph0);
+            const double2 e = ph(m);
             out[m] = make_double2(2.0 * fma(dv.x, e.x, -dv.y * e.y), 2.0 * fma(dv.x, e.y, dv.y * e.x));
         }
     }
@@ -360,7 +385,7 @@ __device__ __forceinline__ int fold_columns(double2 *__restrict__ t, int n, int 
 // rows of mmax+1 phased terms used when the ring folds many m per bin,
 // n < (mmax+1)/2.
 template <int MAXL, int NT>
-__global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t npix, int nmaps, int fold_rows,
+__global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t npix, int nmaps, int fold_rows, int ph_tab,
                                                 const int2 *__restrict__ jobs,
                                                 const int32_t *__restrict__ ring_desc,
                                                 const FftDesc *__restrict__ descs,
@@ -381,13 +406,20 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t np
     const double2 *__restrict__ Da = delta + ((int64_t)mp * nrings + ra) * (mmax + 1);
     const double2 *__restrict__ Db = delta + ((int64_t)mp * nrings + (rb >= 0 ? rb : ra)) * (mmax + 1);
     const double pa = phi0[ra], pb = rb >= 0 ? phi0[rb] : 0.0;
+    Phase pha{nullptr, nullptr, pa}, phb{nullptr, nullptr, pb};
+    if (ph_tab) {
+        double2 *tab = buf + padded_len<MAXL>() + (fold_rows ? 2 * (mmax + 1) : 0);
+        pha = load_phases<NT>(tab, mmax, pa);
+        if (rb >= 0) phb = load_phases<NT>(tab + kPhLo + phase_hi_entries(mmax), mmax, pb);
+        __syncthreads();
+    }
     const bool lds_fold = fold_rows && (2 * N < mmax + 1);
     int lim = mmax;  // last index of the phased-term rows that the bins fold
     if (lds_fold) {
         // all threads evaluate phases; short rings first sum the rows in columns
         double2 *ta = buf + pd(L), *tb = buf + pd(L) + (mmax + 1);
-        phased_terms<NT>(Da, mmax, pa, ta);
-        if (rb >= 0) phased_terms<NT>(Db, mmax, pb, tb);
+        phased_terms<NT>(Da, mmax, pha, ta);
+        if (rb >= 0) phased_terms<NT>(Db, mmax, phb, tb);
         __syncthreads();
         if (N <= NT) {
             lim = fold_columns<NT>(ta, N, mmax);
@@ -408,11 +440,11 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t np
                 b1 = fold_terms(tb, kn, N, lim);
             }
         } else {
-            a0 = fold_bin(Da, k, N, mmax, pa);
-            a1 = fold_bin(Da, kn, N, mmax, pa);
+            a0 = fold_bin(Da, k, N, mmax, pha);
+            a1 = fold_bin(Da, kn, N, mmax, pha);
             if (rb >= 0) {
-                b0 = fold_bin(Db, k, N, mmax, pb);
-                b1 = fold_bin(Db, kn, N, mmax, pb);
+                b0 = fold_bin(Db, k, N, mmax, phb);
+                b1 = fold_bin(Db, kn, N, mmax, phb);
             }
         }
         // h_k = (c_k + conj c_{n-k}) / 2, h_{n-k} = conj h_k
@@ -436,7 +468,7 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t np
 }
 
 template <int MAXL, int NT>
-__global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t npix, int nmaps,
+__global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t npix, int nmaps, int ph_tab,
                                                 const int2 *__restrict__ jobs,
                                                 const int32_t *__restrict__ ring_desc,
                                                 const FftDesc *__restrict__ descs,
@@ -455,14 +487,21 @@ __global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t np
     const FftDesc *d = descs + ring_desc[ra];
     const int N = d->n;
     load_twiddles<NT>(tlo, thi, d->tw, d->L);
+    const double pa = phi0[ra], wa = weight[ra];
+    const double pb = rb >= 0 ? phi0[rb] : 0.0, wb = rb >= 0 ? weight[rb] : 0.0;
+    // phase tables: visible after the barrier that follows the input below
+    Phase pha{nullptr, nullptr, pa}, phb{nullptr, nullptr, pb};
+    if (ph_tab) {
+        double2 *tab = buf + padded_len<MAXL>();
+        pha = load_phases<NT>(tab, mmax, pa);
+        if (rb >= 0) phb = load_phases<NT>(tab + kPhLo + phase_hi_entries(mmax), mmax, pb);
+    }
     const double *ina = map + (int64_t)mp * npix + ofs[ra];
     const double *inb = map + (int64_t)mp * npix + (rb >= 0 ? ofs[rb] : 0);
     for (int j = threadIdx.x; j < N; j += NT)
         buf[pd(j)] = input_point(make_double2(ina[j], rb >= 0 ? inb[j] : 0.0), d, j);
     __syncthreads();
     transform<MAXL, NT>(buf, d, TwLds{tlo, thi});
-    const double pa = phi0[ra], wa = weight[ra];
-    const double pb = rb >= 0 ? phi0[rb] : 0.0, wb = rb >= 0 ? weight[rb] : 0.0;
     double2 *Da = delta + ((int64_t)mp * nrings + ra) * (mmax + 1);
     double2 *Db = delta + ((int64_t)mp * nrings + (rb >= 0 ? rb : ra)) * (mmax + 1);
     for (int m = threadIdx.x; m <= mmax; m += NT) {
@@ -471,11 +510,11 @@ __global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t np
         // S_a = (Z_k + conj Z_{n-k}) / 2, S_b = (Z_k - conj Z_{n-k}) / (2i)
         const double2 Sa = make_double2(0.5 * (Z.x + Zn.x), 0.5 * (Z.y - Zn.y));
         const double2 Sb = make_double2(0.5 * (Z.y + Zn.y), -0.5 * (Z.x - Zn.x));
-        const double2 ea = phase_exp(m, pa);
+        const double2 ea = pha(m);
         // w * conj(e) * S
         Da[m] = make_double2(wa * fma(Sa.x, ea.x, Sa.y * ea.y), wa * fma(Sa.y, ea.x, -Sa.x * ea.y));
         if (rb >= 0) {
-            const double2 eb = phase_exp(m, pb);
+            const double2 eb = phb(m);
             Db[m] = make_double2(wb * fma(Sb.x, eb.x, Sb.y * eb.y), wb * fma(Sb.y, eb.x, -Sb.x * eb.y));
         }
     }
@@ -515,6 +554,13 @@ int set_lds_attr() {
 
 static_assert((tw_entries<kMaxFftLen>() + padded_len<kMaxFftLen>()) * sizeof(double2) <= kMaxLds, "largest class fits LDS");
 
+// the phase tables of a job's two rings; used for mmax < 64 kPhHiMax when
+// they fit next to the other LDS data
+size_t phase_table_bytes(int mmax) { return 2 * (size_t)(kPhLo + phase_hi_entries(mmax)) * sizeof(double2); }
+int phase_tables_fit(int mmax, size_t lds) {
+    return phase_hi_entries(mmax) <= kPhHiMax && lds + phase_table_bytes(mmax) <= (size_t)kMaxLds;
+}
+
 template <int MAXL>
 int launch_syn_class(const GeomPlan &p, int c, int mmax, const void *delta, double *map, int nmaps,
                      hipStream_t st) {
@@ -523,9 +569,11 @@ int launch_syn_class(const GeomPlan &p, int c, int mmax, const void *delta, doub
     const size_t rows = 2 * (size_t)(mmax + 1) * sizeof(double2);
     // the small-length class keeps the phased terms in LDS when they fit
     const int fold_rows = (MAXL <= 1024 && base + rows <= kMaxLds) ? 1 : 0;
-    const size_t lds = base + (fold_rows ? rows : 0);
+    size_t lds = base + (fold_rows ? rows : 0);
+    const int ph_tab = phase_tables_fit(mmax, lds);
+    if (ph_tab) lds += phase_table_bytes(mmax);
     hipLaunchKernelGGL((k_fft_syn<MAXL, NT>), dim3((unsigned)((int64_t)p.class_count[c] * nmaps)), dim3(NT), lds,
-                       st, mmax, p.nrings, p.npix, nmaps, fold_rows, p.class_jobs[c], p.ring_desc, p.descs, p.phi0,
+                       st, mmax, p.nrings, p.npix, nmaps, fold_rows, ph_tab, p.class_jobs[c], p.ring_desc, p.descs, p.phi0,
                        p.ofs, static_cast<const double2 *>(delta), map);
     return SHT_OK;
 }
@@ -534,9 +582,11 @@ template <int MAXL>
 void launch_ana_class(const GeomPlan &p, int c, int mmax, const double *map, void *delta, int nmaps,
                       hipStream_t st) {
     constexpr int NT = fft_threads<MAXL>();
-    const size_t lds = (size_t)(tw_entries<MAXL>() + padded_len<MAXL>()) * sizeof(double2);
+    size_t lds = (size_t)(tw_entries<MAXL>() + padded_len<MAXL>()) * sizeof(double2);
+    const int ph_tab = phase_tables_fit(mmax, lds);
+    if (ph_tab) lds += phase_table_bytes(mmax);
     hipLaunchKernelGGL((k_fft_ana<MAXL, NT>), dim3((unsigned)((int64_t)p.class_count[c] * nmaps)), dim3(NT), lds,
-                       st, mmax, p.nrings, p.npix, nmaps, p.class_jobs[c], p.ring_desc, p.descs, p.phi0, p.weight,
+                       st, mmax, p.nrings, p.npix, nmaps, ph_tab, p.class_jobs[c], p.ring_desc, p.descs, p.phi0, p.weight,
                        p.ofs, map, static_cast<double2 *>(delta));
 }
 
