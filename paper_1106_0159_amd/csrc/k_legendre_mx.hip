@@ -115,19 +115,32 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
 
     double q1 = 0.0, q2 = 0.0;  // a pair carries zeros until it starts
     const int kb0 = lo <= lmax ? (lo - m) / kMxL : nb;
+    // a' operands one block ahead: those of block kb are loaded while block
+    // kb - 1 runs (the index is clamped, so the load after the last block
+    // re-reads it and stays in bounds)
+    floatx4 an[2][NCF];
+    auto load_a = [&](int kb) {
+        const float *__restrict__ t = apm + (int64_t)min(kb, nb - 1) * kTile;
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int cf = 0; cf < NCF; ++cf)
+                an[p][cf] = *reinterpret_cast<const floatx4 *>(t + p * NC * kMxHalf + (cf * 16 + c16) * kMxHalf + kq * 4);
+    };
+    if (kb0 < nb) load_a(kb0);
     for (int kb = kb0; kb < nb; ++kb) {
         // uniform; restated so that the compiler keeps alpha on scalar loads
         // (inside the injection branch it may otherwise use the equal lane
         // value ls in its place)
         const int l0 = __builtin_amdgcn_readfirstlane(m + kMxL * kb);
-        // a' operands of this block (issued first, used after the recurrence)
         floatx4 av[2][NCF];
-        const float *__restrict__ t = apm + (int64_t)kb * kTile;
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
-            for (int cf = 0; cf < NCF; ++cf)
-                av[p][cf] = *reinterpret_cast<const floatx4 *>(t + p * NC * kMxHalf + (cf * 16 + c16) * kMxHalf + kq * 4);
+            for (int cf = 0; cf < NCF; ++cf) av[p][cf] = an[p][cf];
+        load_a(kb + 1);
+        // compiler-only fence: the prefetch stays here, ahead of this block's work
+        asm volatile("" ::: "memory");
 
         // 32 recurrence steps, written as FP32 to this lane's LDS rows; starts
         // lie at m + kStartStep j, so only the four 8-step boundaries inject
