@@ -121,8 +121,8 @@ def cpu_baseline(g, lmax, a, mp, target_s: float = 12.0):
 
 def batched_mixed(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a_fp64):
     """One batch of power-law maps through both transforms with SHT_MIXED
-    (FP64 recurrence, FP32 matrix-core contraction; Delta and FFTs FP64),
-    through the four stage entry points as in the plain step, HIP events on
+    (FP64 recurrence, FP32 matrix-core contraction; Delta and FFTs FP64,
+    Delta map-minor in synthesis), through the four stage entry points, HIP events on
     the launch stream around each stage.  Map 0 of the batch is the map of the
     plain FP64 step: the relative RMS differences of its map and of its
     analysed a_lm to the FP64 results are reported."""
@@ -132,12 +132,16 @@ def batched_mixed(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a
     alm = torch.empty((nmaps, si.nalm(lmax, lmax)), dtype=torch.complex128, device=dev)
     for i in range(nmaps):
         alm[i] = torch.from_numpy(si.powerlaw_alm(lmax, lmax, si.config_seed(2, i))).to(dev)
-    delta = torch.empty((nmaps, g.nrings, lmax + 1), dtype=torch.complex128, device=dev)
-    delta_s = torch.empty_like(delta)
+    # Delta as sht_alm2map / sht_map2alm keep it with SHT_MIXED (the stage
+    # calls give the same bits as the combined ones): map-minor,
+    # [nrings][mmax+1][nmaps], in synthesis and ring-major in analysis
+    delta = torch.empty((g.nrings, lmax + 1, nmaps), dtype=torch.complex128, device=dev)
+    delta_s = torch.empty((nmaps, g.nrings, lmax + 1), dtype=torch.complex128, device=dev)
     mp = torch.zeros((nmaps, g.npix), dtype=torch.float64, device=dev)
     a_out = torch.empty_like(alm)
     ws = sht.workspace(lmax, lmax, gh, nmaps, dev, sht.SHT_MIXED)
-    F = sht.SHT_MIXED
+    MM = sht.SHT_DELTA_MAP_MINOR
+    F = sht.SHT_MIXED | MM
 
     def step(ev=None):
         def mark(i):
@@ -146,11 +150,11 @@ def batched_mixed(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a
         mark(0)
         sht.alm2delta(alm, gh, lmax, lmax, out=delta, ws=ws, flags=F)
         mark(1)
-        sht.delta2map(delta, gh, lmax, out=mp)
+        sht.delta2map(delta, gh, lmax, out=mp, flags=MM)
         mark(2)
         sht.map2delta(mp, gh, lmax, out=delta_s)
         mark(3)
-        sht.delta2alm(delta_s, gh, lmax, lmax, out=a_out, ws=ws, flags=F)
+        sht.delta2alm(delta_s, gh, lmax, lmax, out=a_out, ws=ws, flags=sht.SHT_MIXED)
         mark(4)
 
     for _ in range(warmup):

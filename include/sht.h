@@ -22,7 +22,8 @@
  *          nalm = (mmax+1)*(2*lmax+2-mmax)/2.
  *   map    float64, [nmaps][npix], npix = max_r(ofs[r] + nphi[r]).
  *   delta  complex128, [nmaps][nrings][mmax+1]: Delta_m(r) of Sec. 2.2
- *          (eq. DeltaDef for synthesis, eq. almfftdef for analysis).
+ *          (eq. DeltaDef for synthesis, eq. almfftdef for analysis);
+ *          [nrings][mmax+1][nmaps] with SHT_DELTA_MAP_MINOR.
  *
  * Conventions: Im a_l0 is ignored on input and written as exactly 0 on
  * output.  Rings r, r' whose colatitudes satisfy |theta_r + theta_r' - pi|
@@ -89,8 +90,17 @@ enum sht_flags {
      * pairs in FP32 and adds those sums in FP64.  The Delta and FFT stages stay
      * FP64.  Expected relative RMS error against the FP64 transform: about
      * 1e-7 to 1e-6.  Built for batches: a wave covers 8 to 32 maps in
-     * synthesis and 8 in analysis, so nmaps >= 8 fills it. */
-    SHT_MIXED = 1u
+     * synthesis and 8 in analysis, so nmaps >= 8 fills it.  sht_alm2map with
+     * this flag keeps its workspace Delta map-minor (as SHT_DELTA_MAP_MINOR
+     * below); sht_map2alm keeps it ring-major. */
+    SHT_MIXED = 1u,
+    /* Layout of the `delta` argument of the stage calls: [nrings][mmax+1][nmaps]
+     * (map index fastest) instead of [nmaps][nrings][mmax+1].  Accepted by
+     * sht_delta2map and sht_map2delta, and by sht_alm2delta and sht_delta2alm
+     * together with SHT_MIXED (otherwise SHT_EUNSUPPORTED); no effect on
+     * sht_alm2map, sht_map2alm and sht_workspace_bytes.  Results are bitwise
+     * the same as with the default layout. */
+    SHT_DELTA_MAP_MINOR = 2u
 };
 
 /* Bytes of device workspace needed by sht_alm2map, sht_map2alm,
@@ -107,7 +117,8 @@ size_t sht_workspace_bytes(int lmax, int mmax, const sht_geom *g, int nmaps, uin
  *              rings are left untouched)
  *   workspace  DEVICE, >= sht_workspace_bytes(...) bytes, 256-byte aligned,
  *              must not alias alm or map; contents undefined afterwards
- *   flags      0 (FP64) or SHT_MIXED.  Any other bit: SHT_EUNSUPPORTED. */
+ *   flags      0 (FP64) or SHT_MIXED (SHT_DELTA_MAP_MINOR has no effect).  Any
+ *              other bit: SHT_EUNSUPPORTED. */
 int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *map,
                 int nmaps, void *workspace, size_t ws_bytes, uint32_t flags, void *stream);
 
@@ -118,14 +129,15 @@ int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *
  *   map        DEVICE float64   [nmaps][npix], read only
  *   alm        DEVICE complex128 [nmaps][nalm], fully written
  *   workspace  as for sht_alm2map
- *   flags      0 (FP64) or SHT_MIXED.  Any other bit: SHT_EUNSUPPORTED. */
+ *   flags      as for sht_alm2map. */
 int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *alm,
                 int nmaps, void *workspace, size_t ws_bytes, uint32_t flags, void *stream);
 
 /* The two stages of each transform, for callers that keep Delta
  * themselves (and for per-stage timing).  sht_alm2map = sht_alm2delta then
  * sht_delta2map; sht_map2alm = sht_map2delta then sht_delta2alm.
- *   delta      DEVICE complex128 [nmaps][nrings][mmax+1]
+ *   delta      DEVICE complex128 [nmaps][nrings][mmax+1] ([nrings][mmax+1][nmaps]
+ *              with SHT_DELTA_MAP_MINOR)
  * sht_alm2delta and sht_delta2alm need a workspace of sht_workspace_bytes(...)
  * bytes (it must not alias their other buffers); the two ring stages need none. */
 int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *delta,

@@ -19,7 +19,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsht.so")
 
 SHT_OK, SHT_EINVAL, SHT_EWORKSPACE, SHT_EDEVICE, SHT_ENOMEM, SHT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-SHT_MIXED = 1  # flag: FP32 matrix-core contraction in synthesis (include/sht.h)
+SHT_MIXED = 1  # flag: FP32 matrix-core Legendre contraction (include/sht.h)
+SHT_DELTA_MAP_MINOR = 2  # flag: stage-call Delta laid out [nrings][mmax+1][nmaps]
 
 EXPORTS = ("sht_workspace_bytes", "sht_alm2map", "sht_map2alm", "sht_alm2delta", "sht_delta2map",
            "sht_map2delta", "sht_delta2alm", "sht_strerror", "sht_shutdown")
@@ -174,7 +175,9 @@ def alm2delta(alm, geom, lmax: int, mmax: int | None = None, out=None, ws=None, 
     g = _gh(geom, with_weight=False)
     nm = _nmaps_of(alm, nalm(lmax, mmax))
     if out is None:
-        out = torch.empty(alm.shape[:-1] + (g.nrings, mmax + 1), dtype=torch.complex128, device=alm.device)
+        shape = ((g.nrings, mmax + 1, nm) if flags & SHT_DELTA_MAP_MINOR
+                 else alm.shape[:-1] + (g.nrings, mmax + 1))
+        out = torch.empty(shape, dtype=torch.complex128, device=alm.device)
     if ws is None:
         ws = workspace(lmax, mmax, g, nm, alm.device, flags)
     rc = lib().sht_alm2delta(lmax, mmax, g.ref(), alm.data_ptr(), out.data_ptr(), nm, ws.data_ptr(),
@@ -183,26 +186,31 @@ def alm2delta(alm, geom, lmax: int, mmax: int | None = None, out=None, ws=None, 
     return out
 
 
-def delta2map(delta, geom, mmax: int, out=None, stream=None):
-    """Ring synthesis stage: float64 map [..., npix] from Delta [..., nrings, mmax+1]."""
+def delta2map(delta, geom, mmax: int, out=None, stream=None, flags: int = 0):
+    """Ring synthesis stage: float64 map [..., npix] from Delta [..., nrings, mmax+1]
+    (or [nrings, mmax+1, nmaps] with SHT_DELTA_MAP_MINOR)."""
     torch = _torch()
     g = _gh(geom, with_weight=False)
     nm = _nmaps_of(delta, g.nrings * (mmax + 1))
     if out is None:
-        out = torch.zeros(delta.shape[:-2] + (g.npix,), dtype=torch.float64, device=delta.device)
-    rc = lib().sht_delta2map(mmax, g.ref(), delta.data_ptr(), out.data_ptr(), nm, 0, _stream_ptr(stream))
+        shape = (nm, g.npix) if flags & SHT_DELTA_MAP_MINOR else delta.shape[:-2] + (g.npix,)
+        out = torch.zeros(shape, dtype=torch.float64, device=delta.device)
+    rc = lib().sht_delta2map(mmax, g.ref(), delta.data_ptr(), out.data_ptr(), nm, flags, _stream_ptr(stream))
     _check(rc, "sht_delta2map")
     return out
 
 
-def map2delta(mp, geom, mmax: int, out=None, stream=None):
-    """Ring analysis stage: Delta^S [..., nrings, mmax+1] from a float64 map."""
+def map2delta(mp, geom, mmax: int, out=None, stream=None, flags: int = 0):
+    """Ring analysis stage: Delta^S [..., nrings, mmax+1] (or [nrings, mmax+1, nmaps]
+    with SHT_DELTA_MAP_MINOR) from a float64 map."""
     torch = _torch()
     g = _gh(geom)
     nm = _nmaps_of(mp, g.npix)
     if out is None:
-        out = torch.empty(mp.shape[:-1] + (g.nrings, mmax + 1), dtype=torch.complex128, device=mp.device)
-    rc = lib().sht_map2delta(mmax, g.ref(), mp.data_ptr(), out.data_ptr(), nm, 0, _stream_ptr(stream))
+        shape = ((g.nrings, mmax + 1, nm) if flags & SHT_DELTA_MAP_MINOR
+                 else mp.shape[:-1] + (g.nrings, mmax + 1))
+        out = torch.empty(shape, dtype=torch.complex128, device=mp.device)
+    rc = lib().sht_map2delta(mmax, g.ref(), mp.data_ptr(), out.data_ptr(), nm, flags, _stream_ptr(stream))
     _check(rc, "sht_map2delta")
     return out
 
@@ -214,7 +222,8 @@ def delta2alm(delta, geom, lmax: int, mmax: int | None = None, out=None, ws=None
     g = _gh(geom, with_weight=False)
     nm = _nmaps_of(delta, g.nrings * (mmax + 1))
     if out is None:
-        out = torch.empty(delta.shape[:-2] + (nalm(lmax, mmax),), dtype=torch.complex128, device=delta.device)
+        shape = (nm,) if flags & SHT_DELTA_MAP_MINOR else delta.shape[:-2]
+        out = torch.empty(shape + (nalm(lmax, mmax),), dtype=torch.complex128, device=delta.device)
     if ws is None:
         ws = workspace(lmax, mmax, g, nm, delta.device, flags)
     rc = lib().sht_delta2alm(lmax, mmax, g.ref(), delta.data_ptr(), out.data_ptr(), nm, ws.data_ptr(),

@@ -71,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_prescale_mx(int lmax, int nmaps, int
 }
 
 template <int NCF>
-__global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, int nslots, int tiles, int nrings,
+__global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, int nslots, int tiles, DeltaLayout dl,
                                                         int nmaps, int64_t mxblocks,
                                                         const int64_t *__restrict__ mxofs,
                                                         const float *__restrict__ ap,
@@ -213,9 +213,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
                 if (map >= nmaps) continue;
                 const double er = acc[0][rf][cf][2 * h], ei = acc[0][rf][cf][2 * h + 1];
                 const double orr = acc[1][rf][cf][2 * h], oi = acc[1][rf][cf][2 * h + 1];
-                double2 *d = delta + (int64_t)map * nrings * (mmax + 1) + m;
-                d[rN * (mmax + 1)] = make_double2(er + orr, ei + oi);
-                if (rS >= 0) d[rS * (mmax + 1)] = make_double2(er - orr, ei - oi);
+                double2 *d = delta + map * dl.s_map + m * dl.s_m;
+                d[rN * dl.s_ring] = make_double2(er + orr, ei + oi);
+                if (rS >= 0) d[rS * dl.s_ring] = make_double2(er - orr, ei - oi);
             }
     }
 }
@@ -243,7 +243,7 @@ constexpr int kQRow = 64 + 4;   // floats per k row of a q tile (padding: confli
 static_assert(kAnaMxGroup == kAnaMxWaves * kAnaMxTiles * 64, "pairs per analysis group");
 static_assert(2 * kMxHalf * kAnaMxMaps <= kAnaMxThreads, "one thread per finished (parity, k, map)");
 
-__global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int mmax, int nslots, int nrings,
+__global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int mmax, int nslots, DeltaLayout dl,
                                                               int nmaps, int64_t nalm, int groups,
                                                               const double2 *__restrict__ delta,
                                                               const double *__restrict__ alpha,
@@ -277,7 +277,7 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
     int ls[kAnaMxTiles], tlo[kAnaMxTiles], thi[kAnaMxTiles];
     float dp[kAnaMxTiles][16], dm[kAnaMxTiles][16];
     const double *__restrict__ dcol = reinterpret_cast<const double *>(delta) +
-                                      2 * ((int64_t)(col_ok ? map_c : 0) * nrings * (mmax + 1) + m) + (c16 & 1);
+                                      2 * ((col_ok ? map_c : 0) * dl.s_map + m * dl.s_m) + (c16 & 1);
     int mylo = lmax + 1;
 #pragma unroll
     for (int t = 0; t < kAnaMxTiles; ++t) {
@@ -297,8 +297,8 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
             const bool ok = sl < nslots && col_ok;
             const int slc = min(sl, nslots - 1);
             const int r2 = rsouth[slc];
-            const double vn = dcol[2 * (int64_t)rn[slc] * (mmax + 1)];
-            const double vs = dcol[2 * (int64_t)max(r2, 0) * (mmax + 1)];
+            const double vn = dcol[2 * rn[slc] * dl.s_ring];
+            const double vs = dcol[2 * max(r2, 0) * dl.s_ring];
             const double dn = ok ? vn : 0.0, ds = (ok && r2 >= 0) ? vs : 0.0;
             dp[t][s] = (float)(dn + ds);
             dm[t][s] = (float)(dn - ds);
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
 
 template <int NCF>
 int launch_syn_mx_t(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm, void *aprime,
-                    void *delta, int nmaps, hipStream_t st) {
+                    void *delta, DeltaLayout dl, int nmaps, hipStream_t st) {
     constexpr int NC = 16 * NCF;
     const int ncg = (nmaps + NC / 2 - 1) / (NC / 2);
     const int tiles = (p.nslots + kBlock - 1) / kBlock;
@@ -416,7 +416,7 @@ int launch_syn_mx_t(const CoefTables &c, const GeomPlan &p, const StartTable &s,
                        static_cast<const double2 *>(alm), c.cfac, static_cast<float *>(aprime));
     SHT_HIP(hipGetLastError());
     hipLaunchKernelGGL(k_leg_syn_mx<NCF>, dim3((unsigned)gx, (unsigned)ncg), dim3(kBlock), 0, st, c.lmax, c.mmax,
-                       p.nslots, tiles, p.nrings, nmaps, c.mxblocks, c.mxofs, static_cast<const float *>(aprime),
+                       p.nslots, tiles, dl, nmaps, c.mxblocks, c.mxofs, static_cast<const float *>(aprime),
                        c.alpha, s.lstart, s.state, p.slot_x, p.slot_north, p.slot_south,
                        static_cast<double2 *>(delta));
     SHT_HIP(hipGetLastError());
@@ -425,15 +425,15 @@ int launch_syn_mx_t(const CoefTables &c, const GeomPlan &p, const StartTable &s,
 
 }  // namespace
 
-int launch_leg_ana_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *delta, void *alm,
-                      int nmaps, void *partials, hipStream_t st) {
+int launch_leg_ana_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *delta,
+                      DeltaLayout dl, void *alm, int nmaps, void *partials, hipStream_t st) {
     const int groups = (p.nslots + kAnaMxGroup - 1) / kAnaMxGroup;
     const int ncg = (nmaps + kAnaMxMaps - 1) / kAnaMxMaps;
     const int64_t gx = (int64_t)groups * padded_m(c.mmax);
     if (!grid_ok(gx) || ncg > 65535) return SHT_EUNSUPPORTED;
     if (groups > 1 && !partials) return SHT_EWORKSPACE;
     hipLaunchKernelGGL(k_leg_ana_mx, dim3((unsigned)gx, (unsigned)ncg), dim3(kAnaMxThreads), 0, st, c.lmax, c.mmax,
-                       p.nslots, p.nrings, nmaps, c.nalm, groups, static_cast<const double2 *>(delta), c.alpha,
+                       p.nslots, dl, nmaps, c.nalm, groups, static_cast<const double2 *>(delta), c.alpha,
                        c.cfac, s.lstart, s.state, p.slot_x, p.slot_north, p.slot_south, static_cast<double2 *>(alm),
                        static_cast<double2 *>(partials));
     SHT_HIP(hipGetLastError());
@@ -451,11 +451,11 @@ size_t mx_aprime_bytes(int lmax, int mmax, int nmaps) {
 }
 
 int launch_leg_syn_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm, void *aprime,
-                      void *delta, int nmaps, hipStream_t st) {
+                      void *delta, DeltaLayout dl, int nmaps, hipStream_t st) {
     switch (mx_col_frags(nmaps)) {
-        case 1: return launch_syn_mx_t<1>(c, p, s, alm, aprime, delta, nmaps, st);
-        case 2: return launch_syn_mx_t<2>(c, p, s, alm, aprime, delta, nmaps, st);
-        default: return launch_syn_mx_t<4>(c, p, s, alm, aprime, delta, nmaps, st);
+        case 1: return launch_syn_mx_t<1>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+        case 2: return launch_syn_mx_t<2>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+        default: return launch_syn_mx_t<4>(c, p, s, alm, aprime, delta, dl, nmaps, st);
     }
 }
 

@@ -320,11 +320,11 @@ __device__ __forceinline__ double2 input_point(double2 v, const FftDesc *__restr
 // S_a,k = (Z_k + conj Z_{-k}) / 2, S_b,k = (Z_k - conj Z_{-k}) / (2i).
 
 // c_k of one ring: sum over m = k mod n (m <= mmax) of w_m Delta_m e^{i m phi0}
-__device__ __forceinline__ double2 fold_bin(const double2 *__restrict__ D, int k, int n, int mmax,
+__device__ __forceinline__ double2 fold_bin(const double2 *__restrict__ D, int64_t sm, int k, int n, int mmax,
                                             const Phase &ph) {
     double cr = 0.0, ci = 0.0;
     for (int m = k; m <= mmax; m += n) {
-        const double2 dv = D[m];
+        const double2 dv = D[m * sm];
         if (m == 0) {
             cr += dv.x;
         } else {
@@ -338,10 +338,10 @@ __device__ __forceinline__ double2 fold_bin(const double2 *__restrict__ D, int k
 
 // phased terms of one ring for m = tid, tid+NT, ...: w_m Delta_m e^{i m phi0}
 template <int NT>
-__device__ __forceinline__ void phased_terms(const double2 *__restrict__ D, int mmax, const Phase &ph,
+__device__ __forceinline__ void phased_terms(const double2 *__restrict__ D, int64_t sm, int mmax, const Phase &ph,
                                              double2 *__restrict__ out) {
     for (int m = threadIdx.x; m <= mmax; m += NT) {
-        const double2 dv = D[m];
+        const double2 dv = D[m * sm];
         if (m == 0) {
             out[0] = make_double2(dv.x, 0.0);
         } else {
@@ -381,11 +381,40 @@ __device__ __forceinline__ int fold_columns(double2 *__restrict__ t, int n, int 
     return min(S - 1, mmax);
 }
 
+// Workgroup -> (job, map).  Ring-major Delta: the maps of one job are
+// consecutive workgroups (they share the job's tables through L2).  Map-minor
+// Delta: units of (job, 8 maps), whose Delta entries share 128-byte lines,
+// go to the XCDs in turn (workgroup b runs on XCD b mod 8) and a unit's 8
+// workgroups run back to back on its XCD, so that the lines are fetched (or
+// completed) once in that XCD's L2.  Returns false for the padding of the
+// grid (a whole workgroup).
+__device__ __forceinline__ bool job_map(int njobs, int nmaps, int map_minor, int &job, int &mp) {
+    if (!map_minor) {
+        job = blockIdx.x / nmaps;
+        mp = blockIdx.x % nmaps;
+        return true;
+    }
+    const int groups = (nmaps + 7) / 8;
+    const int x = blockIdx.x % 8, k = blockIdx.x / 8;
+    const int unit = (k / 8) * 8 + x;
+    job = unit / groups;
+    mp = (unit % groups) * 8 + k % 8;
+    return job < njobs && mp < nmaps;
+}
+// workgroups of one class launch: njobs * nmaps, or for map-minor Delta 64 per
+// 8 units of (job, 8 maps)
+inline int64_t fft_grid(int njobs, int nmaps, int map_minor) {
+    if (!map_minor) return (int64_t)njobs * nmaps;
+    const int64_t units = (int64_t)njobs * ((nmaps + 7) / 8);
+    return (units + 7) / 8 * 64;
+}
+
 // Synthesis.  LDS: the twiddle tables, buf[L], plus (fold_rows != 0) two
 // rows of mmax+1 phased terms used when the ring folds many m per bin,
 // n < (mmax+1)/2.
 template <int MAXL, int NT>
-__global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t npix, int nmaps, int fold_rows, int ph_tab,
+__global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int njobs, int64_t npix, int nmaps, DeltaLayout dl,
+                                                int fold_rows, int ph_tab,
                                                 const int2 *__restrict__ jobs,
                                                 const int32_t *__restrict__ ring_desc,
                                                 const FftDesc *__restrict__ descs,
@@ -395,16 +424,15 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t np
                                                 double *__restrict__ map) {
     extern __shared__ double2 lds[];
     double2 *tlo = lds, *thi = lds + kTwLo, *buf = lds + tw_entries<MAXL>();
-    // maps vary fastest: the workgroups of one ring's maps run together and
-    // share its tables (Bluestein chirp and kernel) through L2
-    const int2 job = jobs[blockIdx.x / nmaps];
+    int ji, mp;
+    if (!job_map(njobs, nmaps, dl.map_minor, ji, mp)) return;  // grid padding (whole workgroup)
+    const int2 job = jobs[ji];
     const int ra = job.x, rb = job.y;
-    const int mp = blockIdx.x % nmaps;
     const FftDesc *d = descs + ring_desc[ra];
     const int N = d->n, L = d->L;
     load_twiddles<NT>(tlo, thi, d->tw, L);
-    const double2 *__restrict__ Da = delta + ((int64_t)mp * nrings + ra) * (mmax + 1);
-    const double2 *__restrict__ Db = delta + ((int64_t)mp * nrings + (rb >= 0 ? rb : ra)) * (mmax + 1);
+    const double2 *__restrict__ Da = delta + mp * dl.s_map + ra * dl.s_ring;
+    const double2 *__restrict__ Db = delta + mp * dl.s_map + (rb >= 0 ? rb : ra) * dl.s_ring;
     const double pa = phi0[ra], pb = rb >= 0 ? phi0[rb] : 0.0;
     Phase pha{nullptr, nullptr, pa}, phb{nullptr, nullptr, pb};
     if (ph_tab) {
@@ -418,8 +446,8 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t np
     if (lds_fold) {
         // all threads evaluate phases; short rings first sum the rows in columns
         double2 *ta = buf + pd(L), *tb = buf + pd(L) + (mmax + 1);
-        phased_terms<NT>(Da, mmax, pha, ta);
-        if (rb >= 0) phased_terms<NT>(Db, mmax, phb, tb);
+        phased_terms<NT>(Da, dl.s_m, mmax, pha, ta);
+        if (rb >= 0) phased_terms<NT>(Db, dl.s_m, mmax, phb, tb);
         __syncthreads();
         if (N <= NT) {
             lim = fold_columns<NT>(ta, N, mmax);
@@ -440,11 +468,11 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t np
                 b1 = fold_terms(tb, kn, N, lim);
             }
         } else {
-            a0 = fold_bin(Da, k, N, mmax, pha);
-            a1 = fold_bin(Da, kn, N, mmax, pha);
+            a0 = fold_bin(Da, dl.s_m, k, N, mmax, pha);
+            a1 = fold_bin(Da, dl.s_m, kn, N, mmax, pha);
             if (rb >= 0) {
-                b0 = fold_bin(Db, k, N, mmax, phb);
-                b1 = fold_bin(Db, kn, N, mmax, phb);
+                b0 = fold_bin(Db, dl.s_m, k, N, mmax, phb);
+                b1 = fold_bin(Db, dl.s_m, kn, N, mmax, phb);
             }
         }
         // h_k = (c_k + conj c_{n-k}) / 2, h_{n-k} = conj h_k
@@ -468,7 +496,7 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int nrings, int64_t np
 }
 
 template <int MAXL, int NT>
-__global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t npix, int nmaps, int ph_tab,
+__global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int njobs, int64_t npix, int nmaps, DeltaLayout dl, int ph_tab,
                                                 const int2 *__restrict__ jobs,
                                                 const int32_t *__restrict__ ring_desc,
                                                 const FftDesc *__restrict__ descs,
@@ -479,11 +507,10 @@ __global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t np
                                                 double2 *__restrict__ delta) {
     extern __shared__ double2 lds[];
     double2 *tlo = lds, *thi = lds + kTwLo, *buf = lds + tw_entries<MAXL>();
-    // maps vary fastest: the workgroups of one ring's maps run together and
-    // share its tables (Bluestein chirp and kernel) through L2
-    const int2 job = jobs[blockIdx.x / nmaps];
+    int ji, mp;
+    if (!job_map(njobs, nmaps, dl.map_minor, ji, mp)) return;  // grid padding (whole workgroup)
+    const int2 job = jobs[ji];
     const int ra = job.x, rb = job.y;
-    const int mp = blockIdx.x % nmaps;
     const FftDesc *d = descs + ring_desc[ra];
     const int N = d->n;
     load_twiddles<NT>(tlo, thi, d->tw, d->L);
@@ -502,8 +529,8 @@ __global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t np
         buf[pd(j)] = input_point(make_double2(ina[j], rb >= 0 ? inb[j] : 0.0), d, j);
     __syncthreads();
     transform<MAXL, NT>(buf, d, TwLds{tlo, thi});
-    double2 *Da = delta + ((int64_t)mp * nrings + ra) * (mmax + 1);
-    double2 *Db = delta + ((int64_t)mp * nrings + (rb >= 0 ? rb : ra)) * (mmax + 1);
+    double2 *Da = delta + mp * dl.s_map + ra * dl.s_ring;
+    double2 *Db = delta + mp * dl.s_map + (rb >= 0 ? rb : ra) * dl.s_ring;
     for (int m = threadIdx.x; m <= mmax; m += NT) {
         const int k = m % N, kn = (N - k) % N;
         const double2 Z = result_at(buf, d, k), Zn = result_at(buf, d, kn);
@@ -512,10 +539,10 @@ __global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int nrings, int64_t np
         const double2 Sb = make_double2(0.5 * (Z.y + Zn.y), -0.5 * (Z.x - Zn.x));
         const double2 ea = pha(m);
         // w * conj(e) * S
-        Da[m] = make_double2(wa * fma(Sa.x, ea.x, Sa.y * ea.y), wa * fma(Sa.y, ea.x, -Sa.x * ea.y));
+        Da[m * dl.s_m] = make_double2(wa * fma(Sa.x, ea.x, Sa.y * ea.y), wa * fma(Sa.y, ea.x, -Sa.x * ea.y));
         if (rb >= 0) {
             const double2 eb = phb(m);
-            Db[m] = make_double2(wb * fma(Sb.x, eb.x, Sb.y * eb.y), wb * fma(Sb.y, eb.x, -Sb.x * eb.y));
+            Db[m * dl.s_m] = make_double2(wb * fma(Sb.x, eb.x, Sb.y * eb.y), wb * fma(Sb.y, eb.x, -Sb.x * eb.y));
         }
     }
 }
@@ -562,7 +589,7 @@ int phase_tables_fit(int mmax, size_t lds) {
 }
 
 template <int MAXL>
-int launch_syn_class(const GeomPlan &p, int c, int mmax, const void *delta, double *map, int nmaps,
+int launch_syn_class(const GeomPlan &p, int c, int mmax, const void *delta, DeltaLayout dl, double *map, int nmaps,
                      hipStream_t st) {
     constexpr int NT = fft_threads<MAXL>();
     const size_t base = (size_t)(tw_entries<MAXL>() + padded_len<MAXL>()) * sizeof(double2);
@@ -572,21 +599,21 @@ int launch_syn_class(const GeomPlan &p, int c, int mmax, const void *delta, doub
     size_t lds = base + (fold_rows ? rows : 0);
     const int ph_tab = phase_tables_fit(mmax, lds);
     if (ph_tab) lds += phase_table_bytes(mmax);
-    hipLaunchKernelGGL((k_fft_syn<MAXL, NT>), dim3((unsigned)((int64_t)p.class_count[c] * nmaps)), dim3(NT), lds,
-                       st, mmax, p.nrings, p.npix, nmaps, fold_rows, ph_tab, p.class_jobs[c], p.ring_desc, p.descs, p.phi0,
+    hipLaunchKernelGGL((k_fft_syn<MAXL, NT>), dim3((unsigned)fft_grid(p.class_count[c], nmaps, dl.map_minor)),
+                       dim3(NT), lds, st, mmax, p.class_count[c], p.npix, nmaps, dl, fold_rows, ph_tab, p.class_jobs[c], p.ring_desc, p.descs, p.phi0,
                        p.ofs, static_cast<const double2 *>(delta), map);
     return SHT_OK;
 }
 
 template <int MAXL>
-void launch_ana_class(const GeomPlan &p, int c, int mmax, const double *map, void *delta, int nmaps,
+void launch_ana_class(const GeomPlan &p, int c, int mmax, const double *map, void *delta, DeltaLayout dl, int nmaps,
                       hipStream_t st) {
     constexpr int NT = fft_threads<MAXL>();
     size_t lds = (size_t)(tw_entries<MAXL>() + padded_len<MAXL>()) * sizeof(double2);
     const int ph_tab = phase_tables_fit(mmax, lds);
     if (ph_tab) lds += phase_table_bytes(mmax);
-    hipLaunchKernelGGL((k_fft_ana<MAXL, NT>), dim3((unsigned)((int64_t)p.class_count[c] * nmaps)), dim3(NT), lds,
-                       st, mmax, p.nrings, p.npix, nmaps, ph_tab, p.class_jobs[c], p.ring_desc, p.descs, p.phi0, p.weight,
+    hipLaunchKernelGGL((k_fft_ana<MAXL, NT>), dim3((unsigned)fft_grid(p.class_count[c], nmaps, dl.map_minor)),
+                       dim3(NT), lds, st, mmax, p.class_count[c], p.npix, nmaps, dl, ph_tab, p.class_jobs[c], p.ring_desc, p.descs, p.phi0, p.weight,
                        p.ofs, map, static_cast<double2 *>(delta));
 }
 
@@ -596,16 +623,17 @@ static_assert(kFftClasses == 4 && kFftClassLen[0] == 1024 && kFftClassLen[3] == 
 }  // namespace
 
 // one workgroup per (job, map) of a class
-static bool grid_fits(const GeomPlan &p, int nmaps) {
+static bool grid_fits(const GeomPlan &p, int nmaps, int map_minor) {
     for (int c = 0; c < kFftClasses; ++c)
-        if ((int64_t)p.class_count[c] * nmaps >= (int64_t)INT32_MAX) return false;
+        if (fft_grid(p.class_count[c], nmaps, map_minor) >= (int64_t)INT32_MAX) return false;
     return true;
 }
 
 // The length classes are independent: they run concurrently, the largest on
 // the caller's stream and the others on side streams (fork_join).
-int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, double *map, int nmaps, hipStream_t st) {
-    if (nmaps > 65535 || !grid_fits(p, nmaps)) return SHT_EUNSUPPORTED;
+int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, DeltaLayout dl, double *map, int nmaps,
+                   hipStream_t st) {
+    if (nmaps > 65535 || !grid_fits(p, nmaps, dl.map_minor)) return SHT_EUNSUPPORTED;
     int rc = set_lds_attr();
     if (rc) return rc;
     int cls[kFftClasses], n = 0;
@@ -613,18 +641,19 @@ int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, double *map, 
         if (p.class_count[c]) cls[n++] = c;
     return fork_join(st, n, [&](int i, hipStream_t s) {
         switch (cls[i]) {
-            case 0: launch_syn_class<1024>(p, 0, mmax, delta, map, nmaps, s); break;
-            case 1: launch_syn_class<2048>(p, 1, mmax, delta, map, nmaps, s); break;
-            case 2: launch_syn_class<4096>(p, 2, mmax, delta, map, nmaps, s); break;
-            default: launch_syn_class<8192>(p, 3, mmax, delta, map, nmaps, s); break;
+            case 0: launch_syn_class<1024>(p, 0, mmax, delta, dl, map, nmaps, s); break;
+            case 1: launch_syn_class<2048>(p, 1, mmax, delta, dl, map, nmaps, s); break;
+            case 2: launch_syn_class<4096>(p, 2, mmax, delta, dl, map, nmaps, s); break;
+            default: launch_syn_class<8192>(p, 3, mmax, delta, dl, map, nmaps, s); break;
         }
         SHT_HIP(hipGetLastError());
         return SHT_OK;
     });
 }
 
-int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, int nmaps, hipStream_t st) {
-    if (nmaps > 65535 || !grid_fits(p, nmaps)) return SHT_EUNSUPPORTED;
+int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, DeltaLayout dl, int nmaps,
+                   hipStream_t st) {
+    if (nmaps > 65535 || !grid_fits(p, nmaps, dl.map_minor)) return SHT_EUNSUPPORTED;
     if (!p.weight) return SHT_EINVAL;
     int rc = set_lds_attr();
     if (rc) return rc;
@@ -633,10 +662,10 @@ int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, 
         if (p.class_count[c]) cls[n++] = c;
     return fork_join(st, n, [&](int i, hipStream_t s) {
         switch (cls[i]) {
-            case 0: launch_ana_class<1024>(p, 0, mmax, map, delta, nmaps, s); break;
-            case 1: launch_ana_class<2048>(p, 1, mmax, map, delta, nmaps, s); break;
-            case 2: launch_ana_class<4096>(p, 2, mmax, map, delta, nmaps, s); break;
-            default: launch_ana_class<8192>(p, 3, mmax, map, delta, nmaps, s); break;
+            case 0: launch_ana_class<1024>(p, 0, mmax, map, delta, dl, nmaps, s); break;
+            case 1: launch_ana_class<2048>(p, 1, mmax, map, delta, dl, nmaps, s); break;
+            case 2: launch_ana_class<4096>(p, 2, mmax, map, delta, dl, nmaps, s); break;
+            default: launch_ana_class<8192>(p, 3, mmax, map, delta, dl, nmaps, s); break;
         }
         SHT_HIP(hipGetLastError());
         return SHT_OK;

@@ -13,7 +13,7 @@ using namespace sht;
 
 namespace {
 
-constexpr uint32_t kKnownFlags = SHT_MIXED;
+constexpr uint32_t kKnownFlags = SHT_MIXED | SHT_DELTA_MAP_MINOR;
 
 size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -50,6 +50,12 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// Delta layout of a stage call; the FP64 Legendre kernels take ring-major only
+DeltaLayout stage_layout(const HostGeom &h, int mmax, int nmaps, uint32_t flags) {
+    return delta_layout(h.nrings, mmax, nmaps, (flags & SHT_DELTA_MAP_MINOR) != 0);
+}
+bool legendre_layout_ok(uint32_t flags) { return !(flags & SHT_DELTA_MAP_MINOR) || (flags & SHT_MIXED); }
+
 // Common checks for the transforms; fills the validated geometry.
 int check_common(int lmax, int mmax, const sht_geom *g, int nmaps, uint32_t flags, bool need_weight,
                  HostGeom *h) {
@@ -74,6 +80,7 @@ int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *
     HostGeom h;
     int rc = check_common(lmax, mmax, g, nmaps, flags, false, &h);
     if (rc) return rc;
+    if (!legendre_layout_ok(flags)) return SHT_EUNSUPPORTED;
     if (!alm || !delta || !aligned(alm, 16) || !aligned(delta, 16)) return SHT_EINVAL;
     const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
     if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps, flags))
@@ -87,7 +94,9 @@ int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *
     if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p)) ||
         (rc = get_start(*c, p, as_stream(stream), &s)))
         return rc;
-    if (flags & SHT_MIXED) return launch_leg_syn_mx(*c, *p, *s, alm, workspace, delta, nmaps, as_stream(stream));
+    if (flags & SHT_MIXED)
+        return launch_leg_syn_mx(*c, *p, *s, alm, workspace, delta, stage_layout(h, mmax, nmaps, flags), nmaps,
+                                 as_stream(stream));
     if ((rc = launch_prescale(*c, alm, workspace, nmaps, as_stream(stream)))) return rc;
     return launch_leg_syn(*c, *p, *s, workspace, delta, nmaps, as_stream(stream));
 }
@@ -102,7 +111,7 @@ int sht_delta2map(int mmax, const sht_geom *g, const void *delta, double *map, i
         return SHT_EINVAL;
     GeomRef p;
     if ((rc = get_geom(h, mmax, &p))) return rc;
-    return launch_fft_syn(*p, mmax, delta, map, nmaps, as_stream(stream));
+    return launch_fft_syn(*p, mmax, delta, stage_layout(h, mmax, nmaps, flags), map, nmaps, as_stream(stream));
 }
 
 int sht_map2delta(int mmax, const sht_geom *g, const double *map, void *delta, int nmaps,
@@ -115,7 +124,7 @@ int sht_map2delta(int mmax, const sht_geom *g, const double *map, void *delta, i
         return SHT_EINVAL;
     GeomRef p;
     if ((rc = get_geom(h, mmax, &p))) return rc;
-    return launch_fft_ana(*p, mmax, map, delta, nmaps, as_stream(stream));
+    return launch_fft_ana(*p, mmax, map, delta, stage_layout(h, mmax, nmaps, flags), nmaps, as_stream(stream));
 }
 
 int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void *alm, int nmaps,
@@ -123,6 +132,7 @@ int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void
     HostGeom h;
     int rc = check_common(lmax, mmax, g, nmaps, flags, false, &h);
     if (rc) return rc;
+    if (!legendre_layout_ok(flags)) return SHT_EUNSUPPORTED;
     if (!delta || !alm || !aligned(delta, 16) || !aligned(alm, 16)) return SHT_EINVAL;
     const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
     if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps, flags))
@@ -136,7 +146,9 @@ int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void
     if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p)) ||
         (rc = get_start(*c, p, as_stream(stream), &s)))
         return rc;
-    if (flags & SHT_MIXED) return launch_leg_ana_mx(*c, *p, *s, delta, alm, nmaps, workspace, as_stream(stream));
+    if (flags & SHT_MIXED)
+        return launch_leg_ana_mx(*c, *p, *s, delta, stage_layout(h, mmax, nmaps, flags), alm, nmaps, workspace,
+                                 as_stream(stream));
     return launch_leg_ana(*c, *p, *s, delta, alm, nmaps, workspace, as_stream(stream));
 }
 
@@ -161,13 +173,17 @@ int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *
         return rc;
     char *ws = static_cast<char *>(workspace);
     void *delta = ws, *aprime = ws + round256(db);
+    // mixed precision keeps the workspace Delta map-minor: the matrix-core
+    // kernel then stores whole 128-byte lines per (ring, m), which saves more
+    // than the ring FFT loses on its strided reads
+    const DeltaLayout dl = delta_layout(h.nrings, mmax, nmaps, (flags & SHT_MIXED) != 0);
     if (flags & SHT_MIXED) {
-        if ((rc = launch_leg_syn_mx(*c, *p, *s, alm, aprime, delta, nmaps, st))) return rc;
+        if ((rc = launch_leg_syn_mx(*c, *p, *s, alm, aprime, delta, dl, nmaps, st))) return rc;
     } else {
         if ((rc = launch_prescale(*c, alm, aprime, nmaps, st))) return rc;
         if ((rc = launch_leg_syn(*c, *p, *s, aprime, delta, nmaps, st))) return rc;
     }
-    return launch_fft_syn(*p, mmax, delta, map, nmaps, st);
+    return launch_fft_syn(*p, mmax, delta, dl, map, nmaps, st);
 }
 
 int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *alm, int nmaps,
@@ -191,8 +207,11 @@ int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *
         return rc;
     char *ws = static_cast<char *>(workspace);
     void *delta = ws, *partials = ws + round256(db);
-    if ((rc = launch_fft_ana(*p, mmax, map, delta, nmaps, st))) return rc;
-    if (flags & SHT_MIXED) return launch_leg_ana_mx(*c, *p, *s, delta, alm, nmaps, partials, st);
+    // ring-major here also with SHT_MIXED: the strided stores of the ring FFT
+    // would cost more than the analysis kernel's reads gain
+    const DeltaLayout dl = delta_layout(h.nrings, mmax, nmaps, false);
+    if ((rc = launch_fft_ana(*p, mmax, map, delta, dl, nmaps, st))) return rc;
+    if (flags & SHT_MIXED) return launch_leg_ana_mx(*c, *p, *s, delta, dl, alm, nmaps, partials, st);
     return launch_leg_ana(*c, *p, *s, delta, alm, nmaps, partials, st);
 }
 

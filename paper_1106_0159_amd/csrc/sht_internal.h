@@ -134,6 +134,21 @@ struct GeomPlan {
     ~GeomPlan();                     // waits for the device, then frees
 };
 
+// Element (map, ring, m) of a Delta array lies at
+// map * s_map + ring * s_ring + m * s_m (complex entries).  Ring-major (the
+// default) is [nmaps][nrings][mmax+1]; map-minor (SHT_DELTA_MAP_MINOR) is
+// [nrings][mmax+1][nmaps], where the 8 maps that share a 128-byte line for one
+// (ring, m) are written or read together by the mixed Legendre kernels.
+struct DeltaLayout {
+    int64_t s_map, s_ring, s_m;
+    int map_minor;
+};
+inline DeltaLayout delta_layout(int nrings, int mmax, int nmaps, bool map_minor) {
+    const int64_t nm = mmax + 1;
+    if (map_minor) return DeltaLayout{1, nm * nmaps, (int64_t)nmaps, 1};
+    return DeltaLayout{(int64_t)nrings * nm, nm, 1, 0};
+}
+
 // Validated, normalised copy of the caller's geometry.
 struct HostGeom {
     int nrings = 0;
@@ -190,15 +205,15 @@ int launch_leg_ana(const CoefTables &c, const GeomPlan &p, const StartTable &s, 
 int mx_col_frags(int nmaps);
 size_t mx_aprime_bytes(int lmax, int mmax, int nmaps);
 int launch_leg_syn_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm,
-                      void *aprime, void *delta, int nmaps, hipStream_t st);
-int launch_leg_ana_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *delta, void *alm,
-                      int nmaps, void *partials, hipStream_t st);
+                      void *aprime, void *delta, DeltaLayout dl, int nmaps, hipStream_t st);
+int launch_leg_ana_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *delta,
+                      DeltaLayout dl, void *alm, int nmaps, void *partials, hipStream_t st);
 // a_lm = c_lm * (sum of the per-group partials, groups in order); Im a_l0 = 0.
 int launch_ana_combine(const CoefTables &c, int nmaps, int groups, const void *partials, void *alm,
                        hipStream_t st);
-int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, double *map, int nmaps,
+int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, DeltaLayout dl, double *map, int nmaps,
                    hipStream_t st);
-int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, int nmaps,
+int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, DeltaLayout dl, int nmaps,
                    hipStream_t st);
 
 inline int64_t nalm_of(int lmax, int mmax) {

@@ -93,6 +93,10 @@ def test_workspace_bytes_mixed():
 
     for lmax, nmaps in [(16, 1), (16, 3), (16, 12), (16, 20), (16, 40), (70, 33), (0, 1)]:
         assert _ws(lmax, lmax, g, nmaps, sht.SHT_MIXED) == delta(lmax, nmaps) + r256(tiles(lmax, nmaps)), (lmax, nmaps)
+    # the Delta layout flag does not change the workspace
+    for nmaps in (1, 20):
+        assert _ws(16, 16, g, nmaps, sht.SHT_MIXED | sht.SHT_DELTA_MAP_MINOR) == _ws(16, 16, g, nmaps, sht.SHT_MIXED)
+        assert _ws(16, 16, g, nmaps, sht.SHT_DELTA_MAP_MINOR) == _ws(16, 16, g, nmaps)
     # lmax = 16: 17 columns of one block each; 20 maps -> one group of 32 maps (64 columns)
     assert tiles(16, 20) == 17 * 2 * 64 * 16 * 4
 
@@ -146,11 +150,14 @@ def test_invalid_arguments_rejected_on_host(L):
     assert L.sht_alm2map(-1, 0, g.ref(), a, m, 1, w, big, 0, None) == sht.SHT_EINVAL
     assert L.sht_alm2map(4, 5, g.ref(), a, m, 1, w, big, 0, None) == sht.SHT_EINVAL
     assert L.sht_alm2map(4, 4, g.ref(), a, m, 0, w, big, 0, None) == sht.SHT_EINVAL
-    # flags: unknown bits
-    assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, big, 2, None) == sht.SHT_EUNSUPPORTED
+    # flags: unknown bits; the map-minor Delta layout needs SHT_MIXED in the Legendre stage calls
+    assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, big, 4, None) == sht.SHT_EUNSUPPORTED
     assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, big, 1 << 31, None) == sht.SHT_EUNSUPPORTED
     assert L.sht_map2alm(4, 4, g.ref(), m, a, 1, w, big, sht.SHT_MIXED | 4, None) == sht.SHT_EUNSUPPORTED
     assert L.sht_delta2alm(4, 4, g.ref(), m, a, 1, w, big, 8, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_delta2map(4, g.ref(), m, a, 1, 16, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_alm2delta(4, 4, g.ref(), a, m, 1, w, big, sht.SHT_DELTA_MAP_MINOR, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_delta2alm(4, 4, g.ref(), m, a, 1, w, big, sht.SHT_DELTA_MAP_MINOR, None) == sht.SHT_EUNSUPPORTED
     # null and misaligned pointers
     assert L.sht_alm2map(4, 4, g.ref(), None, m, 1, w, big, 0, None) == sht.SHT_EINVAL
     assert L.sht_alm2map(4, 4, g.ref(), a, None, 1, w, big, 0, None) == sht.SHT_EINVAL
