@@ -63,6 +63,14 @@ def count_triples(geom_handle_slots: int, lmax: int, mmax: int) -> int:
     return geom_handle_slots * nalm
 
 
+def latency(times_ms) -> dict:
+    """Percentiles of the event-timed solve latency (one step or one batch)."""
+    import numpy as np
+    t = np.asarray(times_ms, dtype=float)
+    return {"p50": float(np.percentile(t, 50)), "p99": float(np.percentile(t, 99)),
+            "min": float(t.min()), "max": float(t.max()), "n": int(t.size)}
+
+
 def mirror_slots(theta) -> int:
     """Number of ring slots (mirror pairs plus unpaired rings), as the library forms them."""
     th = sorted(float(t) for t in theta)
@@ -108,14 +116,29 @@ def cpu_baseline(g, lmax, a, mp, target_s: float = 12.0):
     t0 = time.perf_counter()
     oracle.map2alm(lmax, lmax, g, mp, ms=ms)
     t_ana = (time.perf_counter() - t0) * (lmax + 1) / len(ms)
+    # the same oracle on one thread, on a sample a quarter that size
+    oracle.set_threads(1)
+    try:
+        r1 = rings[:: max(1, 4 * cores)] if len(rings) > 4 * cores else rings[:1]
+        m1 = ms[:: max(1, 4 * cores)] if len(ms) > 4 * cores else ms[:1]
+        t0 = time.perf_counter()
+        oracle.alm2map(lmax, lmax, g, a, rings=r1)
+        t1_syn = (time.perf_counter() - t0) * g.nrings / len(r1)
+        t0 = time.perf_counter()
+        oracle.map2alm(lmax, lmax, g, mp, ms=m1)
+        t1_ana = (time.perf_counter() - t0) * (lmax + 1) / len(m1)
+    finally:
+        oracle.set_threads(cores)
     return {
         "value": 1.0 / (t_syn + t_ana),
         "unit": "maps/s",
         "cores": int(cores),
+        "value_1core": 1.0 / (t1_syn + t1_ana),
         "kind": "oracle",
         "sample": (f"oracle alm2map on {len(rings)} of {g.nrings} rings (evenly spaced) and map2alm on "
                    f"{len(ms)} of {lmax + 1} m values (evenly spaced), scaled to the full map; "
-                   f"est. {t_syn:.1f} s + {t_ana:.1f} s per map"),
+                   f"est. {t_syn:.1f} s + {t_ana:.1f} s per map; value_1core: one thread on every "
+                   f"{max(1, 4 * cores)}-th of those rings and m values ({len(r1)} and {len(m1)})"),
     }
 
 
@@ -168,6 +191,7 @@ def batched_mixed(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a
     wall = time.perf_counter() - t0
     names = ["leg_syn_mx", "fft_syn", "fft_ana", "leg_ana_mx"]
     st = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])) for i, n in enumerate(names)}
+    batch_times = np.array([e[0].elapsed_time(e[4]) for e in evs])
     ms = max(wall * 1000.0 / steps, sum(st.values()))
     flops = 4 * nmaps * count_triples(nslots, lmax, lmax)  # matrix-core flops of one contraction
     dom = max(("leg_syn_mx", "leg_ana_mx"), key=lambda n: st[n])
@@ -179,6 +203,7 @@ def batched_mixed(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a
         "value": nmaps * 1000.0 / ms,
         "unit": "maps/s",
         "ms_per_batch": ms,
+        "latency_ms": latency(batch_times),
         "steps": steps,
         "stages_ms": st,
         "alm2map_maps_per_s": nmaps * 1000.0 / (st["leg_syn_mx"] + st["fft_syn"]),
@@ -283,7 +308,8 @@ def main():
     stage_names = ["leg_syn", "fft_syn", "fft_ana", "leg_ana"]
     stage_ms = {n: float(np.mean([evs[k][i].elapsed_time(evs[k][i + 1]) for k in range(K)]))
                 for i, n in enumerate(stage_names)}
-    step_ms = float(np.mean([evs[k][0].elapsed_time(evs[k][4]) for k in range(K)]))
+    step_times = np.array([evs[k][0].elapsed_time(evs[k][4]) for k in range(K)])
+    step_ms = float(np.mean(step_times))
     ms_per_step = max(wall * 1000.0 / K, step_ms)
 
     nslots = mirror_slots(g.theta)
@@ -313,6 +339,7 @@ def main():
             "nrings": g.nrings, "npix": g.npix, "slots": nslots,
         },
         "stages_ms": stage_ms,
+        "latency_ms": latency(step_times),
         "alm2map_maps_per_s": 1000.0 / (stage_ms["leg_syn"] + stage_ms["fft_syn"]),
         "map2alm_maps_per_s": 1000.0 / (stage_ms["fft_ana"] + stage_ms["leg_ana"]),
         "roofline": {
