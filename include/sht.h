@@ -98,8 +98,10 @@ enum sht_flags {
      * (map index fastest) instead of [nmaps][nrings][mmax+1].  Accepted by
      * sht_delta2map and sht_map2delta, and by sht_alm2delta and sht_delta2alm
      * together with SHT_MIXED (otherwise SHT_EUNSUPPORTED); no effect on
-     * sht_alm2map, sht_map2alm and sht_workspace_bytes.  Results are bitwise
-     * the same as with the default layout. */
+     * sht_alm2map, sht_map2alm and sht_workspace_bytes.  The Legendre stages
+     * give the same bits in either layout; the ring stages then transform two
+     * adjacent maps of one ring together instead of the two rings of a mirror
+     * pair, which changes their results by rounding only. */
     SHT_DELTA_MAP_MINOR = 2u
 };
 

@@ -381,32 +381,47 @@ __device__ __forceinline__ int fold_columns(double2 *__restrict__ t, int n, int 
     return min(S - 1, mmax);
 }
 
-// Workgroup -> (job, map).  Ring-major Delta: the maps of one job are
-// consecutive workgroups (they share the job's tables through L2).  Map-minor
-// Delta: units of (job, 8 maps), whose Delta entries share 128-byte lines,
-// go to the XCDs in turn (workgroup b runs on XCD b mod 8) and a unit's 8
-// workgroups run back to back on its XCD, so that the lines are fetched (or
+// The two real sequences a workgroup transforms as one complex sequence:
+// ring ra of map ma and ring rb of map mb (rings of equal length).
+struct JobSeqs {
+    int ra, rb, ma, mb;
+    bool two;  // false: only sequence a
+};
+// Workgroup -> sequences.  Ring-major Delta: a job (a mirror pair or two
+// rings of equal length) of one map, the maps of one job in consecutive
+// workgroups (they share the job's tables through L2).  Map-minor Delta: one
+// ring of two adjacent maps, whose Delta entries are adjacent (32 bytes per m);
+// units of (job, ring of the job, 8 maps), whose entries share 128-byte lines,
+// go to the XCDs in turn (workgroup b runs on XCD b mod 8) and a unit's 4
+// workgroups run back to back on its XCD, so that each line is fetched (or
 // completed) once in that XCD's L2.  Returns false for the padding of the
-// grid (a whole workgroup).
-__device__ __forceinline__ bool job_map(int njobs, int nmaps, int map_minor, int &job, int &mp) {
+// grid and for the missing second ring of a single-ring job (whole workgroups).
+__device__ __forceinline__ bool job_seqs(int njobs, int nmaps, int map_minor, const int2 *__restrict__ jobs,
+                                         JobSeqs &js) {
     if (!map_minor) {
-        job = blockIdx.x / nmaps;
-        mp = blockIdx.x % nmaps;
+        const int2 job = jobs[blockIdx.x / nmaps];
+        const int mp = blockIdx.x % nmaps;
+        js = JobSeqs{job.x, job.y >= 0 ? job.y : job.x, mp, mp, job.y >= 0};
         return true;
     }
     const int groups = (nmaps + 7) / 8;
     const int x = blockIdx.x % 8, k = blockIdx.x / 8;
-    const int unit = (k / 8) * 8 + x;
-    job = unit / groups;
-    mp = (unit % groups) * 8 + k % 8;
-    return job < njobs && mp < nmaps;
+    const int unit = (k / 4) * 8 + x;
+    const int ji = unit / (2 * groups), rem = unit % (2 * groups);
+    const int ma = (rem % groups) * 8 + 2 * (k % 4);
+    if (ji >= njobs || ma >= nmaps) return false;
+    const int2 job = jobs[ji];
+    const int r = rem / groups ? job.y : job.x;
+    if (r < 0) return false;
+    js = JobSeqs{r, r, ma, ma + 1 < nmaps ? ma + 1 : ma, ma + 1 < nmaps};
+    return true;
 }
-// workgroups of one class launch: njobs * nmaps, or for map-minor Delta 64 per
-// 8 units of (job, 8 maps)
+// workgroups of one class launch: njobs * nmaps, or for map-minor Delta 32 per
+// 8 units of (job, ring of the job, 8 maps)
 inline int64_t fft_grid(int njobs, int nmaps, int map_minor) {
     if (!map_minor) return (int64_t)njobs * nmaps;
-    const int64_t units = (int64_t)njobs * ((nmaps + 7) / 8);
-    return (units + 7) / 8 * 64;
+    const int64_t units = (int64_t)njobs * 2 * ((nmaps + 7) / 8);
+    return (units + 7) / 8 * 32;
 }
 
 // Synthesis.  LDS: the twiddle tables, buf[L], plus (fold_rows != 0) two
@@ -424,21 +439,21 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int njobs, int64_t npi
                                                 double *__restrict__ map) {
     extern __shared__ double2 lds[];
     double2 *tlo = lds, *thi = lds + kTwLo, *buf = lds + tw_entries<MAXL>();
-    int ji, mp;
-    if (!job_map(njobs, nmaps, dl.map_minor, ji, mp)) return;  // grid padding (whole workgroup)
-    const int2 job = jobs[ji];
-    const int ra = job.x, rb = job.y;
-    const FftDesc *d = descs + ring_desc[ra];
+    JobSeqs js;
+    if (!job_seqs(njobs, nmaps, dl.map_minor, jobs, js)) return;  // whole workgroup
+    const bool two = js.two;
+    const FftDesc *d = descs + ring_desc[js.ra];
     const int N = d->n, L = d->L;
     load_twiddles<NT>(tlo, thi, d->tw, L);
-    const double2 *__restrict__ Da = delta + mp * dl.s_map + ra * dl.s_ring;
-    const double2 *__restrict__ Db = delta + mp * dl.s_map + (rb >= 0 ? rb : ra) * dl.s_ring;
-    const double pa = phi0[ra], pb = rb >= 0 ? phi0[rb] : 0.0;
+    const double2 *__restrict__ Da = delta + js.ma * dl.s_map + js.ra * dl.s_ring;
+    const double2 *__restrict__ Db = delta + js.mb * dl.s_map + js.rb * dl.s_ring;
+    const double pa = phi0[js.ra], pb = phi0[js.rb];
     Phase pha{nullptr, nullptr, pa}, phb{nullptr, nullptr, pb};
     if (ph_tab) {
         double2 *tab = buf + padded_len<MAXL>() + (fold_rows ? 2 * (mmax + 1) : 0);
         pha = load_phases<NT>(tab, mmax, pa);
-        if (rb >= 0) phb = load_phases<NT>(tab + kPhLo + phase_hi_entries(mmax), mmax, pb);
+        phb = pha;
+        if (two && js.rb != js.ra) phb = load_phases<NT>(tab + kPhLo + phase_hi_entries(mmax), mmax, pb);
         __syncthreads();
     }
     const bool lds_fold = fold_rows && (2 * N < mmax + 1);
@@ -447,11 +462,11 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int njobs, int64_t npi
         // all threads evaluate phases; short rings first sum the rows in columns
         double2 *ta = buf + pd(L), *tb = buf + pd(L) + (mmax + 1);
         phased_terms<NT>(Da, dl.s_m, mmax, pha, ta);
-        if (rb >= 0) phased_terms<NT>(Db, dl.s_m, mmax, phb, tb);
+        if (two) phased_terms<NT>(Db, dl.s_m, mmax, phb, tb);
         __syncthreads();
         if (N <= NT) {
             lim = fold_columns<NT>(ta, N, mmax);
-            if (rb >= 0) fold_columns<NT>(tb, N, mmax);
+            if (two) fold_columns<NT>(tb, N, mmax);
             __syncthreads();
         }
     }
@@ -463,14 +478,14 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int njobs, int64_t npi
             const double2 *ta = buf + pd(L), *tb = buf + pd(L) + (mmax + 1);
             a0 = fold_terms(ta, k, N, lim);
             a1 = fold_terms(ta, kn, N, lim);
-            if (rb >= 0) {
+            if (two) {
                 b0 = fold_terms(tb, k, N, lim);
                 b1 = fold_terms(tb, kn, N, lim);
             }
         } else {
             a0 = fold_bin(Da, dl.s_m, k, N, mmax, pha);
             a1 = fold_bin(Da, dl.s_m, kn, N, mmax, pha);
-            if (rb >= 0) {
+            if (two) {
                 b0 = fold_bin(Db, dl.s_m, k, N, mmax, phb);
                 b1 = fold_bin(Db, dl.s_m, kn, N, mmax, phb);
             }
@@ -486,12 +501,12 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int njobs, int64_t npi
     }
     __syncthreads();
     transform<MAXL, NT>(buf, d, TwLds{tlo, thi});
-    double *outa = map + (int64_t)mp * npix + ofs[ra];
-    double *outb = map + (int64_t)mp * npix + (rb >= 0 ? ofs[rb] : 0);
+    double *outa = map + (int64_t)js.ma * npix + ofs[js.ra];
+    double *outb = map + (int64_t)js.mb * npix + ofs[js.rb];
     for (int j = threadIdx.x; j < N; j += NT) {
         const double2 z = result_at(buf, d, j);  // FFT(conj g)_j; IDFT(g)_j = conj of it
         outa[j] = z.x;
-        if (rb >= 0) outb[j] = -z.y;
+        if (two) outb[j] = -z.y;
     }
 }
 
@@ -507,30 +522,30 @@ __global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int njobs, int64_t npi
                                                 double2 *__restrict__ delta) {
     extern __shared__ double2 lds[];
     double2 *tlo = lds, *thi = lds + kTwLo, *buf = lds + tw_entries<MAXL>();
-    int ji, mp;
-    if (!job_map(njobs, nmaps, dl.map_minor, ji, mp)) return;  // grid padding (whole workgroup)
-    const int2 job = jobs[ji];
-    const int ra = job.x, rb = job.y;
-    const FftDesc *d = descs + ring_desc[ra];
+    JobSeqs js;
+    if (!job_seqs(njobs, nmaps, dl.map_minor, jobs, js)) return;  // whole workgroup
+    const bool two = js.two;
+    const FftDesc *d = descs + ring_desc[js.ra];
     const int N = d->n;
     load_twiddles<NT>(tlo, thi, d->tw, d->L);
-    const double pa = phi0[ra], wa = weight[ra];
-    const double pb = rb >= 0 ? phi0[rb] : 0.0, wb = rb >= 0 ? weight[rb] : 0.0;
+    const double pa = phi0[js.ra], wa = weight[js.ra];
+    const double pb = phi0[js.rb], wb = weight[js.rb];
     // phase tables: visible after the barrier that follows the input below
     Phase pha{nullptr, nullptr, pa}, phb{nullptr, nullptr, pb};
     if (ph_tab) {
         double2 *tab = buf + padded_len<MAXL>();
         pha = load_phases<NT>(tab, mmax, pa);
-        if (rb >= 0) phb = load_phases<NT>(tab + kPhLo + phase_hi_entries(mmax), mmax, pb);
+        phb = pha;
+        if (two && js.rb != js.ra) phb = load_phases<NT>(tab + kPhLo + phase_hi_entries(mmax), mmax, pb);
     }
-    const double *ina = map + (int64_t)mp * npix + ofs[ra];
-    const double *inb = map + (int64_t)mp * npix + (rb >= 0 ? ofs[rb] : 0);
+    const double *ina = map + (int64_t)js.ma * npix + ofs[js.ra];
+    const double *inb = map + (int64_t)js.mb * npix + ofs[js.rb];
     for (int j = threadIdx.x; j < N; j += NT)
-        buf[pd(j)] = input_point(make_double2(ina[j], rb >= 0 ? inb[j] : 0.0), d, j);
+        buf[pd(j)] = input_point(make_double2(ina[j], two ? inb[j] : 0.0), d, j);
     __syncthreads();
     transform<MAXL, NT>(buf, d, TwLds{tlo, thi});
-    double2 *Da = delta + mp * dl.s_map + ra * dl.s_ring;
-    double2 *Db = delta + mp * dl.s_map + (rb >= 0 ? rb : ra) * dl.s_ring;
+    double2 *Da = delta + js.ma * dl.s_map + js.ra * dl.s_ring;
+    double2 *Db = delta + js.mb * dl.s_map + js.rb * dl.s_ring;
     for (int m = threadIdx.x; m <= mmax; m += NT) {
         const int k = m % N, kn = (N - k) % N;
         const double2 Z = result_at(buf, d, k), Zn = result_at(buf, d, kn);
@@ -540,7 +555,7 @@ __global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int njobs, int64_t npi
         const double2 ea = pha(m);
         // w * conj(e) * S
         Da[m * dl.s_m] = make_double2(wa * fma(Sa.x, ea.x, Sa.y * ea.y), wa * fma(Sa.y, ea.x, -Sa.x * ea.y));
-        if (rb >= 0) {
+        if (two) {
             const double2 eb = phb(m);
             Db[m * dl.s_m] = make_double2(wb * fma(Sb.x, eb.x, Sb.y * eb.y), wb * fma(Sb.y, eb.x, -Sb.x * eb.y));
         }

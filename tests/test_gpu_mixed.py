@@ -255,10 +255,11 @@ def test_mixed_batched_gl1025_lmax1024_64maps(sht):
 
 @pytest.mark.parametrize("nmaps", [1, 12, 40])
 def test_map_minor_delta_layout_is_bitwise_equal(sht, nmaps):
-    """SHT_DELTA_MAP_MINOR only moves Delta: every stage gives the same bits
-    as with the ring-major layout (FFT stages in FP64 and mixed Legendre
-    stages), and the combined mixed transforms (which use it internally)
-    equal the stage composition."""
+    """SHT_DELTA_MAP_MINOR moves Delta.  The mixed Legendre stages give the
+    same bits in either layout.  The FFT stages pair two adjacent maps of one
+    ring in a complex transform instead of the two rings of a mirror pair, so
+    they agree to rounding (the ring-major FFT stages are pinned to the oracle
+    at 1e-12).  The combined mixed transforms equal the stage composition."""
     import torch
     lmax, mmax, g = 77, 61, si.healpix(32)
     MM = sht.SHT_DELTA_MAP_MINOR
@@ -267,11 +268,13 @@ def test_map_minor_delta_layout_is_bitwise_equal(sht, nmaps):
     say(f"map-minor layout hp32 lmax={lmax} mmax={mmax} nmaps={nmaps}")
     d = dev(rng.standard_normal((nmaps, g.nrings, mmax + 1)) + 1j * rng.standard_normal((nmaps, g.nrings, mmax + 1)))
     d_mm = d.permute(1, 2, 0).contiguous()
-    assert torch.equal(sht.delta2map(d, g, mmax), sht.delta2map(d_mm, g, mmax, flags=MM))
+    rel = lambda x, y: ((x - y).norm() / y.norm()).item()
+    assert rel(sht.delta2map(d_mm, g, mmax, flags=MM), sht.delta2map(d, g, mmax)) <= 1e-14
     mp = dev(np.stack([si.random_map(g, 1100 + i) for i in range(nmaps)]))
     ds = sht.map2delta(mp, g, mmax)
     ds_mm = sht.map2delta(mp, g, mmax, flags=MM)
-    assert torch.equal(ds.permute(1, 2, 0), ds_mm)
+    assert rel(ds_mm, ds.permute(1, 2, 0)) <= 1e-14
+    ds_mm = ds.permute(1, 2, 0).contiguous()  # the same Delta^S in both layouts below
     a = dev(batch(lmax, mmax, nmaps, 1200))
     dx = sht.alm2delta(a, g, lmax, mmax, flags=X)
     dx_mm = sht.alm2delta(a, g, lmax, mmax, flags=X | MM)
