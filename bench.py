@@ -248,6 +248,8 @@ def main():
     ap.add_argument("--batch", type=int, default=64,
                     help="maps in the batched mixed-precision alm2map leg (0: skip it)")
     ap.add_argument("--copy-probe", type=int, default=0, help="run only a device copy of this many bytes")
+    ap.add_argument("--peak-probe", action="store_true",
+                    help="run only the throughput probes (FP64 FMA, FP32 and BF16 matrix instructions)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); run it with --gpus 1.",
@@ -255,6 +257,14 @@ def main():
         sys.exit(2)
     if args.copy_probe:
         copy_probe(args.copy_probe)
+        return
+    if args.peak_probe:
+        import paper_1106_0159_amd as sht
+        rates = [sht.probe_rate(k) for k in sht.PROBE_KINDS]
+        print(json.dumps({"peak_probe": rates,
+                          "nominal_tflops": {"fp64_fma": PEAK_FP64_VALU_TFLOPS,
+                                             "fp32_mfma_16x16x4": PEAK_FP32_MFMA_TFLOPS,
+                                             "bf16_mfma_16x16x32": 2500.0}}))
         return
 
     import numpy as np

@@ -23,7 +23,8 @@ SHT_MIXED = 1  # flag: FP32 matrix-core Legendre contraction (include/sht.h)
 SHT_DELTA_MAP_MINOR = 2  # flag: stage-call Delta laid out [nrings][mmax+1][nmaps]
 
 EXPORTS = ("sht_workspace_bytes", "sht_alm2map", "sht_map2alm", "sht_alm2delta", "sht_delta2map",
-           "sht_map2delta", "sht_delta2alm", "sht_strerror", "sht_shutdown")
+           "sht_map2delta", "sht_delta2alm", "sht_strerror", "sht_shutdown",
+           "sht_probe_flops", "sht_probe_run")
 
 
 class ShtError(RuntimeError):
@@ -66,6 +67,10 @@ def lib() -> ctypes.CDLL:
         L.sht_strerror.argtypes = [I]
         L.sht_shutdown.restype = None
         L.sht_shutdown.argtypes = []
+        L.sht_probe_flops.restype = ctypes.c_double
+        L.sht_probe_flops.argtypes = [I, I, I]
+        L.sht_probe_run.restype = I
+        L.sht_probe_run.argtypes = [I, I, I, P, P]
         _lib = L
     return _lib
 
@@ -230,6 +235,29 @@ def delta2alm(delta, geom, lmax: int, mmax: int | None = None, out=None, ws=None
                              ws.numel() * ws.element_size(), flags, _stream_ptr(stream))
     _check(rc, "sht_delta2alm")
     return out
+
+
+PROBE_KINDS = {"fp64_fma": 0, "fp32_mfma_16x16x4": 1, "bf16_mfma_16x16x32": 2}  # include/sht_probe.h
+
+
+def probe_rate(kind: str, blocks: int = 8192, iters: int = 4000, device="cuda") -> dict:
+    """Attained TFLOP/s of one throughput probe (one warm-up launch, one timed
+    with HIP events on the current stream)."""
+    torch = _torch()
+    k = PROBE_KINDS[kind]
+    flops = lib().sht_probe_flops(k, blocks, iters)
+    if flops <= 0:
+        raise ShtError(SHT_EINVAL, "sht_probe_flops")
+    out = torch.empty(blocks * 256, dtype=torch.float64, device=device)
+    s = _stream_ptr(None)
+    _check(lib().sht_probe_run(k, blocks, iters, out.data_ptr(), s), "sht_probe_run")
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    _check(lib().sht_probe_run(k, blocks, iters, out.data_ptr(), s), "sht_probe_run")
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    return {"kind": kind, "blocks": blocks, "iters": iters, "flops": flops, "ms": ms, "tflops": flops / ms / 1e9}
 
 
 def shutdown() -> None:

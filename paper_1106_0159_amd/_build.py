@@ -8,7 +8,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libsht.so")
-SOURCES = ["sht_abi.cpp", "sht_plan.cpp", "k_legendre.hip", "k_legendre_mx.hip", "k_ring_fft.hip"]
+SOURCES = ["sht_abi.cpp", "sht_plan.cpp", "k_legendre.hip", "k_legendre_mx.hip", "k_ring_fft.hip", "k_probe.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -2,6 +2,7 @@
 header declares, sizes its workspace, and rejects invalid arguments on the host
 before any device work is enqueued."""
 import ctypes
+import glob
 import os
 import re
 
@@ -11,7 +12,7 @@ import pytest
 import sht_inputs as si
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "sht.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 sht = pytest.importorskip("paper_1106_0159_amd")
 
@@ -24,7 +25,7 @@ def L():
 
 
 def declared_functions():
-    text = open(HEADER).read()
+    text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
     return sorted(set(re.findall(r"\b(sht_[a-z0-9_]+)\s*\(", text)))
 
