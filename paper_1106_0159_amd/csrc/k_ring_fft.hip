@@ -1,7 +1,9 @@
-// Ring Fourier stage for gfx950: one workgroup per ring (and map), the
-// ring's transform held in LDS.  Rings are launched in classes of transform
-// length (<= 1024, 2048, 4096, 8192 points) so that LDS and the per-thread
-// register arrays are sized for the class, with about four points per thread.
+// Ring Fourier stage for gfx950: one workgroup per job, two real sequences of
+// one length transformed as one complex sequence held in LDS (the two rings
+// of a mirror pair of one map, or with map-minor Delta one ring of two
+// adjacent maps).  Jobs are launched in classes of transform length (<= 1024,
+// 2048, 4096, 8192 points) so that LDS and the per-thread register arrays are
+// sized for the class, with four or eight points per thread.
 //
 // Synthesis (Sec. 2.2 eq. Delta2map, with phi_j = phi0 + 2 pi j/N): for a
 // real map the m < 0 half is the conjugate of the m > 0 half (eq. DeltaDef),

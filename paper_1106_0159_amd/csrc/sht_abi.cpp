@@ -207,8 +207,8 @@ int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *
         return rc;
     char *ws = static_cast<char *>(workspace);
     void *delta = ws, *partials = ws + round256(db);
-    // ring-major here also with SHT_MIXED: the strided stores of the ring FFT
-    // would cost more than the analysis kernel's reads gain
+    // ring-major here also with SHT_MIXED: with map-minor Delta the ring FFT
+    // loses about what the analysis kernel gains on its reads
     const DeltaLayout dl = delta_layout(h.nrings, mmax, nmaps, false);
     if ((rc = launch_fft_ana(*p, mmax, map, delta, dl, nmaps, st))) return rc;
     if (flags & SHT_MIXED) return launch_leg_ana_mx(*c, *p, *s, delta, dl, alm, nmaps, partials, st);
