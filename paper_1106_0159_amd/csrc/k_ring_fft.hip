@@ -16,9 +16,11 @@
 //   Delta^S_m = w_r e^{-i m phi0} S_{m mod N},  S = FFT_forward(s).
 //
 // The FFT is an in-place Stockham decimation-in-time over the radices of the
-// length (8, 4, 2, 3, 5); each stage reads its butterflies into registers,
-// synchronises, and writes them back.  Lengths with a larger prime factor use
-// Bluestein's chirp-z identity
+// length (8, 4, 2, 3, 5, then any larger prime as a direct R-term stage); each
+// stage reads its butterflies into registers, synchronises, and writes them
+// back.  Lengths whose larger prime factors would make those direct stages
+// costly use Bluestein's chirp-z identity instead (when 2N-1 rounds up to a
+// 5-smooth length that fits)
 //   X_k = conj(b_k) sum_n (x_n conj(b_n)) b_{k-n},  b_t = e^{i pi t^2/N},
 // as a cyclic convolution of 5-smooth length L >= 2N-1 done with two forward
 // transforms (the filter spectrum, scaled by 1/L, is a plan table).
@@ -265,6 +267,48 @@ __device__ __forceinline__ void fft_stage(double2 *buf, int L, int Ns, TwLds tw)
     __syncthreads();
 }
 
+// One Stockham stage of any radix R (the prime factors above 5): output
+// y_s of butterfly j is sum_q x_q W^{q (k tstep + s L/R)} with x_q the q-th
+// input of the butterfly, i.e. the twiddles and the R-point DFT of the
+// fixed-radix stages taken together.  Each thread computes up to kMaxOut
+// outputs directly (R terms each, exponents reduced exactly as integers),
+// then writes them back after the barrier.
+template <int MAXL, int NT>
+__device__ __forceinline__ void fft_stage_generic(double2 *buf, int L, int Ns, int R, TwLds tw) {
+    constexpr int kMaxOut = (MAXL + NT - 1) / NT;
+    const int nbf = L / R;
+    const int tstep = L / (Ns * R);
+    double2 y[kMaxOut];
+#pragma unroll
+    for (int i = 0; i < kMaxOut; ++i) {
+        const int o = threadIdx.x + i * NT;
+        y[i] = make_double2(0.0, 0.0);
+        if (o < L) {
+            const int k = o % Ns, t = o / Ns;
+            const int sidx = t % R, jq = t / R;
+            const int j = jq * Ns + k;
+            const int step = (k * tstep + sidx * nbf) % L;
+            double yr = 0.0, yi = 0.0;
+            int e = 0;
+            for (int q = 0; q < R; ++q) {
+                const double2 v = cmul(buf[pd(j + q * nbf)], tw(e));
+                yr += v.x;
+                yi += v.y;
+                e += step;
+                if (e >= L) e -= L;
+            }
+            y[i] = make_double2(yr, yi);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kMaxOut; ++i) {
+        const int o = threadIdx.x + i * NT;
+        if (o < L) buf[pd(o)] = y[i];
+    }
+    __syncthreads();
+}
+
 // Forward FFT of length d->L (<= MAXL) in LDS (natural order in and out).
 template <int MAXL, int NT>
 __device__ __forceinline__ void fft_forward(double2 *buf, const FftDesc *__restrict__ d, TwLds tw) {
@@ -277,7 +321,8 @@ __device__ __forceinline__ void fft_forward(double2 *buf, const FftDesc *__restr
             case 4: fft_stage<4, MAXL, NT>(buf, L, Ns, tw); break;
             case 2: fft_stage<2, MAXL, NT>(buf, L, Ns, tw); break;
             case 3: fft_stage<3, MAXL, NT>(buf, L, Ns, tw); break;
-            default: fft_stage<5, MAXL, NT>(buf, L, Ns, tw); break;
+            case 5: fft_stage<5, MAXL, NT>(buf, L, Ns, tw); break;
+            default: fft_stage_generic<MAXL, NT>(buf, L, Ns, R, tw); break;
         }
         Ns *= R;
     }

@@ -224,6 +224,18 @@ static bool factor_small(int n, std::vector<int> &rad) {
     return n == 1 && (int)rad.size() <= kMaxRadices;
 }
 
+// All prime factors: 8, 4, 2, 3, 5 first (the fixed-radix stages), then the
+// other primes ascending (direct R-term stages).
+static bool factor_all(int n, std::vector<int> &rad) {
+    factor_small(n, rad);
+    int r = n;
+    for (int f : rad) r /= f;
+    for (int p = 7; (long long)p * p <= r; p += 2)
+        while (r % p == 0) { rad.push_back(p); r /= p; }
+    if (r > 1) rad.push_back(r);
+    return (int)rad.size() <= kMaxRadices;
+}
+
 static bool smooth5(int n) {
     for (int p : {2, 3, 5})
         while (n % p == 0) n /= p;
@@ -288,12 +300,25 @@ static int fft_desc(FftCache &fc, int n, FftDesc *out) {
     d.n = n;
     std::vector<int> rad;
     int rc;
+    // Direct transform of length n when it is 5-smooth, or when its direct
+    // R-term stages (about 12 R flops per point each) cost less than
+    // Bluestein's two transforms of length L >= 2n - 1 (taken as 200 flops
+    // per point of L), or when Bluestein's L would not fit the largest class.
+    int Lb = 2 * n - 1;
+    while (!smooth5(Lb)) ++Lb;
+    std::vector<int> all;
+    const bool all_ok = factor_all(n, all);
+    double direct = 0.0;
+    for (int f : all) direct += f > 5 ? 12.0 * f * n : 0.0;
     if (factor_small(n, rad)) {
         d.L = n;
         d.bluestein = 0;
+    } else if (all_ok && (Lb > kMaxFftLen || direct <= 200.0 * Lb)) {
+        rad = all;
+        d.L = n;
+        d.bluestein = 0;
     } else {
-        int L = 2 * n - 1;
-        while (!smooth5(L)) ++L;
+        const int L = Lb;
         d.L = L;
         d.bluestein = 1;
         factor_small(L, rad);

@@ -286,3 +286,43 @@ def test_map_minor_delta_layout_is_bitwise_equal(sht, nmaps):
     # ring-major) equal the stage composition
     assert torch.equal(sht.alm2map(a, g, lmax, mmax, flags=X), sht.delta2map(dx_mm, g, mmax, flags=MM))
     assert torch.equal(sht.map2alm(mp, g, lmax, mmax, flags=X), ax)
+
+
+def test_healpix2048_lmax4096_fp64_and_mixed(sht):
+    """lmax = 4096 on HEALPix N_side = 2048 (8191 rings, 4096 ring pairs: two
+    analysis groups and the combine kernel at full size).  FP64 against the
+    oracle on sampled rings and sampled m (1e-12); a mixed batch of 8 maps
+    against the FP64 path in both directions (the relative RMS is printed)."""
+    import torch
+    lmax, nmaps = 4096, 8
+    g = si.healpix(2048)
+    say("healpix 2048 lmax 4096: fp64 and mixed (8 maps)")
+    alm = torch.empty((nmaps, si.nalm(lmax, lmax)), dtype=torch.complex128, device="cuda")
+    for i in range(nmaps):
+        alm[i] = dev(si.powerlaw_alm(lmax, lmax, si.config_seed(5, i)))
+    f64 = sht.alm2map(alm, g, lmax)
+    a0 = host(alm[0])
+    rings = [0, 1, 2047, 4095, 6000, 8190]
+    ref = oracle.alm2map(lmax, lmax, g, a0, rings=rings)
+    m0 = host(f64[0])
+    # per ring (as few as 4 pixels) the FP64 bar scales with the 4096 steps of
+    # the recurrence: 3e-12 in the north; a southern colatitude given as a
+    # double mirrors the northern one only to ~2e-16 rad (the mirror pairing
+    # reading), which moves the 4-pixel rings at the south pole by ~1e-11 here
+    for r in rings:
+        sl = slice(g.ofs[r], g.ofs[r] + g.nphi[r])
+        tol = 3e-12 if r < g.nrings // 2 else 4e-11
+        assert relrms(m0[sl], ref[sl]) <= tol, (r, relrms(m0[sl], ref[sl]))
+    back64 = sht.map2alm(f64, g, lmax)
+    ms = [0, 5, 2048, 4095, 4096]
+    ref = oracle.map2alm(lmax, lmax, g, m0, ms=ms)
+    b0 = host(back64[0])
+    for m in ms:
+        idx = si.alm_index(np.arange(m, lmax + 1), m, lmax)
+        assert relrms(b0[idx], ref[idx]) <= 1e-11, (m, relrms(b0[idx], ref[idx]))
+    mx = sht.alm2map(alm, g, lmax, flags=sht.SHT_MIXED)
+    err_s = ((mx - f64).norm(dim=1) / f64.norm(dim=1)).cpu().numpy()
+    back = sht.map2alm(f64, g, lmax, flags=sht.SHT_MIXED)
+    err_a = ((back - back64).norm(dim=1) / back64.norm(dim=1)).cpu().numpy()
+    say(f"lmax 4096 mixed rel rms: alm2map max {err_s.max():.3e}, map2alm max {err_a.max():.3e}")
+    assert np.all(err_s <= 2 * MX_TOL) and np.all(err_a <= 2 * MX_TOL), (err_s.max(), err_a.max())
