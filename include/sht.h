@@ -86,8 +86,9 @@ enum sht_flags {
      * north +- south Delta_m of a ring pair (analysis), and the per-m matrix
      * products of Sec. 3 (eq. matrix_vec and its transpose, one column per
      * map and real/imaginary part) run on the FP32 matrix cores: synthesis
-     * sums over l in FP32; analysis sums 32 l at a time over up to 256 ring
-     * pairs in FP32 and adds those sums in FP64.  The Delta and FFT stages stay
+     * sums over l in FP32 (above lmax 2048 in two chains, the lower and the
+     * upper half of the l range, added in FP64); analysis sums 32 l at a time
+     * over up to 256 ring pairs in FP32 and adds those sums in FP64.  The Delta and FFT stages stay
      * FP64.  Expected relative RMS error against the FP64 transform: about
      * 1e-7 to 1e-6.  Built for batches: a wave covers 8 to 32 maps in
      * synthesis and 8 in analysis, so nmaps >= 8 fills it.  sht_alm2map with

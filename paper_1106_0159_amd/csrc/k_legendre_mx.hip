@@ -17,7 +17,8 @@
 // FP32 over l by v_mfma_f32_16x16x4_f32.  The ring FFTs stay FP64.
 //
 // Tiling: a wave owns 64 ring pairs (one recurrence per lane) and 16 NCF
-// columns of one m; a workgroup holds four such waves on 256 consecutive
+// columns (NCF = 1, 2, 4; 1 above lmax 2048, where the sum over l runs in two
+// FP32 chains added in FP64) of one m; a workgroup holds four such waves on 256 consecutive
 // pairs with the same columns, and the pair tiles of one m share one XCD's L2
 // (the mapping of the FP64 kernels).  l advances in blocks of kMxL = 32: each
 // lane runs 32 recurrence steps and writes its 16 even and 16 odd q (FP32) to
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_prescale_mx(int lmax, int nmaps, int
     }
 }
 
-template <int NCF>
+template <int NCF, int CH>
 __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, int nslots, int tiles, DeltaLayout dl,
                                                         int nmaps, int64_t mxblocks,
                                                         const int64_t *__restrict__ mxofs,
@@ -105,16 +106,22 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
     const float *__restrict__ apm = ap + ((int64_t)cg * mxblocks + mxofs[m]) * kTile;
     const int nb = mx_blocks(lmax, m);
 
-    floatx4 acc[2][4][NCF];
+    // CH FP32 accumulator chains: with two, the first half of the l-blocks
+    // and the second are summed apart and added in FP64 at the end (each
+    // chain then sums half the terms, the second only the small tail)
+    floatx4 acc[CH][2][4][NCF];
 #pragma unroll
-    for (int p = 0; p < 2; ++p)
+    for (int c = 0; c < CH; ++c)
 #pragma unroll
-        for (int rf = 0; rf < 4; ++rf)
+        for (int p = 0; p < 2; ++p)
 #pragma unroll
-            for (int cf = 0; cf < NCF; ++cf) acc[p][rf][cf] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int rf = 0; rf < 4; ++rf)
+#pragma unroll
+                for (int cf = 0; cf < NCF; ++cf) acc[c][p][rf][cf] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     double q1 = 0.0, q2 = 0.0;  // a pair carries zeros until it starts
     const int kb0 = lo <= lmax ? (lo - m) / kMxL : nb;
+    const int kb_mid = kb0 + (nb - kb0) / 2;
     // a' operands one block ahead: those of block kb are loaded while block
     // kb - 1 runs (the index is clamped, so the load after the last block
     // re-reads it and stays in bounds)
@@ -186,16 +193,26 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
 #pragma unroll
             for (int rf = 0; rf < 4; ++rf)
                 bv[p][rf] = pt[w][p][rf * 16 + c16][kq];
+        auto mma = [&](floatx4 (&a)[2][4][NCF]) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+            for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int p = 0; p < 2; ++p)
+                for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int rf = 0; rf < 4; ++rf)
+                    for (int rf = 0; rf < 4; ++rf)
 #pragma unroll
-                    for (int cf = 0; cf < NCF; ++cf)
-                        acc[p][rf][cf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[p][cf][j], bv[p][rf][j],
-                                                                              acc[p][rf][cf], 0, 0, 0);
+                        for (int cf = 0; cf < NCF; ++cf)
+                            a[p][rf][cf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[p][cf][j], bv[p][rf][j],
+                                                                                a[p][rf][cf], 0, 0, 0);
+        };
+        if constexpr (CH == 2) {
+            if (kb < kb_mid)
+                mma(acc[0]);
+            else
+                mma(acc[CH - 1]);
+        } else {
+            mma(acc[0]);
+        }
     }
 
     // lane l holds rows (columns of the batch) 4 (l / 16) + r, r < 4, i.e. two
@@ -211,8 +228,14 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
             for (int h = 0; h < 2; ++h) {
                 const int map = cg * (NC / 2) + cf * 8 + 2 * kq + h;
                 if (map >= nmaps) continue;
-                const double er = acc[0][rf][cf][2 * h], ei = acc[0][rf][cf][2 * h + 1];
-                const double orr = acc[1][rf][cf][2 * h], oi = acc[1][rf][cf][2 * h + 1];
+                double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
+#pragma unroll
+                for (int c = 0; c < CH; ++c) {
+                    er += acc[c][0][rf][cf][2 * h];
+                    ei += acc[c][0][rf][cf][2 * h + 1];
+                    orr += acc[c][1][rf][cf][2 * h];
+                    oi += acc[c][1][rf][cf][2 * h + 1];
+                }
                 double2 *d = delta + map * dl.s_map + m * dl.s_m;
                 d[rN * dl.s_ring] = make_double2(er + orr, ei + oi);
                 if (rS >= 0) d[rS * dl.s_ring] = make_double2(er - orr, ei - oi);
@@ -403,7 +426,7 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
     }
 }
 
-template <int NCF>
+template <int NCF, int CH>
 int launch_syn_mx_t(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm, void *aprime,
                     void *delta, DeltaLayout dl, int nmaps, hipStream_t st) {
     constexpr int NC = 16 * NCF;
@@ -415,7 +438,7 @@ int launch_syn_mx_t(const CoefTables &c, const GeomPlan &p, const StartTable &s,
                        dim3(kBlock), 0, st, c.lmax, nmaps, c.nalm, c.mxblocks, c.mxofs,
                        static_cast<const double2 *>(alm), c.cfac, static_cast<float *>(aprime));
     SHT_HIP(hipGetLastError());
-    hipLaunchKernelGGL(k_leg_syn_mx<NCF>, dim3((unsigned)gx, (unsigned)ncg), dim3(kBlock), 0, st, c.lmax, c.mmax,
+    hipLaunchKernelGGL((k_leg_syn_mx<NCF, CH>), dim3((unsigned)gx, (unsigned)ncg), dim3(kBlock), 0, st, c.lmax, c.mmax,
                        p.nslots, tiles, dl, nmaps, c.mxblocks, c.mxofs, static_cast<const float *>(aprime),
                        c.alpha, s.lstart, s.state, p.slot_x, p.slot_north, p.slot_south,
                        static_cast<double2 *>(delta));
@@ -440,22 +463,30 @@ int launch_leg_ana_mx(const CoefTables &c, const GeomPlan &p, const StartTable &
     return groups > 1 ? launch_ana_combine(c, nmaps, groups, partials, alm, st) : SHT_OK;
 }
 
-int mx_col_frags(int nmaps) { return nmaps <= 8 ? 1 : nmaps <= 16 ? 2 : 4; }
+// Above kMxOneChainLmax synthesis sums in two chains (the FP32 error of one
+// chain over more l would pass the 1e-6 target), which needs the accumulator
+// registers of two column groups: 8 maps per wave then (16 would spill).
+constexpr int kMxOneChainLmax = 2048;
+int mx_col_frags(int nmaps, int lmax) {
+    if (lmax > kMxOneChainLmax) return 1;
+    return nmaps <= 8 ? 1 : nmaps <= 16 ? 2 : 4;
+}
 
 size_t mx_aprime_bytes(int lmax, int mmax, int nmaps) {
     int64_t blocks = 0;
     for (int m = 0; m <= mmax; ++m) blocks += mx_blocks(lmax, m);
-    const int nc = 16 * mx_col_frags(nmaps);
+    const int nc = 16 * mx_col_frags(nmaps, lmax);
     const int64_t ncg = (nmaps + nc / 2 - 1) / (nc / 2);
     return (size_t)(ncg * blocks * 2 * nc * kMxHalf) * sizeof(float);
 }
 
 int launch_leg_syn_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm, void *aprime,
                       void *delta, DeltaLayout dl, int nmaps, hipStream_t st) {
-    switch (mx_col_frags(nmaps)) {
-        case 1: return launch_syn_mx_t<1>(c, p, s, alm, aprime, delta, dl, nmaps, st);
-        case 2: return launch_syn_mx_t<2>(c, p, s, alm, aprime, delta, dl, nmaps, st);
-        default: return launch_syn_mx_t<4>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+    if (c.lmax > kMxOneChainLmax) return launch_syn_mx_t<1, 2>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+    switch (mx_col_frags(nmaps, c.lmax)) {
+        case 1: return launch_syn_mx_t<1, 1>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+        case 2: return launch_syn_mx_t<2, 1>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+        default: return launch_syn_mx_t<4, 1>(c, p, s, alm, aprime, delta, dl, nmaps, st);
     }
 }
 

@@ -81,7 +81,8 @@ def test_workspace_bytes_values_and_monotonic():
 def test_workspace_bytes_mixed():
     """SHT_MIXED: aux holds FP32 tiles of c a_lm, [column group][l-block of
     column m][parity][16 NCF columns][16 k] floats, NCF = 1, 2, 4 for up to
-    8, 16 and more maps (8 NCF maps per column group), kMxL = 32 l per block."""
+    8, 16 and more maps (8 NCF maps per column group; NCF = 1 above
+    lmax 2048), kMxL = 32 l per block."""
     g = si.healpix(8)
     r256 = lambda b: (b + 255) // 256 * 256
     delta = lambda lmax, n: r256(n * g.nrings * (lmax + 1) * 16)
@@ -89,10 +90,12 @@ def test_workspace_bytes_mixed():
     def tiles(lmax, nmaps):
         blocks = sum((lmax - m + 32) // 32 for m in range(lmax + 1))
         ncf = 1 if nmaps <= 8 else 2 if nmaps <= 16 else 4
+        if lmax > 2048:  # two accumulator chains: 8 maps per wave
+            ncf = 1
         ncg = -(-nmaps // (8 * ncf))
         return ncg * blocks * 2 * (16 * ncf) * 16 * 4
 
-    for lmax, nmaps in [(16, 1), (16, 3), (16, 12), (16, 20), (16, 40), (70, 33), (0, 1)]:
+    for lmax, nmaps in [(16, 1), (16, 3), (16, 12), (16, 20), (16, 40), (70, 33), (0, 1), (2048, 40), (2049, 40)]:
         assert _ws(lmax, lmax, g, nmaps, sht.SHT_MIXED) == delta(lmax, nmaps) + r256(tiles(lmax, nmaps)), (lmax, nmaps)
     # the Delta layout flag does not change the workspace
     for nmaps in (1, 20):

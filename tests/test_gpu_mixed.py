@@ -291,8 +291,9 @@ def test_map_minor_delta_layout_is_bitwise_equal(sht, nmaps):
 def test_healpix2048_lmax4096_fp64_and_mixed(sht):
     """lmax = 4096 on HEALPix N_side = 2048 (8191 rings, 4096 ring pairs: two
     analysis groups and the combine kernel at full size).  FP64 against the
-    oracle on sampled rings and sampled m (1e-12); a mixed batch of 8 maps
-    against the FP64 path in both directions (the relative RMS is printed)."""
+    oracle on sampled rings and sampled m; a mixed batch of 8 maps against the
+    FP64 path in both directions at 1e-6 (synthesis sums in two FP32 chains
+    above lmax 2048)."""
     import torch
     lmax, nmaps = 4096, 8
     g = si.healpix(2048)
@@ -325,4 +326,4 @@ def test_healpix2048_lmax4096_fp64_and_mixed(sht):
     back = sht.map2alm(f64, g, lmax, flags=sht.SHT_MIXED)
     err_a = ((back - back64).norm(dim=1) / back64.norm(dim=1)).cpu().numpy()
     say(f"lmax 4096 mixed rel rms: alm2map max {err_s.max():.3e}, map2alm max {err_a.max():.3e}")
-    assert np.all(err_s <= 2 * MX_TOL) and np.all(err_a <= 2 * MX_TOL), (err_s.max(), err_a.max())
+    assert np.all(err_s <= MX_TOL) and np.all(err_a <= MX_TOL), (err_s.max(), err_a.max())
