@@ -303,7 +303,9 @@ def test_healpix2048_lmax4096_fp64_and_mixed(sht):
         alm[i] = dev(si.powerlaw_alm(lmax, lmax, si.config_seed(5, i)))
     f64 = sht.alm2map(alm, g, lmax)
     a0 = host(alm[0])
-    rings = [0, 1, 2047, 4095, 6000, 8190]
+    # ring 2038 has 8156 = 4 x 2039 pixels: a direct radix-2039 stage
+    rings = [0, 1, 2038, 2047, 4095, 6000, 8190]
+    assert g.nphi[2038] == 4 * 2039
     ref = oracle.alm2map(lmax, lmax, g, a0, rings=rings)
     m0 = host(f64[0])
     # per ring (as few as 4 pixels) the FP64 bar scales with the 4096 steps of
