@@ -184,3 +184,18 @@ def test_invalid_arguments_rejected_on_host(L):
     assert L.sht_delta2alm(4, 4, g.ref(), a, m, 1, None, big, 0, None) == sht.SHT_EWORKSPACE
     assert L.sht_delta2map(4, g.ref(), None, m, 1, 0, None) == sht.SHT_EINVAL
     assert L.sht_alm2delta(4, 4, g.ref(), a, m, 1, w, 8, 0, None) == sht.SHT_EWORKSPACE
+
+
+def test_probe_flop_counts_and_argument_checks(L):
+    """The throughput probes' flop counts (include/sht_probe.h): 256 threads per
+    workgroup, 8 chains; FP64 FMA 2 flops per lane and step, matrix
+    instructions 2*16*16*K per wave and step (K = 4 for FP32, 32 for BF16)."""
+    blocks, iters = 3, 5
+    assert L.sht_probe_flops(0, blocks, iters) == blocks * 256 * iters * 8 * 2
+    assert L.sht_probe_flops(1, blocks, iters) == blocks * 4 * iters * 8 * 2 * 16 * 16 * 4
+    assert L.sht_probe_flops(2, blocks, iters) == blocks * 4 * iters * 8 * 2 * 16 * 16 * 32
+    for kind, b, it in [(3, 1, 1), (-1, 1, 1), (0, 0, 1), (0, 1, 0)]:
+        assert L.sht_probe_flops(kind, b, it) == 0.0
+    # rejected on the host, before any device call
+    assert L.sht_probe_run(0, 1, 1, None, None) == sht.SHT_EINVAL
+    assert L.sht_probe_run(7, 1, 1, ctypes.c_void_p(0x1000), None) == sht.SHT_EINVAL
