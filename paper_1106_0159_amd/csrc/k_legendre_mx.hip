@@ -43,8 +43,10 @@ constexpr int kPRow = 5;           // 16-byte words per LDS row: 16 k + 4 floats
 constexpr int kWaves = kBlock / 64;
 
 // a'_lm = c_lm a_lm rounded to FP32, in the block-tiled operand layout.  One
-// workgroup per (l-block, m, column group); entries with l > lmax or with a
-// map index >= nmaps are zero, and Im a_l0 is ignored.
+// workgroup per (l-block, m, column group); a thread takes one complex a_lm
+// (consecutive threads: consecutive l of one map, so the reads are
+// contiguous) and writes its two columns into the workgroup's tile.  Entries
+// with l > lmax or with a map index >= nmaps are zero, and Im a_l0 is ignored.
 template <int NCF>
 __global__ __launch_bounds__(kBlock) void k_prescale_mx(int lmax, int nmaps, int64_t nalm, int64_t mxblocks,
                                                       const int64_t *__restrict__ mxofs,
@@ -57,17 +59,19 @@ __global__ __launch_bounds__(kBlock) void k_prescale_mx(int lmax, int nmaps, int
     if (kb >= mx_blocks(lmax, m)) return;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
     float *__restrict__ o = out + ((int64_t)cg * mxblocks + mxofs[m] + kb) * kTile;
-    for (int e = threadIdx.x; e < kTile; e += kBlock) {
-        const int p = e / (NC * kMxHalf), col = (e / kMxHalf) % NC, k = e % kMxHalf;
-        const int l = m + kMxL * kb + 2 * k + p;
-        const int map = cg * (NC / 2) + col / 2;
-        double v = 0.0;
+    for (int e = threadIdx.x; e < kMxL * (NC / 2); e += kBlock) {
+        const int lt = e % kMxL, mm = e / kMxL;  // l offset in the block, map in the group
+        const int l = m + kMxL * kb + lt, map = cg * (NC / 2) + mm;
+        double re = 0.0, im = 0.0;
         if (l <= lmax && map < nmaps) {
             const double2 a = alm[(int64_t)map * nalm + base + l];
-            v = (col & 1) ? (m == 0 ? 0.0 : a.y) : a.x;
-            v *= cfac[base + l];
+            const double c = cfac[base + l];
+            re = a.x * c;
+            im = m == 0 ? 0.0 : a.y * c;
         }
-        o[e] = (float)v;
+        float *__restrict__ t = o + ((lt & 1) * NC + 2 * mm) * kMxHalf + (lt >> 1);
+        t[0] = (float)re;
+        t[kMxHalf] = (float)im;
     }
 }
 
