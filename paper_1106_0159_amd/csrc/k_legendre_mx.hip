@@ -260,15 +260,15 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
 // pairs on the matrix cores with a fresh FP32 accumulator: rows are the 16 l
 // of one parity, columns the 16 columns, K the pairs (in k step j of tile t,
 // lane l takes pair 16 (l / 16) + 4 u + j of the tile for its u-th operand
-// load).  The waves' block sums are added in wave order in FP64 after one
-// barrier (two LDS buffers in turn), scaled by c_lm and written.
+// load).  The waves' sums of two consecutive blocks are added in wave order in
+// FP64 after one barrier (two LDS buffers in turn), scaled by c_lm and written.
 constexpr int kAnaMxWaves = 8;
 constexpr int kAnaMxThreads = 64 * kAnaMxWaves;
 constexpr int kAnaMxTiles = 4;
 constexpr int kAnaMxMaps = 8;   // 16 columns
 constexpr int kQRow = 64 + 4;   // floats per k row of a q tile (padding: conflict-free operand reads)
 static_assert(kAnaMxGroup == kAnaMxWaves * kAnaMxTiles * 64, "pairs per analysis group");
-static_assert(2 * kMxHalf * kAnaMxMaps <= kAnaMxThreads, "one thread per finished (parity, k, map)");
+static_assert(2 * 2 * kMxHalf * kAnaMxMaps <= kAnaMxThreads, "one thread per finished (block, parity, k, map)");
 
 __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int mmax, int nslots, DeltaLayout dl,
                                                               int nmaps, int64_t nalm, int groups,
@@ -283,7 +283,7 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
                                                               double2 *__restrict__ alm,
                                                               double2 *__restrict__ part) {
     __shared__ float qs[kAnaMxWaves][2][kMxHalf][kQRow];
-    __shared__ float red[2][kAnaMxWaves][2][kMxHalf][16];
+    __shared__ float red[2][2][kAnaMxWaves][2][kMxHalf][16];  // [buffer][block of the pair]...
     __shared__ int wlo[kAnaMxWaves];
 
     const MPart mp = xcd_m_part(groups);
@@ -355,10 +355,16 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
         if (l <= lmax && map < nmaps) *out_at(map, l) = make_double2(0.0, 0.0);
     }
 
+    // the wave sums of two consecutive blocks are kept (slot b of the pair)
+    // and added across the waves together: one barrier per two blocks
+    floatx4 acc2[2][2];
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc2[b][0] = acc2[b][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+    int buf = 0;
     for (int kb = kb0; kb < nb; ++kb) {
         const int l0 = __builtin_amdgcn_readfirstlane(m + kMxL * kb);
         const bool tail = l0 + kMxL - 1 > lmax;
-        floatx4 acc[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
+        const int slot = (kb - kb0) & 1;
 #pragma unroll
         for (int t = 0; t < kAnaMxTiles; ++t) {
             if (tlo[t] > l0 + kMxL - 1) continue;  // no pair of the tile has started: all q are 0
@@ -390,34 +396,44 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
             else
                 steps(std::false_type{});
             // LDS operations of one wave complete in order (no barrier needed)
+            auto mma = [&](floatx4 (&acc)[2]) {
 #pragma unroll
-            for (int p = 0; p < 2; ++p) {
+                for (int p = 0; p < 2; ++p) {
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const floatx4 a4 = *reinterpret_cast<const floatx4 *>(&qs[w][p][c16][16 * kq + 4 * u]);
+                    for (int u = 0; u < 4; ++u) {
+                        const floatx4 a4 = *reinterpret_cast<const floatx4 *>(&qs[w][p][c16][16 * kq + 4 * u]);
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4[j], p ? dm[t][4 * u + j] : dp[t][4 * u + j],
-                                                                      acc[p], 0, 0, 0);
+                        for (int j = 0; j < 4; ++j)
+                            acc[p] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                                a4[j], p ? dm[t][4 * u + j] : dp[t][4 * u + j], acc[p], 0, 0, 0);
+                    }
                 }
-            }
+            };
+            if (slot == 0)
+                mma(acc2[0]);
+            else
+                mma(acc2[1]);
         }
+        if (slot == 0 && kb + 1 < nb) continue;  // the pair's second block comes first
         // lane l holds rows (k) 4 (l / 16) + r of column l % 16
 #pragma unroll
-        for (int p = 0; p < 2; ++p)
+        for (int b = 0; b < 2; ++b)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) red[kb & 1][w][p][4 * kq + r][c16] = acc[p][r];
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) red[buf][b][w][p][4 * kq + r][c16] = acc2[b][p][r];
         __syncthreads();
-        if (threadIdx.x < 2 * kMxHalf * kAnaMxMaps) {
-            const int p = threadIdx.x / (kMxHalf * kAnaMxMaps);
+        {
+            const int b = threadIdx.x / (2 * kMxHalf * kAnaMxMaps);
+            const int p = (threadIdx.x / (kMxHalf * kAnaMxMaps)) % 2;
             const int k = (threadIdx.x / kAnaMxMaps) % kMxHalf, mm = threadIdx.x % kAnaMxMaps;
-            const int l = l0 + 2 * k + p, map = cg * kAnaMxMaps + mm;
-            if (l <= lmax && map < nmaps) {
+            const int l = m + kMxL * (kb - slot + b) + 2 * k + p, map = cg * kAnaMxMaps + mm;
+            if (b <= slot && l <= lmax && map < nmaps) {
                 double sr = 0.0, si = 0.0;
 #pragma unroll
                 for (int v = 0; v < kAnaMxWaves; ++v) {
-                    sr += red[kb & 1][v][p][k][2 * mm];
-                    si += red[kb & 1][v][p][k][2 * mm + 1];
+                    sr += red[buf][b][v][p][k][2 * mm];
+                    si += red[buf][b][v][p][k][2 * mm + 1];
                 }
                 if (groups == 1) {
                     const double c = cfac[base + l];
@@ -427,6 +443,9 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
                 }
             }
         }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc2[b][0] = acc2[b][1] = floatx4{0.f, 0.f, 0.f, 0.f};
+        buf ^= 1;  // the next pair writes the other buffer while this one may still be read
     }
 }
 
