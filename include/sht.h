@@ -73,7 +73,9 @@ enum sht_status {
     SHT_EWORKSPACE = -2,    /* workspace NULL or smaller than required */
     SHT_EDEVICE = -3,       /* a HIP runtime call failed (see sht_strerror) */
     SHT_ENOMEM = -4,        /* device or host allocation for plan tables failed */
-    SHT_EUNSUPPORTED = -5   /* unknown flag bit, or a size beyond the kernels' limits */
+    SHT_EUNSUPPORTED = -5   /* unknown flag bit, or a size beyond the kernels' limits
+                               (a ring of more than 8192 pixels, mmax >= 65535,
+                               nmaps > 65535, grids beyond 2^31 workgroups) */
 };
 
 /* Flag bits of the `flags` arguments. */
@@ -88,10 +90,11 @@ enum sht_flags {
      * map and real/imaginary part) run on the FP32 matrix cores: synthesis
      * sums over l in FP32 (above lmax 2048 in two chains, the lower and the
      * upper half of the l range, added in FP64); analysis sums 32 l at a time
-     * over up to 256 ring pairs in FP32 and adds those sums in FP64.  The Delta and FFT stages stay
-     * FP64.  Expected relative RMS error against the FP64 transform: about
-     * 1e-7 to 1e-6.  Built for batches: a wave covers 8 to 32 maps in
-     * synthesis and 8 in analysis, so nmaps >= 8 fills it.  sht_alm2map with
+     * over up to 256 ring pairs in FP32 and adds those sums in FP64.  The
+     * Delta and FFT stages stay FP64.  Expected relative RMS error against
+     * the FP64 transform: about 1e-7 to 1e-6.  Built for batches: a wave
+     * covers 8 to 32 maps in synthesis (8 above lmax 2048) and 8 in analysis,
+     * so nmaps >= 8 fills it.  sht_alm2map with
      * this flag keeps its workspace Delta map-minor (as SHT_DELTA_MAP_MINOR
      * below); sht_map2alm keeps it ring-major. */
     SHT_MIXED = 1u,
