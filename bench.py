@@ -225,6 +225,62 @@ def batched_mixed(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a
     }
 
 
+def serving(sht, si, nreq: int, slots: int, budget_gb: float, loads=(0.5, 0.8)) -> dict:
+    """Serving leg: nreq requests of the HEALPix serving mix (lmax log-uniform
+    in [64, 4096], nside = lmax/2, alm2map or map2alm with equal odds, one map
+    each) through the continuous-batching server.  Plans of every grid are
+    built before the timed runs; inputs are resident on the device (map2alm
+    takes the FP64 alm2map of its power-law a_lm).  Per precision mode: first
+    every request at t = 0 (the saturation rate), then Poisson arrivals at
+    fractions of that rate.  Latency is arrival to completion event."""
+    import numpy as np
+    import torch
+    from paper_1106_0159_amd import serve
+
+    lm, kinds, t_unit = si.serving_trace(nreq, si.config_seed(5))
+    grids = {L: sht.GeomHandle(si.healpix(L // 2)) for L in sorted(set(lm.tolist()))}
+    serve.Server.reserve_plans(len(grids) + 8)
+    t0 = time.perf_counter()
+    for L, gh in grids.items():
+        sht.prepare(gh, L)
+    prep_s = time.perf_counter() - t0
+    print(f"[serve] {len(grids)} grids prepared in {prep_s:.1f} s, plan cache {sht.plan_cache_bytes() / 1e9:.2f} GB",
+          file=sys.stderr, flush=True)
+    inputs = []
+    for i, (L, k) in enumerate(zip(lm.tolist(), kinds.tolist())):
+        a = torch.from_numpy(si.powerlaw_alm(L, L, si.config_seed(5, i))).cuda()
+        inputs.append(a if k == "alm2map" else sht.alm2map(a, grids[L], L))
+    torch.cuda.synchronize()
+    print(f"[serve] {nreq} request inputs resident", file=sys.stderr, flush=True)
+    budget = int(budget_gb * (1 << 30))
+    out = {"requests": nreq, "distinct_grids": len(grids), "slots": slots, "hbm_budget_bytes": budget,
+           "lmax_range": [int(lm.min()), int(lm.max())], "alm2map_share": float(np.mean(kinds == "alm2map")),
+           "prepare_s": prep_s, "plan_cache_bytes": sht.plan_cache_bytes()}
+
+    def run(flags, rate):
+        reqs = [serve.Request(k, L, grids[L], inputs[i], arrival=0.0 if rate is None else float(t_unit[i]) / rate)
+                for i, (L, k) in enumerate(zip(lm.tolist(), kinds.tolist()))]
+        srv = serve.Server(budget, slots, flags, keep_results=False)
+        srv.run_trace(reqs)
+        torch.cuda.synchronize()
+        st = srv.stats()
+        st["offered_per_s"] = None if rate is None else rate
+        return st
+
+    for mode, flags in (("fp64", 0), ("mixed", sht.SHT_MIXED)):
+        run(flags, None)  # warm-up pass
+        sat = run(flags, None)
+        rows = [sat]
+        rate_sat = sat["done"] / sat["span_s"]
+        for f in loads:
+            rows.append(run(flags, f * rate_sat))
+        out[mode] = rows
+        print(f"[serve] {mode}: saturation {sat['maps_per_s']:.0f} maps/s, "
+              + ", ".join(f"load {r['offered_per_s']:.0f}/s p50 {r['p50_ms']:.2f} p99 {r['p99_ms']:.2f} ms"
+                          for r in rows[1:]), file=sys.stderr, flush=True)
+    return out
+
+
 def copy_probe(nbytes: int) -> None:
     """A plain device copy of known size, for calibrating HBM byte counters."""
     import torch
@@ -247,6 +303,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=64,
                     help="maps in the batched mixed-precision alm2map leg (0: skip it)")
+    ap.add_argument("--serve", type=int, default=0,
+                    help="requests in the serving leg (mixed lmax in [64, 4096]; 0: skip it)")
+    ap.add_argument("--serve-slots", type=int, default=4, help="concurrent requests (HIP streams) in the serving leg")
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="HBM budget of the serving leg")
+    ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
     ap.add_argument("--copy-probe", type=int, default=0, help="run only a device copy of this many bytes")
     ap.add_argument("--peak-probe", action="store_true",
                     help="run only the throughput probes (FP64 FMA, FP32 and BF16 matrix instructions)")
@@ -272,6 +333,12 @@ def main():
 
     import paper_1106_0159_amd as sht
     import sht_inputs as si
+
+    if args.serve_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"serving": serving(sht, si, max(1, args.serve), args.serve_slots, args.serve_budget_gb)}),
+              flush=True)
+        return
 
     nside = args.nside
     lmax = args.lmax if args.lmax is not None else 2 * nside
@@ -369,6 +436,8 @@ def main():
     if args.batch > 0:
         rec["batched_mixed"] = batched_mixed(sht, si, gh, g, lmax, args.batch, max(3, K // 4), args.warmup,
                                              nslots, mp, a_out)
+    if args.serve > 0:
+        rec["serving"] = serving(sht, si, args.serve, args.serve_slots, args.serve_budget_gb)
     if not args.no_cpu_baseline:
         mp_np = mp.cpu().numpy()
         rec["cpu_baseline"] = cpu_baseline(g, lmax, a_np, mp_np)

@@ -155,6 +155,38 @@ int sht_map2delta(int mmax, const sht_geom *g, const double *map, void *delta, i
 int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void *alm,
                   int nmaps, void *workspace, size_t ws_bytes, uint32_t flags, void *stream);
 
+/* ---- plan residency, for callers that serve requests of many sizes ----
+ *
+ * The plan tables of a (lmax, mmax, geometry) are what the paper's memory
+ * model (Sec. 4.1.2) counts beside the maps and a_lm: per-ring geometry and
+ * FFT plans (proportional to R_N and the ring lengths), recurrence
+ * coefficients (2 lmax mmax terms) and the start table (mmax x ring pairs).
+ * A server that keeps them resident on the device pays for them once, not
+ * per request. */
+
+/* Builds every table that a transform of this (lmax, mmax, geometry) needs
+ * and keeps it in the plan cache, so that later calls find it resident.  The
+ * start table is built by a kernel on `stream`; the call returns after it has
+ * completed.  Validation as for sht_alm2map (weights may be NULL; a geometry
+ * with weights and one without are distinct cache keys, so a caller that
+ * runs both directions passes the weights to both).  `flags` is validated
+ * only: both precision modes use the same tables.  Returns SHT_OK,
+ * SHT_EINVAL, SHT_EUNSUPPORTED, SHT_ENOMEM or SHT_EDEVICE. */
+int sht_prepare(int lmax, int mmax, const sht_geom *g, uint32_t flags, void *stream);
+
+/* Sets how many coefficient tables (one per (device, lmax, mmax)) and how
+ * many geometry plans (one per (device, geometry), each holding up to four
+ * start tables) the cache keeps before it evicts the least recently used
+ * (defaults 8 and 32).  Lowering a limit evicts at once.  An evicted table is
+ * freed when the last call holding it has returned, after a device
+ * synchronisation, so that kernels in flight never lose it.  Returns SHT_OK,
+ * or SHT_EINVAL if either limit is below 1. */
+int sht_plan_cache_limits(int max_coef_tables, int max_geom_plans);
+
+/* Device bytes held by the plan cache over all devices (coefficient tables,
+ * geometry and FFT plans, start tables). */
+size_t sht_plan_cache_bytes(void);
+
 /* Static description of a status code.  For SHT_EDEVICE the text of the
  * last HIP error seen by the calling thread is returned instead. */
 const char *sht_strerror(int code);

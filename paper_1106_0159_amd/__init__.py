@@ -24,6 +24,7 @@ SHT_DELTA_MAP_MINOR = 2  # flag: stage-call Delta laid out [nrings][mmax+1][nmap
 
 EXPORTS = ("sht_workspace_bytes", "sht_alm2map", "sht_map2alm", "sht_alm2delta", "sht_delta2map",
            "sht_map2delta", "sht_delta2alm", "sht_strerror", "sht_shutdown",
+           "sht_prepare", "sht_plan_cache_limits", "sht_plan_cache_bytes",
            "sht_probe_flops", "sht_probe_run")
 
 
@@ -67,6 +68,12 @@ def lib() -> ctypes.CDLL:
         L.sht_strerror.argtypes = [I]
         L.sht_shutdown.restype = None
         L.sht_shutdown.argtypes = []
+        L.sht_prepare.restype = I
+        L.sht_prepare.argtypes = [I, I, GP, U, P]
+        L.sht_plan_cache_limits.restype = I
+        L.sht_plan_cache_limits.argtypes = [I, I]
+        L.sht_plan_cache_bytes.restype = S
+        L.sht_plan_cache_bytes.argtypes = []
         L.sht_probe_flops.restype = ctypes.c_double
         L.sht_probe_flops.argtypes = [I, I, I]
         L.sht_probe_run.restype = I
@@ -235,6 +242,21 @@ def delta2alm(delta, geom, lmax: int, mmax: int | None = None, out=None, ws=None
                              ws.numel() * ws.element_size(), flags, _stream_ptr(stream))
     _check(rc, "sht_delta2alm")
     return out
+
+
+def prepare(geom, lmax: int, mmax: int | None = None, stream=None, flags: int = 0) -> None:
+    """Build and keep resident the plan tables of (lmax, mmax, geom); returns
+    once the start table's kernel has completed."""
+    mmax = lmax if mmax is None else mmax
+    _check(lib().sht_prepare(lmax, mmax, _gh(geom).ref(), flags, _stream_ptr(stream)), "sht_prepare")
+
+
+def plan_cache_limits(max_coef_tables: int, max_geom_plans: int) -> None:
+    _check(lib().sht_plan_cache_limits(max_coef_tables, max_geom_plans), "sht_plan_cache_limits")
+
+
+def plan_cache_bytes() -> int:
+    return int(lib().sht_plan_cache_bytes())
 
 
 PROBE_KINDS = {"fp64_fma": 0, "fp32_mfma_16x16x4": 1, "bf16_mfma_16x16x32": 2}  # include/sht_probe.h

@@ -7,6 +7,8 @@
 namespace sht {
 const char *last_hip_error();
 void shutdown_all();
+int set_cache_limits(int max_coef, int max_geom);
+size_t plan_cache_bytes();
 }  // namespace sht
 
 using namespace sht;
@@ -214,6 +216,25 @@ int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *
     if (flags & SHT_MIXED) return launch_leg_ana_mx(*c, *p, *s, delta, dl, alm, nmaps, partials, st);
     return launch_leg_ana(*c, *p, *s, delta, alm, nmaps, partials, st);
 }
+
+int sht_prepare(int lmax, int mmax, const sht_geom *g, uint32_t flags, void *stream) {
+    HostGeom h;
+    int rc = check_common(lmax, mmax, g, 1, flags, false, &h);
+    if (rc) return rc;
+    CoefRef c;
+    GeomRef p;
+    StartRef s;
+    if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p)) ||
+        (rc = get_start(*c, p, as_stream(stream), &s)))
+        return rc;
+    return SHT_OK;
+}
+
+int sht_plan_cache_limits(int max_coef_tables, int max_geom_plans) {
+    return set_cache_limits(max_coef_tables, max_geom_plans);
+}
+
+size_t sht_plan_cache_bytes(void) { return plan_cache_bytes(); }
 
 const char *sht_strerror(int code) {
     switch (code) {

@@ -7,6 +7,7 @@
 #include <map>
 #include <memory>
 #include <mutex>
+#include <unordered_map>
 #include <tuple>
 
 #include "sht_internal.h"
@@ -76,14 +77,45 @@ int validate_geom(const sht_geom *g, bool need_weight, HostGeom *out) {
 }
 
 // ------------------------------------------------------------------ device memory helpers
+// Every plan-table allocation goes through dev_alloc / dev_free, which keep
+// the bytes the caches hold on the devices (sht_plan_cache_bytes).
+static std::mutex g_bytes_mu;
+static auto &g_sizes = *new std::unordered_map<void *, size_t>();
+static size_t g_plan_bytes = 0;
+
+static bool dev_alloc(void **p, size_t bytes) {
+    if (hipMalloc(p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    std::lock_guard<std::mutex> lk(g_bytes_mu);
+    g_sizes[*p] = bytes;
+    g_plan_bytes += bytes;
+    return true;
+}
+
+static void dev_free(void *p) {
+    {
+        std::lock_guard<std::mutex> lk(g_bytes_mu);
+        auto it = g_sizes.find(p);
+        if (it != g_sizes.end()) {
+            g_plan_bytes -= it->second;
+            g_sizes.erase(it);
+        }
+    }
+    (void)hipFree(p);
+}
+
+size_t plan_cache_bytes() {
+    std::lock_guard<std::mutex> lk(g_bytes_mu);
+    return g_plan_bytes;
+}
+
 template <class T>
 static int upload(const std::vector<T> &v, T **dst, std::vector<void *> &owned) {
     void *p = nullptr;
     const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
-    if (hipMalloc(&p, bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return SHT_ENOMEM;
-    }
+    if (!dev_alloc(&p, bytes)) return SHT_ENOMEM;
     owned.push_back(p);
     if (!v.empty()) SHT_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
     *dst = static_cast<T *>(p);
@@ -103,7 +135,7 @@ static void release_device(int dev, std::vector<void *> &ptrs) {
     (void)hipGetDevice(&cur);
     if (dev >= 0 && cur != dev) (void)hipSetDevice(dev);
     (void)hipDeviceSynchronize();
-    for (void *q : ptrs) (void)hipFree(q);
+    for (void *q : ptrs) dev_free(q);
     ptrs.clear();
     if (dev >= 0 && cur >= 0 && cur != dev) (void)hipSetDevice(cur);
 }
@@ -159,7 +191,9 @@ struct CoefEntry {
 static std::mutex g_mu;
 static uint64_t g_clock = 0;
 static auto &g_coef = *new std::map<std::tuple<int, int, int>, CoefEntry>();
-constexpr size_t kMaxCoefTables = 8;
+// cache capacities (entries per process); sht_plan_cache_limits changes them
+static size_t g_max_coef = 8;
+static size_t g_max_geom = 32;
 
 int get_coef(int lmax, int mmax, CoefRef *out) {
     int dev = 0;
@@ -173,7 +207,7 @@ int get_coef(int lmax, int mmax, CoefRef *out) {
         *out = it->second.t;
         return SHT_OK;
     }
-    if (g_coef.size() >= kMaxCoefTables) {
+    while (g_coef.size() >= g_max_coef) {
         auto lru = std::min_element(g_coef.begin(), g_coef.end(), [](const auto &a, const auto &b) {
             return a.second.last_use < b.second.last_use;
         });
@@ -359,7 +393,6 @@ struct GeomEntry {
     uint64_t last_use;
 };
 static auto &g_geom = *new std::vector<GeomEntry>();
-constexpr size_t kMaxGeomPlans = 32;
 
 static bool same_geom(const HostGeom &a, const HostGeom &b) {
     return a.nrings == b.nrings && a.has_weight == b.has_weight && a.theta == b.theta &&
@@ -425,7 +458,7 @@ int count_slots(const HostGeom &h) {
     build_slots(h, sx, ss, sn, sso);
     const int n = (int)sx.size();
     std::lock_guard<std::mutex> lk(mu);
-    if (memo.size() >= 8) memo.erase(memo.begin());
+    if (memo.size() >= 256) memo.erase(memo.begin());
     memo.emplace_back(h.theta, n);
     return n;
 }
@@ -442,7 +475,7 @@ int get_geom(const HostGeom &hg, int /*mmax_for_fft*/, GeomRef *out) {
             return SHT_OK;
         }
     }
-    if (g_geom.size() >= kMaxGeomPlans) {
+    while (g_geom.size() >= g_max_geom) {
         // drop the least recently used plan; it is freed when its last user is done
         auto lru = std::min_element(g_geom.begin(), g_geom.end(),
                                     [](const GeomEntry &a, const GeomEntry &b) { return a.last_use < b.last_use; });
@@ -549,9 +582,9 @@ int get_start(const CoefTables &c, const GeomRef &pref, hipStream_t st, StartRef
     t->mmax = c.mmax;
     const size_t n = (size_t)(c.mmax + 1) * (size_t)p.nslots;
     void *a = nullptr, *b = nullptr;
-    if (hipMalloc(&a, n * sizeof(int32_t)) != hipSuccess) return SHT_ENOMEM;
+    if (!dev_alloc(&a, n * sizeof(int32_t))) return SHT_ENOMEM;
     t->lstart = static_cast<int32_t *>(a);
-    if (hipMalloc(&b, n * sizeof(double2)) != hipSuccess) return SHT_ENOMEM;  // t frees lstart
+    if (!dev_alloc(&b, n * sizeof(double2))) return SHT_ENOMEM;  // t frees lstart
     t->state = static_cast<double2 *>(b);
     int rc = launch_leg_start(c, p, t->lstart, t->state, st);
     if (rc == SHT_OK && hipStreamSynchronize(st) != hipSuccess) rc = SHT_EDEVICE;
@@ -614,13 +647,31 @@ int fork_join(hipStream_t st, int n, const std::function<int(int, hipStream_t)> 
     return rc;
 }
 
+int set_cache_limits(int max_coef, int max_geom) {
+    if (max_coef < 1 || max_geom < 1) return SHT_EINVAL;
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_max_coef = (size_t)max_coef;
+    g_max_geom = (size_t)max_geom;
+    // entries beyond the new limits go now, least recently used first; each is
+    // freed when its last user is done
+    while (g_coef.size() > g_max_coef)
+        g_coef.erase(std::min_element(g_coef.begin(), g_coef.end(), [](const auto &a, const auto &b) {
+            return a.second.last_use < b.second.last_use;
+        }));
+    while (g_geom.size() > g_max_geom)
+        g_geom.erase(std::min_element(g_geom.begin(), g_geom.end(), [](const GeomEntry &a, const GeomEntry &b) {
+            return a.last_use < b.last_use;
+        }));
+    return SHT_OK;
+}
+
 void shutdown_all() {
     std::lock_guard<std::mutex> lk(g_mu);
     (void)hipDeviceSynchronize();
     g_geom.clear();  // plans and their start tables free themselves
     g_coef.clear();
     for (auto &kv : g_fft)
-        for (void *p : kv.second->owned) (void)hipFree(p);
+        for (void *p : kv.second->owned) dev_free(p);
     g_fft.clear();
     std::lock_guard<std::mutex> lk2(g_side_mu);
     for (auto &kv : g_side) free_side(*kv.second);

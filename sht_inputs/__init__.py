@@ -26,7 +26,7 @@ import numpy as np
 
 __all__ = [
     "Geometry", "gauss_legendre", "healpix", "nalm", "alm_index",
-    "powerlaw_alm", "uniform_alm", "random_map", "config_seed", "subset_geometry",
+    "powerlaw_alm", "uniform_alm", "random_map", "config_seed", "subset_geometry", "serving_trace",
 ]
 
 
@@ -230,3 +230,17 @@ def uniform_alm(lmax: int, mmax: int, seed: int) -> np.ndarray:
 def random_map(g: Geometry, seed: int) -> np.ndarray:
     """A white-noise real map on geometry g (for adjointness and analysis tests)."""
     return np.random.default_rng(seed).standard_normal(g.npix)
+
+
+def serving_trace(n: int, seed: int, lmin: int = 64, lmax_hi: int = 4096):
+    """A serving workload of n requests: lmax = 2*round(exp(U[ln lmin, ln lmax_hi])/2)
+    (even, for a HEALPix grid with nside = lmax/2), each request alm2map or
+    map2alm with probability 1/2, and Poisson arrival times of unit rate
+    (divide by the offered rate), the first at t = 0.
+
+    Returns (lmax int64 [n], kinds str [n], arrival float64 [n])."""
+    rng = np.random.default_rng(seed)
+    lm = 2 * np.round(np.exp(rng.uniform(np.log(lmin), np.log(lmax_hi), n)) / 2).astype(np.int64)
+    kinds = np.where(rng.random(n) < 0.5, "alm2map", "map2alm")
+    gaps = rng.exponential(1.0, n)
+    return lm, kinds, np.cumsum(gaps) - gaps[0]
