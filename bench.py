@@ -303,7 +303,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=64,
                     help="maps in the batched mixed-precision alm2map leg (0: skip it)")
-    ap.add_argument("--serve", type=int, default=0,
+    ap.add_argument("--serve", type=int, default=256,
                     help="requests in the serving leg (mixed lmax in [64, 4096]; 0: skip it)")
     ap.add_argument("--serve-slots", type=int, default=4, help="concurrent requests (HIP streams) in the serving leg")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="HBM budget of the serving leg")
