@@ -95,8 +95,9 @@ enum sht_flags {
      * the FP64 transform: about 1e-7 to 1e-6.  Built for batches: a wave
      * covers 8 to 32 maps in synthesis (8 above lmax 2048) and 8 in analysis,
      * so nmaps >= 8 fills it.  sht_alm2map with
-     * this flag keeps its workspace Delta map-minor (as SHT_DELTA_MAP_MINOR
-     * below); sht_map2alm keeps it ring-major. */
+     * this flag and nmaps >= 8 keeps its workspace Delta map-minor (as
+     * SHT_DELTA_MAP_MINOR below), ring-major with fewer maps; sht_map2alm
+     * keeps it ring-major. */
     SHT_MIXED = 1u,
     /* Layout of the `delta` argument of the stage calls: [nrings][mmax+1][nmaps]
      * (map index fastest) instead of [nmaps][nrings][mmax+1].  Accepted by

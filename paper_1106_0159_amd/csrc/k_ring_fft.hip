@@ -271,11 +271,15 @@ __device__ __forceinline__ void fft_stage(double2 *buf, int L, int Ns, TwLds tw)
 // y_s of butterfly j is sum_q x_q W^{q (k tstep + s L/R)} with x_q the q-th
 // input of the butterfly, i.e. the twiddles and the R-point DFT of the
 // fixed-radix stages taken together.  Each thread computes up to kMaxOut
-// outputs directly (R terms each, exponents reduced exactly as integers),
-// then writes them back after the barrier.
+// outputs directly (R terms each), then writes them back after the barrier.
+// The twiddle of term q is carried in registers (w <- w W^step) and taken
+// afresh from the table, at an exponent reduced exactly as an integer, every
+// kAnchor terms: one LDS read per term instead of three, and a recurrence
+// error of at most kAnchor roundings.
 template <int MAXL, int NT>
 __device__ __forceinline__ void fft_stage_generic(double2 *buf, int L, int Ns, int R, TwLds tw) {
     constexpr int kMaxOut = (MAXL + NT - 1) / NT;
+    constexpr int kAnchor = 16;
     const int nbf = L / R;
     const int tstep = L / (Ns * R);
     double2 y[kMaxOut];
@@ -288,13 +292,20 @@ __device__ __forceinline__ void fft_stage_generic(double2 *buf, int L, int Ns, i
             const int sidx = t % R, jq = t / R;
             const int j = jq * Ns + k;
             const int step = (k * tstep + sidx * nbf) % L;
+            const int jump = (kAnchor * step) % L;  // kAnchor * step < 16 * 8192
+            const double2 ws = tw(step);
             double yr = 0.0, yi = 0.0;
-            int e = 0;
-            for (int q = 0; q < R; ++q) {
-                const double2 v = cmul(buf[pd(j + q * nbf)], tw(e));
-                yr += v.x;
-                yi += v.y;
-                e += step;
+            int e = 0;  // q0 * step mod L
+            for (int q0 = 0; q0 < R; q0 += kAnchor) {
+                double2 w = tw(e);
+                const int qe = min(R, q0 + kAnchor);
+                for (int q = q0; q < qe; ++q) {
+                    const double2 x = buf[pd(j + q * nbf)];
+                    yr = fma(x.x, w.x, fma(-x.y, w.y, yr));
+                    yi = fma(x.x, w.y, fma(x.y, w.x, yi));
+                    w = cmul(w, ws);
+                }
+                e += jump;
                 if (e >= L) e -= L;
             }
             y[i] = make_double2(yr, yi);

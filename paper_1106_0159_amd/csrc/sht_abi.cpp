@@ -175,10 +175,12 @@ int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *
         return rc;
     char *ws = static_cast<char *>(workspace);
     void *delta = ws, *aprime = ws + round256(db);
-    // mixed precision keeps the workspace Delta map-minor: the matrix-core
-    // kernel then stores whole 128-byte lines per (ring, m), which saves more
-    // than the ring FFT loses on its strided reads
-    const DeltaLayout dl = delta_layout(h.nrings, mmax, nmaps, (flags & SHT_MIXED) != 0);
+    // mixed precision keeps the workspace Delta map-minor from 8 maps on: the
+    // matrix-core kernel then stores whole 128-byte lines per (ring, m), which
+    // saves more than the ring FFT loses on its strided reads.  With fewer
+    // maps there are no whole lines to gain, and the ring-major FFT transforms
+    // a mirror pair per workgroup instead of one ring.
+    const DeltaLayout dl = delta_layout(h.nrings, mmax, nmaps, (flags & SHT_MIXED) != 0 && nmaps >= 8);
     if (flags & SHT_MIXED) {
         if ((rc = launch_leg_syn_mx(*c, *p, *s, alm, aprime, delta, dl, nmaps, st))) return rc;
     } else {
