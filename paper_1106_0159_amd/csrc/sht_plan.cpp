@@ -336,8 +336,9 @@ static int fft_desc(FftCache &fc, int n, FftDesc *out) {
     int rc;
     // Direct transform of length n when it is 5-smooth, or when its direct
     // R-term stages (about 12 R flops per point each) cost less than
-    // Bluestein's two transforms of length L >= 2n - 1 (taken as 200 flops
-    // per point of L), or when Bluestein's L would not fit the largest class.
+    // Bluestein's two transforms of length L >= 2n - 1 (taken as 400 flops
+    // per point of L: of 200, 400 and 800, the weight that timed best here),
+    // or when Bluestein's L would not fit the largest class.
     int Lb = 2 * n - 1;
     while (!smooth5(Lb)) ++Lb;
     std::vector<int> all;
@@ -347,7 +348,7 @@ static int fft_desc(FftCache &fc, int n, FftDesc *out) {
     if (factor_small(n, rad)) {
         d.L = n;
         d.bluestein = 0;
-    } else if (all_ok && (Lb > kMaxFftLen || direct <= 200.0 * Lb)) {
+    } else if (all_ok && (Lb > kMaxFftLen || direct <= 400.0 * Lb)) {
         rad = all;
         d.L = n;
         d.bluestein = 0;
