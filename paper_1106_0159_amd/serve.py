@@ -62,6 +62,9 @@ class Request:
 
     @property
     def latency(self) -> float:
+        """Arrival to completion, seconds (the completion event is placed on
+        the host clock to within the few tens of microseconds of one
+        synchronisation)."""
         return self.t_done - self.arrival
 
 
@@ -176,7 +179,9 @@ class Server:
                 f = alm2map if req.kind == "alm2map" else map2alm
                 req.result = f(req.data, req.geom, req.lmax, req.mmax, ws=ws, stream=s, flags=self.flags)
                 ev.record(s)
-        except ShtError as e:  # rejected by the library's host-side checks: nothing was enqueued
+        except RuntimeError as e:
+            # a library rejection (ShtError: nothing was enqueued) or a failed
+            # allocation: the request fails, its slot and bytes go back
             req.status, req.error = "failed", str(e)
             self.adm.release(slot, req.need)
             self.finished.append(req)
@@ -226,11 +231,13 @@ class Server:
     def stats(self) -> dict:
         done = [r for r in self.finished if r.status == "done"]
         lat = np.array([r.latency for r in done]) * 1e3
+        rejected = sum(r.status == "rejected" for r in self.finished)
+        failed = sum(r.status == "failed" for r in self.finished)
         if not done:
-            return {"done": 0, "rejected": len(self.finished)}
+            return {"done": 0, "rejected": rejected, "failed": failed}
         span = max(r.t_done for r in done) - min(r.arrival for r in done)
         maps = sum(r.nmaps for r in done)
-        return {"done": len(done), "rejected": sum(r.status == "rejected" for r in self.finished),
+        return {"done": len(done), "rejected": rejected, "failed": failed,
                 "maps_per_s": maps / span, "span_s": span,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
                 "max_ms": float(lat.max()), "max_running": self.adm.max_running,
