@@ -281,6 +281,56 @@ def serving(sht, si, nreq: int, slots: int, budget_gb: float, loads=(0.5, 0.8)) 
     return out
 
 
+def small_latency(sht, si, calls: int = 200) -> dict:
+    """The launch-bound case: alm2map alone, FP64, lmax = mmax = 256 on a
+    Gauss-Legendre grid of 257 rings x 513 points, one map.  Per-call time of
+    `calls` back-to-back calls, eager and replayed from a HIP graph that
+    captured one call (the plan is resident, so the call only launches)."""
+    import torch
+    lmax = 256
+    g = sht.GeomHandle(si.gauss_legendre(lmax + 1, 2 * lmax + 1))
+    a = torch.from_numpy(si.powerlaw_alm(lmax, lmax, si.config_seed(1))).cuda()
+    out = torch.zeros(g.npix, dtype=torch.float64, device="cuda")
+    ws = sht.workspace(lmax, lmax, g, 1, "cuda")
+    sht.prepare(g, lmax)
+    for _ in range(10):
+        sht.alm2map(a, g, lmax, out=out, ws=ws)
+    torch.cuda.synchronize()
+    ref = out.clone()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e0.record()
+        for _ in range(calls):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / calls, (time.perf_counter() - t0) * 1e6 / calls
+
+    eager_us, eager_host_us = timed(lambda: sht.alm2map(a, g, lmax, out=out, ws=ws))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        sht.alm2map(a, g, lmax, out=out, ws=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        sht.alm2map(a, g, lmax, out=out, ws=ws)
+    out.zero_()
+    graph.replay()
+    torch.cuda.synchronize()
+    if not torch.equal(out, ref):
+        raise RuntimeError("graph replay differs from the eager call")
+    graph_us, graph_host_us = timed(graph.replay)
+    return {"workload": "FP64 alm2map, Gauss-Legendre 257 x 513, lmax=mmax=256, 1 map", "calls": calls,
+            "eager_us_per_map": eager_us, "graph_us_per_map": graph_us,
+            "eager_host_us_per_call": eager_host_us, "graph_host_us_per_call": graph_host_us}
+
+
 def copy_probe(nbytes: int) -> None:
     """A plain device copy of known size, for calibrating HBM byte counters."""
     import torch
@@ -436,6 +486,9 @@ def main():
     if args.batch > 0:
         rec["batched_mixed"] = batched_mixed(sht, si, gh, g, lmax, args.batch, max(3, K // 4), args.warmup,
                                              nslots, mp, a_out)
+    rec["small_latency"] = small_latency(sht, si)
+    print(f"[small] eager {rec['small_latency']['eager_us_per_map']:.1f} us/map, "
+          f"graph {rec['small_latency']['graph_us_per_map']:.1f} us/map", file=sys.stderr, flush=True)
     if args.serve > 0:
         rec["serving"] = serving(sht, si, args.serve, args.serve_slots, args.serve_budget_gb)
     if not args.no_cpu_baseline:
