@@ -358,6 +358,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4, help="concurrent requests (HIP streams) in the serving leg")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="HBM budget of the serving leg")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
+    ap.add_argument("--no-small-latency", action="store_true",
+                    help="skip the launch-bound lmax=256 latency leg (e.g. to profile the main step alone)")
     ap.add_argument("--copy-probe", type=int, default=0, help="run only a device copy of this many bytes")
     ap.add_argument("--peak-probe", action="store_true",
                     help="run only the throughput probes (FP64 FMA, FP32 and BF16 matrix instructions)")
@@ -486,9 +488,10 @@ def main():
     if args.batch > 0:
         rec["batched_mixed"] = batched_mixed(sht, si, gh, g, lmax, args.batch, max(3, K // 4), args.warmup,
                                              nslots, mp, a_out)
-    rec["small_latency"] = small_latency(sht, si)
-    print(f"[small] eager {rec['small_latency']['eager_us_per_map']:.1f} us/map, "
-          f"graph {rec['small_latency']['graph_us_per_map']:.1f} us/map", file=sys.stderr, flush=True)
+    if not args.no_small_latency:
+        rec["small_latency"] = small_latency(sht, si)
+        print(f"[small] eager {rec['small_latency']['eager_us_per_map']:.1f} us/map, "
+              f"graph {rec['small_latency']['graph_us_per_map']:.1f} us/map", file=sys.stderr, flush=True)
     if args.serve > 0:
         rec["serving"] = serving(sht, si, args.serve, args.serve_slots, args.serve_budget_gb)
     if not args.no_cpu_baseline:
