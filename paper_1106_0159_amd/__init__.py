@@ -95,6 +95,9 @@ class GeomHandle:
         self.ofs = None if o is None else np.ascontiguousarray(o, dtype=np.int64)
         self.nrings = int(self.theta.shape[0])
         self.npix = int(np.max(self.ofs + self.nphi)) if self.ofs is not None else int(self.nphi.sum())
+        # rings never overlap (the library rejects that), so when their pixel
+        # counts add up to npix every pixel of a synthesised map is written
+        self.covers_all = int(self.nphi.sum()) == self.npix
         ptr = lambda a: None if a is None else a.ctypes.data
         self.c = _Geom(self.nrings, ptr(self.theta), ptr(self.nphi), ptr(self.phi0), ptr(self.weight),
                        ptr(self.ofs))
@@ -155,7 +158,8 @@ def alm2map(alm, geom, lmax: int, mmax: int | None = None, out=None, ws=None, st
     na = nalm(lmax, mmax)
     nm = _nmaps_of(alm, na)
     if out is None:
-        out = torch.zeros(alm.shape[:-1] + (g.npix,), dtype=torch.float64, device=alm.device)
+        alloc = torch.empty if g.covers_all else torch.zeros
+        out = alloc(alm.shape[:-1] + (g.npix,), dtype=torch.float64, device=alm.device)
     if ws is None:
         ws = workspace(lmax, mmax, g, nm, alm.device, flags)
     rc = lib().sht_alm2map(lmax, mmax, g.ref(), alm.data_ptr(), out.data_ptr(), nm, ws.data_ptr(),
@@ -206,7 +210,8 @@ def delta2map(delta, geom, mmax: int, out=None, stream=None, flags: int = 0):
     nm = _nmaps_of(delta, g.nrings * (mmax + 1))
     if out is None:
         shape = (nm, g.npix) if flags & SHT_DELTA_MAP_MINOR else delta.shape[:-2] + (g.npix,)
-        out = torch.zeros(shape, dtype=torch.float64, device=delta.device)
+        alloc = torch.empty if g.covers_all else torch.zeros
+        out = alloc(shape, dtype=torch.float64, device=delta.device)
     rc = lib().sht_delta2map(mmax, g.ref(), delta.data_ptr(), out.data_ptr(), nm, flags, _stream_ptr(stream))
     _check(rc, "sht_delta2map")
     return out
