@@ -8,7 +8,9 @@ different lmax runs through the server.  It is checked that:
 - admission keeps the bytes in flight within the HBM budget while several
   requests overlap;
 - a request larger than the budget is rejected;
-- plans evicted while other requests are in flight do not change any result.
+- plans evicted while other requests are in flight do not change any result;
+- an uneven batch, each request on its own Gauss-Legendre grid, returns the
+  seed a_lm from map2alm of FP64 maps (exact quadrature).
 One request of each kind is also held to the oracle (relative RMS <= 1e-12
 in FP64, <= 1e-6 in mixed precision).
 """
@@ -180,3 +182,38 @@ def test_prepare_keeps_plans_resident(env):
         assert sht.plan_cache_bytes() == held
     finally:
         sht.plan_cache_limits(8, 32)
+
+
+@pytest.mark.parametrize("flags", [0, 1], ids=["fp64", "mixed"])
+def test_uneven_gauss_legendre_batch(env, flags):
+    """The uneven batch: each request on its own Gauss-Legendre grid of
+    (lmax+1) x (2 lmax+1) points, lmax log-uniform, alm2map or map2alm with
+    equal odds.  The map2alm inputs are FP64 alm2map outputs of seeded a_lm,
+    and Gauss-Legendre quadrature is exact at this band limit, so every
+    map2alm result is the seed a_lm (to 1e-12 in FP64, 1e-6 mixed); every
+    alm2map result matches the FP64 transform (bitwise in FP64, 1e-6 mixed)."""
+    import torch
+    sht, serve, grids, inputs = env
+    rng = np.random.default_rng(si.config_seed(4))
+    n = 12
+    lms = np.round(np.exp(rng.uniform(np.log(16), np.log(96), n))).astype(int)
+    kinds = np.where(rng.random(n) < 0.5, "alm2map", "map2alm")
+    say(f"uneven GL batch flags={flags}: lmax {lms.tolist()}")
+    reqs, want = [], []
+    for i, (L, k) in enumerate(zip(lms.tolist(), kinds.tolist())):
+        gh = sht.GeomHandle(si.gauss_legendre(L + 1, 2 * L + 1))
+        a = torch.from_numpy(si.powerlaw_alm(L, L, si.config_seed(4, i))).cuda()
+        m64 = sht.alm2map(a, gh, L)
+        reqs.append(serve.Request(k, L, gh, a if k == "alm2map" else m64))
+        want.append(m64 if k == "alm2map" else a)
+    srv = serve.Server(64 << 30, 4, flags)
+    for r in reqs:
+        srv.submit(r)
+    srv.drain()
+    torch.cuda.synchronize()
+    for r, w in zip(reqs, want):
+        assert r.status == "done", r.error
+        got = r.result.reshape(w.shape)
+        err = ((got - w).norm() / w.norm()).item()
+        tol = (0.0 if r.kind == "alm2map" else 1e-12) if flags == 0 else 1e-6
+        assert err <= tol, (r.kind, r.lmax, err)
