@@ -5,9 +5,11 @@ One step = one map through both transforms, with inputs resident in HBM:
     map --(ring FFT analysis)--> Delta^S --(Legendre analysis)--> alm'
 called through the four stage entry points of the C ABI (their composition is
 exactly sht_alm2map followed by sht_map2alm), with HIP events on the launch
-stream between stages.  A second leg ("batched_mixed" in the output) runs
-the same two transforms on a batch of 64 maps with the mixed-precision
-Legendre contraction.
+stream between stages.  Further legs: "batched_mixed" and "batched_fp64" run
+the same two transforms on a batch of 64 maps (mixed-precision and FP64
+Legendre contraction); "config3" the batched Gauss-Legendre configuration
+(1025 x 2049, lmax 1024, 64 maps); "small_latency" the launch-bound lmax 256
+case; "serving" the continuous-batching server.
 Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--batch N] [--no-cpu-baseline]
@@ -72,15 +74,19 @@ def latency(times_ms) -> dict:
 
 
 def mirror_slots(theta) -> int:
-    """Number of ring slots (mirror pairs plus unpaired rings), as the library forms them."""
+    """Number of ring slots (mirror pairs plus unpaired rings), as the library
+    forms them: rings pair when |theta + theta' - pi| <= 2^-50 (two ulp of pi),
+    the sum taken exactly."""
+    import numpy as np
     th = sorted(float(t) for t in theta)
+    pi_l = np.longdouble("3.14159265358979323846264338327950288")
     i, j, n = 0, len(th) - 1, 0
     while i <= j:
         if i == j:
             n += 1
             break
-        d = th[i] + th[j] - math.pi
-        if abs(d) <= 1e-14:
+        d = float((np.longdouble(th[i]) + np.longdouble(th[j])) - pi_l)
+        if abs(d) <= 2.0 ** -50:
             i += 1
             j -= 1
         elif d < 0:
@@ -142,42 +148,43 @@ def cpu_baseline(g, lmax, a, mp, target_s: float = 12.0):
     }
 
 
-def batched_mixed(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a_fp64):
-    """One batch of power-law maps through both transforms with SHT_MIXED
-    (FP64 recurrence, FP32 matrix-core contraction; Delta and FFTs FP64,
-    Delta map-minor in synthesis), through the four stage entry points, HIP events on
-    the launch stream around each stage.  Map 0 of the batch is the map of the
-    plain FP64 step: the relative RMS differences of its map and of its
-    analysed a_lm to the FP64 results are reported."""
+def run_batch(sht, gh, g, lmax, alm, steps, warmup, flags):
+    """A batch of maps through both transforms (alm -> map -> alm'), through
+    the four stage entry points, HIP events on the launch stream around each
+    stage.  With SHT_MIXED, Delta is kept as sht_alm2map / sht_map2alm keep
+    it (the stage calls give the same bits as the combined ones): map-minor,
+    [nrings][mmax+1][nmaps], in synthesis from 8 maps on, ring-major in
+    analysis.  Returns (stage ms, per-batch ms list, wall ms per batch, map,
+    a_lm')."""
     import numpy as np
     import torch
-    dev = torch.device("cuda", 0)
-    alm = torch.empty((nmaps, si.nalm(lmax, lmax)), dtype=torch.complex128, device=dev)
-    for i in range(nmaps):
-        alm[i] = torch.from_numpy(si.powerlaw_alm(lmax, lmax, si.config_seed(2, i))).to(dev)
-    # Delta as sht_alm2map / sht_map2alm keep it with SHT_MIXED (the stage
-    # calls give the same bits as the combined ones): map-minor,
-    # [nrings][mmax+1][nmaps], in synthesis and ring-major in analysis
-    delta = torch.empty((g.nrings, lmax + 1, nmaps), dtype=torch.complex128, device=dev)
+    dev = alm.device
+    nmaps = alm.shape[0]
+    mixed = bool(flags & sht.SHT_MIXED)
+    mm = mixed and nmaps >= 8
+    MM = sht.SHT_DELTA_MAP_MINOR
+    if mm:
+        delta = torch.empty((g.nrings, lmax + 1, nmaps), dtype=torch.complex128, device=dev)
+    else:
+        delta = torch.empty((nmaps, g.nrings, lmax + 1), dtype=torch.complex128, device=dev)
     delta_s = torch.empty((nmaps, g.nrings, lmax + 1), dtype=torch.complex128, device=dev)
     mp = torch.zeros((nmaps, g.npix), dtype=torch.float64, device=dev)
     a_out = torch.empty_like(alm)
-    ws = sht.workspace(lmax, lmax, gh, nmaps, dev, sht.SHT_MIXED)
-    MM = sht.SHT_DELTA_MAP_MINOR
-    F = sht.SHT_MIXED | MM
+    ws = sht.workspace(lmax, lmax, gh, nmaps, dev, flags)
+    fs = flags | (MM if mm else 0)
 
     def step(ev=None):
         def mark(i):
             if ev is not None:
                 ev[i].record()
         mark(0)
-        sht.alm2delta(alm, gh, lmax, lmax, out=delta, ws=ws, flags=F)
+        sht.alm2delta(alm, gh, lmax, lmax, out=delta, ws=ws, flags=fs)
         mark(1)
-        sht.delta2map(delta, gh, lmax, out=mp, flags=MM)
+        sht.delta2map(delta, gh, lmax, out=mp, flags=MM if mm else 0)
         mark(2)
         sht.map2delta(mp, gh, lmax, out=delta_s)
         mark(3)
-        sht.delta2alm(delta_s, gh, lmax, lmax, out=a_out, ws=ws, flags=sht.SHT_MIXED)
+        sht.delta2alm(delta_s, gh, lmax, lmax, out=a_out, ws=ws, flags=flags)
         mark(4)
 
     for _ in range(warmup):
@@ -188,41 +195,144 @@ def batched_mixed(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a
     for k in range(steps):
         step(evs[k])
     torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    names = ["leg_syn_mx", "fft_syn", "fft_ana", "leg_ana_mx"]
+    wall_ms = (time.perf_counter() - t0) * 1000.0 / steps
+    names = ["leg_syn", "fft_syn", "fft_ana", "leg_ana"]
     st = {n: float(np.mean([e[i].elapsed_time(e[i + 1]) for e in evs])) for i, n in enumerate(names)}
-    batch_times = np.array([e[0].elapsed_time(e[4]) for e in evs])
-    ms = max(wall * 1000.0 / steps, sum(st.values()))
-    flops = 4 * nmaps * count_triples(nslots, lmax, lmax)  # matrix-core flops of one contraction
-    dom = max(("leg_syn_mx", "leg_ana_mx"), key=lambda n: st[n])
-    achieved = flops / (st[dom] * 1e-3) / 1e12
-    rel = lambda x, y: (x - y).norm().item() / y.norm().item()
+    batch_ms = [e[0].elapsed_time(e[4]) for e in evs]
+    del delta, delta_s, ws
+    return st, batch_ms, wall_ms, mp, a_out
+
+
+def batch_record(nmaps, st, batch_ms, wall_ms, steps, dtype, flops_per_launch, peak, bound, kernels):
+    """Throughput, stage times and the roofline of the slower Legendre stage."""
+    ms = max(wall_ms, sum(st.values()))
+    dom = max(("leg_syn", "leg_ana"), key=lambda n: st[n])
+    achieved = flops_per_launch / (st[dom] * 1e-3) / 1e12
     return {
-        "direction": "alm2map+map2alm",
         "nmaps": nmaps,
         "value": nmaps * 1000.0 / ms,
         "unit": "maps/s",
         "ms_per_batch": ms,
-        "latency_ms": latency(batch_times),
+        "latency_ms": latency(batch_ms),
         "steps": steps,
         "stages_ms": st,
-        "alm2map_maps_per_s": nmaps * 1000.0 / (st["leg_syn_mx"] + st["fft_syn"]),
-        "map2alm_maps_per_s": nmaps * 1000.0 / (st["fft_ana"] + st["leg_ana_mx"]),
-        "dtype": "f64 recurrence, f32 contraction",
-        "relrms_map0_vs_fp64": rel(mp[0], mp_fp64),
-        "relrms_alm0_vs_fp64": rel(a_out[0], a_fp64),
+        "alm2map_maps_per_s": nmaps * 1000.0 / (st["leg_syn"] + st["fft_syn"]),
+        "map2alm_maps_per_s": nmaps * 1000.0 / (st["fft_ana"] + st["leg_ana"]),
+        "dtype": dtype,
         "roofline": {
-            "kernel": {"leg_syn_mx": "k_prescale_mx + k_leg_syn_mx",
-                       "leg_ana_mx": "k_leg_ana_mx"}[dom],
-            "bound": "mfma",
+            "kernel": kernels[dom],
+            "bound": bound,
             "achieved": achieved,
-            "peak": PEAK_FP32_MFMA_TFLOPS,
+            "peak": peak,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32_MFMA_TFLOPS,
+            "frac": achieved / peak,
             "traffic": None,
-            "flops_per_launch": flops,
+            "flops_per_launch": flops_per_launch,
         },
     }
+
+
+def fft_roofline(g, mmax, nmaps, stages_ms) -> dict:
+    """Ring stages against the HBM roofline: algorithmic bytes per launch
+    set = Delta (16 B per ring and m <= mmax, read in synthesis, written in
+    analysis) plus the map (8 B per pixel, written / read), times the maps,
+    over the event-timed stage."""
+    nbytes = nmaps * (16 * g.nrings * (mmax + 1) + 8 * g.npix)
+    out = {"bytes_per_launch": nbytes, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    for key, st in (("syn", "fft_syn"), ("ana", "fft_ana")):
+        gbs = nbytes / (stages_ms[st] * 1e-3) / 1e9
+        out[key] = {"achieved": gbs, "frac": gbs / PEAK_HBM_GBS, "ms": stages_ms[st]}
+    return out
+
+
+def power_law_batch(si, lmax, nmaps, config):
+    import torch
+    alm = torch.empty((nmaps, si.nalm(lmax, lmax)), dtype=torch.complex128, device="cuda")
+    for i in range(nmaps):
+        alm[i] = torch.from_numpy(si.powerlaw_alm(lmax, lmax, si.config_seed(config, i))).cuda()
+    return alm
+
+
+MX_KERNELS = {"leg_syn": "k_prescale_mx + k_leg_syn_mx", "leg_ana": "k_leg_ana_mx"}
+F64_KERNELS = {"leg_syn": "k_prescale + k_leg_syn", "leg_ana": "k_leg_ana (+ k_ana_combine above 2048 slots)"}
+
+
+def rel_per_map(x, y):
+    """Relative RMS of x - y per map (rows), as a list."""
+    return ((x - y).norm(dim=1) / y.norm(dim=1)).cpu().tolist()
+
+
+def batched_legs(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a_fp64):
+    """Batches of nmaps power-law maps on the benchmark grid, both transforms:
+    "batched_mixed" (SHT_MIXED: FP64 recurrence, FP32 matrix-core
+    contraction; Delta and FFTs FP64) and "batched_fp64" (the same work in
+    FP64).  Map 0 of the batch is the map of the plain FP64 step: the
+    relative RMS differences of its map and of its analysed a_lm to the plain
+    results are reported, and every map of the mixed batch against the FP64
+    batch."""
+    alm = power_law_batch(si, lmax, nmaps, 2)
+    flops_mx = 4 * nmaps * count_triples(nslots, lmax, lmax)
+    st, bm, wall, mp_x, a_x = run_batch(sht, gh, g, lmax, alm, steps, warmup, sht.SHT_MIXED)
+    mx = batch_record(nmaps, st, bm, wall, steps, "f64 recurrence, f32 contraction", flops_mx,
+                      PEAK_FP32_MFMA_TFLOPS, "mfma", MX_KERNELS)
+    flops_64 = FLOPS_PER_TRIPLE * nmaps * count_triples(nslots, lmax, lmax)
+    st, bm, wall, mp_d, a_d = run_batch(sht, gh, g, lmax, alm, steps, warmup, 0)
+    f64 = batch_record(nmaps, st, bm, wall, steps, "f64", flops_64, PEAK_FP64_VALU_TFLOPS, "alu", F64_KERNELS)
+    rel = lambda x, y: (x - y).norm().item() / y.norm().item()
+    f64["relrms_map0_vs_plain"] = rel(mp_d[0], mp_fp64)
+    f64["relrms_alm0_vs_plain"] = rel(a_d[0], a_fp64)
+    mx["relrms_map0_vs_fp64"] = rel(mp_x[0], mp_fp64)
+    mx["relrms_alm0_vs_fp64"] = rel(a_x[0], a_fp64)
+    e_map, e_alm = rel_per_map(mp_x, mp_d), rel_per_map(a_x, a_d)
+    mx["relrms_vs_fp64_batch"] = {"map_max": max(e_map), "map_mean": sum(e_map) / nmaps,
+                                  "alm_max": max(e_alm), "alm_mean": sum(e_alm) / nmaps}
+    mx["speedup_vs_batched_fp64"] = mx["value"] / f64["value"]
+    mx["fft_roofline"] = fft_roofline(g, lmax, nmaps, mx["stages_ms"])
+    f64["fft_roofline"] = fft_roofline(g, lmax, nmaps, f64["stages_ms"])
+    mx["direction"] = f64["direction"] = "alm2map+map2alm"
+    return mx, f64
+
+
+def config3(sht, si, steps, warmup, with_oracle):
+    """The batched Gauss-Legendre configuration: 64 power-law maps on 1025
+    rings x 2049 points (2049 = 3 x 683: Bluestein ring transforms), lmax =
+    mmax = 1024, both transforms, mixed precision and FP64.  Errors: every
+    mixed map against the FP64 map, map 0 against the oracle over every
+    pixel, and the round trip against the seed a_lm (exact on this grid, so
+    a property of the transforms, independent of either implementation)."""
+    import numpy as np
+    lmax, nmaps = 1024, 64
+    g = si.gauss_legendre(lmax + 1, 2 * lmax + 1)
+    gh = sht.GeomHandle(g)
+    nslots = mirror_slots(g.theta)
+    alm = power_law_batch(si, lmax, nmaps, 3)
+    tri = count_triples(nslots, lmax, lmax)
+    st, bm, wall, mp_x, a_x = run_batch(sht, gh, g, lmax, alm, steps, warmup, sht.SHT_MIXED)
+    mx = batch_record(nmaps, st, bm, wall, steps, "f64 recurrence, f32 contraction", 4 * nmaps * tri,
+                      PEAK_FP32_MFMA_TFLOPS, "mfma", MX_KERNELS)
+    st, bm, wall, mp_d, a_d = run_batch(sht, gh, g, lmax, alm, steps, warmup, 0)
+    f64 = batch_record(nmaps, st, bm, wall, steps, "f64", FLOPS_PER_TRIPLE * nmaps * tri,
+                       PEAK_FP64_VALU_TFLOPS, "alu", F64_KERNELS)
+    e_map = rel_per_map(mp_x, mp_d)
+    e_rt_x, e_rt_d = rel_per_map(a_x, alm), rel_per_map(a_d, alm)
+    out = {
+        "workload": "batched alm2map+map2alm, Gauss-Legendre 1025 x 2049, lmax=mmax=1024, 64 maps, power-law a_lm",
+        "mixed": mx, "fp64": f64, "speedup_mixed_vs_fp64": mx["value"] / f64["value"],
+        "fft_roofline": fft_roofline(g, lmax, nmaps, mx["stages_ms"]),
+        "errors": {"mixed_map_vs_fp64_max": max(e_map), "mixed_map_vs_fp64_mean": float(np.mean(e_map)),
+                   "mixed_roundtrip_vs_seed_max": max(e_rt_x), "fp64_roundtrip_vs_seed_max": max(e_rt_d)},
+    }
+    if with_oracle:
+        import oracle
+        a0 = alm[0].cpu().numpy()
+        t0 = time.perf_counter()
+        ref = oracle.alm2map(lmax, lmax, g, a0)
+        m0x, m0d = mp_x[0].cpu().numpy(), mp_d[0].cpu().numpy()
+        nrm = np.linalg.norm(ref)
+        out["errors"]["mixed_map0_vs_oracle"] = float(np.linalg.norm(m0x - ref) / nrm)
+        out["errors"]["fp64_map0_vs_oracle"] = float(np.linalg.norm(m0d - ref) / nrm)
+        out["errors"]["oracle_s"] = time.perf_counter() - t0
+    return out
 
 
 def serving(sht, si, nreq: int, slots: int, budget_gb: float, loads=(0.5, 0.8)) -> dict:
@@ -331,6 +441,103 @@ def small_latency(sht, si, calls: int = 200) -> dict:
             "eager_host_us_per_call": eager_host_us, "graph_host_us_per_call": graph_host_us}
 
 
+def config4(sht, si, steps, warmup, nreq=256):
+    """The uneven batch: nreq single-map requests, lmax = round(exp U[ln 128,
+    ln 2048]), each on its own Gauss-Legendre grid of (lmax+1) x (2 lmax+1)
+    points, alm2map or map2alm with equal odds; map2alm inputs are FP64
+    alm2map outputs of power-law a_lm, so (exact quadrature) every map2alm
+    must return its seed a_lm.  Timed three ways on one stream: the batch
+    (sht_batch_run: ring analysis, one persistent Legendre launch for every
+    request, ring synthesis) replayed from a HIP graph; and the per-request
+    loop of sht_alm2map / sht_map2alm calls, FP64 and mixed precision."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(si.config_seed(4))
+    lms = np.round(np.exp(rng.uniform(np.log(128), np.log(2048), nreq))).astype(int)
+    kinds = np.where(rng.random(nreq) < 0.5, "alm2map", "map2alm")
+    t0 = time.perf_counter()
+    geoms = [sht.GeomHandle(si.gauss_legendre(L + 1, 2 * L + 1)) for L in lms.tolist()]
+    seeds, inputs = [], []
+    for i, (L, k, gh) in enumerate(zip(lms.tolist(), kinds.tolist(), geoms)):
+        a = torch.from_numpy(si.powerlaw_alm(L, L, si.config_seed(4, i))).cuda()
+        seeds.append(a)
+        inputs.append(a if k == "alm2map" else sht.alm2map(a, gh, L))
+    torch.cuda.synchronize()
+    batch = sht.Batch([(k, L, gh, x, None) for k, L, gh, x in zip(kinds.tolist(), lms.tolist(), geoms, inputs)],
+                      tiles="auto")
+    setup_s = time.perf_counter() - t0
+    print(f"[config4] {nreq} requests, plans and batch built in {setup_s:.1f} s", file=sys.stderr, flush=True)
+    for _ in range(warmup):
+        batch.run()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        batch.run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        batch.run()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, n):
+        fn()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(n):
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        return times
+
+    t_graph = timed(graph.replay, steps)
+    t_eager = timed(batch.run, steps)
+    # per-request loop, buffers preallocated
+    outs = [torch.empty_like(o) for o in batch.outputs]
+    wss = {f: [sht.workspace(L, L, gh, 1, "cuda", f) for L, gh in zip(lms.tolist(), geoms)] for f in (0, sht.SHT_MIXED)}
+
+    def loop(flags):
+        def run():
+            for i, (k, L, gh, x) in enumerate(zip(kinds.tolist(), lms.tolist(), geoms, inputs)):
+                fn = sht.alm2map if k == "alm2map" else sht.map2alm
+                fn(x, gh, L, out=outs[i], ws=wss[flags][i], flags=flags)
+        return run
+
+    t_loop = timed(loop(0), max(2, steps // 2))
+    loop_out = [o.clone() for o in outs]
+    t_loop_mx = timed(loop(sht.SHT_MIXED), max(2, steps // 2))
+    rel = lambda x, y: (x - y).norm().item() / y.norm().item()
+    ana = [i for i, k in enumerate(kinds.tolist()) if k == "map2alm"]
+    syn = [i for i, k in enumerate(kinds.tolist()) if k == "alm2map"]
+    err_ana = max(rel(batch.outputs[i], seeds[i]) for i in ana)
+    err_syn = max(rel(batch.outputs[i], loop_out[i]) for i in syn)
+    err_mx_ana = max(rel(outs[i], seeds[i]) for i in ana)
+    nslots = [(L + 2) // 2 for L in lms.tolist()]
+    flops = sum(FLOPS_PER_TRIPLE * ns * (L + 1) * (L + 2) // 2 for ns, L in zip(nslots, lms.tolist()))
+    ms = float(np.median(t_graph))
+    batch.close()
+    return {
+        "workload": (f"uneven batch: {nreq} single-map requests, lmax log-uniform in [128, 2048] on their own "
+                     f"Gauss-Legendre grids, {len(syn)} alm2map + {len(ana)} map2alm, FP64"),
+        "value": nreq * 1000.0 / ms, "unit": "maps/s", "ms_per_batch": ms,
+        "latency_ms": latency(t_graph),
+        "eager_ms_per_batch": float(np.median(t_eager)),
+        "per_request_loop_fp64": {"ms_per_batch": float(np.median(t_loop)),
+                                  "value": nreq * 1000.0 / float(np.median(t_loop))},
+        "per_request_loop_mixed": {"ms_per_batch": float(np.median(t_loop_mx)),
+                                   "value": nreq * 1000.0 / float(np.median(t_loop_mx)),
+                                   "map2alm_relrms_vs_seed_max": err_mx_ana},
+        "speedup_vs_per_request_fp64": float(np.median(t_loop)) / ms,
+        "legendre_flops_per_batch": flops,
+        "legendre_tflops_whole_batch": flops / (ms * 1e-3) / 1e12,
+        "errors": {"map2alm_relrms_vs_seed_max": err_ana, "alm2map_relrms_vs_single_calls_max": err_syn},
+        "lmax_range": [int(lms.min()), int(lms.max())], "setup_s": setup_s,
+    }
+
+
 def copy_probe(nbytes: int) -> None:
     """A plain device copy of known size, for calibrating HBM byte counters."""
     import torch
@@ -358,6 +565,10 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=4, help="concurrent requests (HIP streams) in the serving leg")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0, help="HBM budget of the serving leg")
     ap.add_argument("--serve-only", action="store_true", help="run only the serving leg")
+    ap.add_argument("--no-config4", action="store_true",
+                    help="skip the uneven-batch leg (256 requests, lmax 128..2048, one persistent Legendre launch)")
+    ap.add_argument("--no-config3", action="store_true",
+                    help="skip the batched Gauss-Legendre leg (1025 x 2049, lmax 1024, 64 maps)")
     ap.add_argument("--no-small-latency", action="store_true",
                     help="skip the launch-bound lmax=256 latency leg (e.g. to profile the main step alone)")
     ap.add_argument("--copy-probe", type=int, default=0, help="run only a device copy of this many bytes")
@@ -372,8 +583,8 @@ def main():
         copy_probe(args.copy_probe)
         return
     if args.peak_probe:
-        import paper_1106_0159_amd as sht
-        rates = [sht.probe_rate(k) for k in sht.PROBE_KINDS]
+        from paper_1106_0159_amd import probe
+        rates = [probe.rate(k) for k in probe.KINDS]
         print(json.dumps({"peak_probe": rates,
                           "nominal_tflops": {"fp64_fma": PEAK_FP64_VALU_TFLOPS,
                                              "fp32_mfma_16x16x4": PEAK_FP32_MFMA_TFLOPS,
@@ -469,6 +680,7 @@ def main():
         },
         "stages_ms": stage_ms,
         "latency_ms": latency(step_times),
+        "fft_roofline": fft_roofline(g, lmax, 1, stage_ms),
         "alm2map_maps_per_s": 1000.0 / (stage_ms["leg_syn"] + stage_ms["fft_syn"]),
         "map2alm_maps_per_s": 1000.0 / (stage_ms["fft_ana"] + stage_ms["leg_ana"]),
         "roofline": {
@@ -486,8 +698,19 @@ def main():
         },
     }
     if args.batch > 0:
-        rec["batched_mixed"] = batched_mixed(sht, si, gh, g, lmax, args.batch, max(3, K // 4), args.warmup,
-                                             nslots, mp, a_out)
+        rec["batched_mixed"], rec["batched_fp64"] = batched_legs(sht, si, gh, g, lmax, args.batch, max(3, K // 4),
+                                                                 args.warmup, nslots, mp, a_out)
+        print(f"[batch] mixed {rec['batched_mixed']['value']:.0f} maps/s, "
+              f"fp64 {rec['batched_fp64']['value']:.0f} maps/s", file=sys.stderr, flush=True)
+    if not args.no_config3:
+        rec["config3"] = config3(sht, si, max(3, K // 4), args.warmup, not args.no_cpu_baseline)
+        print(f"[config3] mixed {rec['config3']['mixed']['value']:.0f} maps/s, "
+              f"fp64 {rec['config3']['fp64']['value']:.0f} maps/s", file=sys.stderr, flush=True)
+    if not args.no_config4:
+        rec["config4"] = config4(sht, si, max(5, K // 2), args.warmup)
+        print(f"[config4] batch {rec['config4']['value']:.0f} maps/s ({rec['config4']['ms_per_batch']:.2f} ms), "
+              f"per-request loop {rec['config4']['per_request_loop_fp64']['value']:.0f} maps/s", file=sys.stderr,
+              flush=True)
     if not args.no_small_latency:
         rec["small_latency"] = small_latency(sht, si)
         print(f"[small] eager {rec['small_latency']['eager_us_per_map']:.1f} us/map, "

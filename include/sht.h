@@ -27,8 +27,10 @@
  *
  * Conventions: Im a_l0 is ignored on input and written as exactly 0 on
  * output.  Rings r, r' whose colatitudes satisfy |theta_r + theta_r' - pi|
- * <= 1e-14 are treated as mirror images (cos theta_r' = -cos theta_r) and
- * share one Legendre recurrence.
+ * <= 2^-50 (8.9e-16 rad, two ulp of pi; the sum taken exactly) are treated as
+ * mirror images (cos theta_r' = -cos theta_r, evaluated from the northern
+ * ring) and share one Legendre recurrence; any other ring is evaluated at its
+ * own colatitude.
  *
  * Execution: every compute call validates its arguments on the host, then
  * enqueues kernels on `stream` (a hipStream_t; NULL = the null stream) and
@@ -38,7 +40,7 @@
  * for a (lmax, mmax, geometry) builds and caches device tables (recurrence
  * coefficients, FFT plans, and for the Legendre stage the start table: where
  * each (m, ring pair) recurrence enters double range, 20 bytes per (m, pair),
- * built by a kernel on `stream`); that call synchronises the device.  The
+ * built by a kernel on `stream`); that call waits for `stream`.  The
  * library owns these tables and frees them on eviction or sht_shutdown().
  *
  * Thread safety: all functions may be called from several host threads.
@@ -73,9 +75,12 @@ enum sht_status {
     SHT_EWORKSPACE = -2,    /* workspace NULL or smaller than required */
     SHT_EDEVICE = -3,       /* a HIP runtime call failed (see sht_strerror) */
     SHT_ENOMEM = -4,        /* device or host allocation for plan tables failed */
-    SHT_EUNSUPPORTED = -5   /* unknown flag bit, or a size beyond the kernels' limits
+    SHT_EUNSUPPORTED = -5,  /* unknown flag bit, or a size beyond the kernels' limits
                                (a ring of more than 8192 pixels, mmax >= 65535,
                                nmaps > 65535, grids beyond 2^31 workgroups) */
+    SHT_ENOPLAN = -6        /* the plan tables of this (lmax, mmax, geometry) are not
+                               resident and pinned (sht_prepare with SHT_PIN), where a
+                               call requires that (sht_unpin) */
 };
 
 /* Flag bits of the `flags` arguments. */
@@ -107,7 +112,13 @@ enum sht_flags {
      * give the same bits in either layout; the ring stages then transform two
      * adjacent maps of one ring together instead of the two rings of a mirror
      * pair, which changes their results by rounding only. */
-    SHT_DELTA_MAP_MINOR = 2u
+    SHT_DELTA_MAP_MINOR = 2u,
+    /* sht_prepare only: pin the plan's tables (one more pin per call) so that
+     * no eviction (LRU or sht_plan_cache_limits) frees them until as many
+     * sht_unpin calls have removed the pins; only sht_shutdown frees pinned
+     * tables.  A pinned cache may hold more entries than its limits.  The
+     * transforms reject this bit (SHT_EUNSUPPORTED). */
+    SHT_PIN = 4u
 };
 
 /* Bytes of device workspace needed by sht_alm2map, sht_map2alm,
@@ -156,6 +167,61 @@ int sht_map2delta(int mmax, const sht_geom *g, const double *map, void *delta, i
 int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void *alm,
                   int nmaps, void *workspace, size_t ws_bytes, uint32_t flags, void *stream);
 
+/* ---- uneven batches: many requests, one persistent Legendre launch ----
+ *
+ * A batch is a fixed set of transforms, each with its own lmax, mmax,
+ * geometry and direction (one map each), whose Legendre stage (Sec. 3,
+ * Algs. 1 and 2) runs in ONE persistent launch: every workgroup takes the
+ * next work item -- (request, m-block, ring tile) -- from a device queue
+ * until it is empty.  The items are listed longest first, the dynamic
+ * counterpart of the paper's min-max balancing of m (Sec. 4.2.1, where
+ * pairs m' + m'' = mmax cost the same): the cheap items of every request
+ * fill the end of the run on each CU.  Around it: the ring analysis of the
+ * map2alm requests before, the ring synthesis of the alm2map requests after.
+ * Precision: FP64 (flags 0).  Results equal those of sht_alm2map /
+ * sht_map2alm to rounding (the same arithmetic; analysis tiles may sum ring
+ * pairs in another order). */
+enum sht_kind { SHT_ALM2MAP = 0, SHT_MAP2ALM = 1 };
+typedef struct sht_request {
+    int32_t kind;          /* SHT_ALM2MAP or SHT_MAP2ALM */
+    int32_t lmax, mmax;    /* 0 <= mmax <= lmax */
+    const sht_geom *geom;  /* HOST, read during sht_batch_create only; map2alm needs weights */
+    const void *in;        /* DEVICE: a_lm complex128 [nalm] (alm2map) or map float64 [npix] (map2alm) */
+    void *out;             /* DEVICE: map (alm2map) or a_lm (map2alm), written by every sht_batch_run */
+    int32_t tile;          /* Legendre tile: 0 = the library's choice, else 16 * shape + T with T in {1, 2, 4}:
+                              shape 0 = one wave per (m, 64 T ring slots), four such units per item
+                              (analysis: every slot of m in one wave, so 64 T >= slots); shape 1
+                              (analysis only) = one workgroup per (m, group of 256 T slots), groups
+                              added by a combine kernel.  A slot is a mirror ring pair or a ring. */
+} sht_request;
+typedef struct sht_batch sht_batch;
+
+/* Device workspace bytes of a batch (a multiple of 256; 0 if a request is
+ * invalid).  It holds the queue head and every request's Delta and aux. */
+size_t sht_batch_workspace_bytes(int nreq, const sht_request *reqs, uint32_t flags);
+
+/* Builds a batch: validates every request (SHT_EINVAL / SHT_EUNSUPPORTED as
+ * for the single transforms; flags must be 0), builds and pins each plan
+ * (start tables by kernels on `stream`, waited for), and uploads the request
+ * table and the item list.  `workspace` (DEVICE, 256-byte aligned, at least
+ * sht_batch_workspace_bytes, not aliasing any request's buffers) and every
+ * request's in/out pointers are bound to the batch: they must stay valid until
+ * sht_batch_destroy.  On success *out owns the batch; on failure *out is NULL. */
+int sht_batch_create(int nreq, const sht_request *reqs, void *workspace, size_t ws_bytes, uint32_t flags,
+                     void *stream, sht_batch **out);
+
+/* Enqueues every transform of the batch on `stream` (a fixed launch
+ * sequence: no allocation, copy or synchronisation, so it may be captured
+ * in a HIP graph and replayed; the queue is reset by a kernel at its start).
+ * Runs of one batch must not overlap (they share its workspace).  Returns
+ * SHT_OK, SHT_EINVAL (NULL batch, or another device current than at
+ * creation) or SHT_EDEVICE. */
+int sht_batch_run(sht_batch *b, void *stream);
+
+/* Frees the batch's device tables and unpins its plans.  No run of it may be
+ * in flight. */
+void sht_batch_destroy(sht_batch *b);
+
 /* ---- plan residency, for callers that serve requests of many sizes ----
  *
  * The plan tables of a (lmax, mmax, geometry) are what the paper's memory
@@ -170,18 +236,35 @@ int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void
  * start table is built by a kernel on `stream`; the call returns after it has
  * completed.  Validation as for sht_alm2map (weights may be NULL; a geometry
  * with weights and one without are distinct cache keys, so a caller that
- * runs both directions passes the weights to both).  `flags` is validated
- * only: both precision modes use the same tables.  Returns SHT_OK,
- * SHT_EINVAL, SHT_EUNSUPPORTED, SHT_ENOMEM or SHT_EDEVICE. */
+ * runs both directions passes the weights to both).  `flags`: SHT_MIXED is
+ * validated only (both precision modes use the same tables); SHT_PIN pins the
+ * tables (see sht_flags).  Returns SHT_OK, SHT_EINVAL, SHT_EUNSUPPORTED,
+ * SHT_ENOMEM or SHT_EDEVICE.
+ *
+ * HIP graph capture: once its plan is resident, a transform call enqueues
+ * kernels and stream-ordering events only (no allocation, copy, memset or
+ * synchronisation), so it may be captured.  A captured graph holds the
+ * tables' device addresses: it is valid only while the plan stays pinned
+ * (SHT_PIN) and until sht_shutdown.  Under capture the ring stages fork onto
+ * side streams that belong to the capturing stream, so captures on
+ * different streams, and eager calls on other streams, do not interfere. */
 int sht_prepare(int lmax, int mmax, const sht_geom *g, uint32_t flags, void *stream);
+
+/* Removes one pin that sht_prepare(..., SHT_PIN) put on the tables of this
+ * (lmax, mmax, geometry); they become evictable when no pin is left.
+ * Returns SHT_OK, SHT_EINVAL (invalid arguments) or SHT_ENOPLAN (no pinned
+ * tables for these arguments). */
+int sht_unpin(int lmax, int mmax, const sht_geom *g);
 
 /* Sets how many coefficient tables (one per (device, lmax, mmax)) and how
  * many geometry plans (one per (device, geometry), each holding up to four
  * start tables) the cache keeps before it evicts the least recently used
- * (defaults 8 and 32).  Lowering a limit evicts at once.  An evicted table is
- * freed when the last call holding it has returned, after a device
- * synchronisation, so that kernels in flight never lose it.  Returns SHT_OK,
- * or SHT_EINVAL if either limit is below 1. */
+ * unpinned one (defaults 8 and 32).  Lowering a limit evicts at once.  An
+ * evicted table is freed when the last call holding it has returned, after
+ * the host has waited for the work that each stream enqueued with it (an
+ * event per stream, re-recorded by every call), so kernels in flight never
+ * lose it; no device-wide synchronisation is involved.  Returns SHT_OK, or
+ * SHT_EINVAL if either limit is below 1. */
 int sht_plan_cache_limits(int max_coef_tables, int max_geom_plans);
 
 /* Device bytes held by the plan cache over all devices (coefficient tables,

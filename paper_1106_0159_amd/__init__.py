@@ -19,13 +19,17 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libsht.so")
 
 SHT_OK, SHT_EINVAL, SHT_EWORKSPACE, SHT_EDEVICE, SHT_ENOMEM, SHT_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+SHT_ENOPLAN = -6
 SHT_MIXED = 1  # flag: FP32 matrix-core Legendre contraction (include/sht.h)
 SHT_DELTA_MAP_MINOR = 2  # flag: stage-call Delta laid out [nrings][mmax+1][nmaps]
+SHT_PIN = 4  # sht_prepare flag: keep the plan's tables until sht_unpin
 
 EXPORTS = ("sht_workspace_bytes", "sht_alm2map", "sht_map2alm", "sht_alm2delta", "sht_delta2map",
            "sht_map2delta", "sht_delta2alm", "sht_strerror", "sht_shutdown",
-           "sht_prepare", "sht_plan_cache_limits", "sht_plan_cache_bytes",
-           "sht_probe_flops", "sht_probe_run")
+           "sht_prepare", "sht_unpin", "sht_plan_cache_limits", "sht_plan_cache_bytes",
+           "sht_batch_workspace_bytes", "sht_batch_create", "sht_batch_run",
+           "sht_batch_destroy")
+SHT_ALM2MAP, SHT_MAP2ALM = 0, 1  # sht_request.kind
 
 
 class ShtError(RuntimeError):
@@ -37,6 +41,12 @@ class ShtError(RuntimeError):
 class _Geom(ctypes.Structure):
     _fields_ = [("nrings", ctypes.c_int32), ("theta", ctypes.c_void_p), ("nphi", ctypes.c_void_p),
                 ("phi0", ctypes.c_void_p), ("weight", ctypes.c_void_p), ("ofs", ctypes.c_void_p)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("lmax", ctypes.c_int32), ("mmax", ctypes.c_int32),
+                ("geom", ctypes.POINTER(_Geom)), ("in_", ctypes.c_void_p), ("out", ctypes.c_void_p),
+                ("tile", ctypes.c_int32)]
 
 
 _lib = None
@@ -70,14 +80,21 @@ def lib() -> ctypes.CDLL:
         L.sht_shutdown.argtypes = []
         L.sht_prepare.restype = I
         L.sht_prepare.argtypes = [I, I, GP, U, P]
+        L.sht_unpin.restype = I
+        L.sht_unpin.argtypes = [I, I, GP]
+        RP = ctypes.POINTER(_Request)
+        L.sht_batch_workspace_bytes.restype = S
+        L.sht_batch_workspace_bytes.argtypes = [I, RP, U]
+        L.sht_batch_create.restype = I
+        L.sht_batch_create.argtypes = [I, RP, P, S, U, P, ctypes.POINTER(P)]
+        L.sht_batch_run.restype = I
+        L.sht_batch_run.argtypes = [P, P]
+        L.sht_batch_destroy.restype = None
+        L.sht_batch_destroy.argtypes = [P]
         L.sht_plan_cache_limits.restype = I
         L.sht_plan_cache_limits.argtypes = [I, I]
         L.sht_plan_cache_bytes.restype = S
         L.sht_plan_cache_bytes.argtypes = []
-        L.sht_probe_flops.restype = ctypes.c_double
-        L.sht_probe_flops.argtypes = [I, I, I]
-        L.sht_probe_run.restype = I
-        L.sht_probe_run.argtypes = [I, I, I, P, P]
         _lib = L
     return _lib
 
@@ -249,11 +266,19 @@ def delta2alm(delta, geom, lmax: int, mmax: int | None = None, out=None, ws=None
     return out
 
 
-def prepare(geom, lmax: int, mmax: int | None = None, stream=None, flags: int = 0) -> None:
+def prepare(geom, lmax: int, mmax: int | None = None, stream=None, flags: int = 0, pin: bool = False) -> None:
     """Build and keep resident the plan tables of (lmax, mmax, geom); returns
-    once the start table's kernel has completed."""
+    once the start table's kernel has completed.  pin=True adds a pin (no
+    eviction until unpin())."""
     mmax = lmax if mmax is None else mmax
-    _check(lib().sht_prepare(lmax, mmax, _gh(geom).ref(), flags, _stream_ptr(stream)), "sht_prepare")
+    f = flags | (SHT_PIN if pin else 0)
+    _check(lib().sht_prepare(lmax, mmax, _gh(geom).ref(), f, _stream_ptr(stream)), "sht_prepare")
+
+
+def unpin(geom, lmax: int, mmax: int | None = None) -> None:
+    """Remove one pin that prepare(..., pin=True) put on these plan tables."""
+    mmax = lmax if mmax is None else mmax
+    _check(lib().sht_unpin(lmax, mmax, _gh(geom).ref()), "sht_unpin")
 
 
 def plan_cache_limits(max_coef_tables: int, max_geom_plans: int) -> None:
@@ -264,27 +289,88 @@ def plan_cache_bytes() -> int:
     return int(lib().sht_plan_cache_bytes())
 
 
-PROBE_KINDS = {"fp64_fma": 0, "fp32_mfma_16x16x4": 1, "bf16_mfma_16x16x32": 2}  # include/sht_probe.h
+def ring_slots(theta) -> int:
+    """Ring slots of a geometry as the library forms them (mirror pairs, with
+    |theta + theta' - pi| <= 2^-50 summed exactly, plus unpaired rings)."""
+    th = sorted(float(t) for t in np.asarray(theta))
+    pi_l = np.longdouble("3.14159265358979323846264338327950288")
+    i, j, n = 0, len(th) - 1, 0
+    while i <= j:
+        if i == j:
+            return n + 1
+        d = float((np.longdouble(th[i]) + np.longdouble(th[j])) - pi_l)
+        if abs(d) <= 2.0 ** -50:
+            i, j = i + 1, j - 1
+        elif d < 0:
+            i += 1
+        else:
+            j -= 1
+        n += 1
+    return n
 
 
-def probe_rate(kind: str, blocks: int = 8192, iters: int = 4000, device="cuda") -> dict:
-    """Attained TFLOP/s of one throughput probe (one warm-up launch, one timed
-    with HIP events on the current stream)."""
-    torch = _torch()
-    k = PROBE_KINDS[kind]
-    flops = lib().sht_probe_flops(k, blocks, iters)
-    if flops <= 0:
-        raise ShtError(SHT_EINVAL, "sht_probe_flops")
-    out = torch.empty(blocks * 256, dtype=torch.float64, device=device)
-    s = _stream_ptr(None)
-    _check(lib().sht_probe_run(k, blocks, iters, out.data_ptr(), s), "sht_probe_run")
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    _check(lib().sht_probe_run(k, blocks, iters, out.data_ptr(), s), "sht_probe_run")
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1)
-    return {"kind": kind, "blocks": blocks, "iters": iters, "flops": flops, "ms": ms, "tflops": flops / ms / 1e9}
+class Batch:
+    """An uneven batch (sht_batch_*): transforms of any lmax, geometry and
+    direction whose Legendre stage runs in one persistent launch.
+
+    requests: list of (kind, lmax, geom, input tensor, output tensor[, tile])
+    with kind "alm2map" or "map2alm", one map each.  Outputs may be None (they
+    are allocated).  Inputs, outputs and the workspace are bound to the batch:
+    every run() reads the inputs and writes the outputs."""
+
+    def __init__(self, requests, device="cuda", stream=None, tiles=None):
+        """tiles: None (the library's choice), "auto" (the autotuner's table,
+        autotune.TABLE_PATH) or a table dict; a tile given in a request wins."""
+        torch = _torch()
+        if tiles == "auto":
+            from . import autotune
+            tiles = autotune.load()
+        self.geoms, self.inputs, self.outputs, self.kinds = [], [], [], []
+        arr = (_Request * len(requests))()
+        for i, rq in enumerate(requests):
+            kind, lmax, geom, x, y = rq[:5]
+            tile = rq[5] if len(rq) > 5 else 0
+            if not tile and tiles:
+                from . import autotune
+                tile = autotune.choose(tiles, kind, lmax, ring_slots(_gh(geom).theta))
+            k = {"alm2map": SHT_ALM2MAP, "map2alm": SHT_MAP2ALM}[kind]
+            g = _gh(geom, with_weight=True)
+            if y is None:
+                if k == SHT_ALM2MAP:
+                    alloc = torch.empty if g.covers_all else torch.zeros
+                    y = alloc(g.npix, dtype=torch.float64, device=device)
+                else:
+                    y = torch.empty(nalm(lmax, lmax), dtype=torch.complex128, device=device)
+            self.geoms.append(g)
+            self.inputs.append(x)
+            self.outputs.append(y)
+            self.kinds.append(kind)
+            arr[i] = _Request(k, lmax, lmax, ctypes.pointer(g.c), x.data_ptr(), y.data_ptr(), tile)
+        self._reqs = arr
+        n = int(lib().sht_batch_workspace_bytes(len(requests), arr, 0))
+        if n == 0:
+            raise ShtError(SHT_EINVAL, "sht_batch_workspace_bytes")
+        self.workspace = torch.empty(n, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(lib().sht_batch_create(len(requests), arr, self.workspace.data_ptr(), n, 0, _stream_ptr(stream),
+                                      ctypes.byref(h)), "sht_batch_create")
+        self._h = h
+
+    def run(self, stream=None) -> None:
+        _check(lib().sht_batch_run(self._h, _stream_ptr(stream)), "sht_batch_run")
+
+    def close(self) -> None:
+        """Free the batch (after the device has finished every run of it)."""
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _torch().cuda.synchronize()
+            lib().sht_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def shutdown() -> None:

@@ -152,27 +152,22 @@ __device__ __forceinline__ double warm_l2(const double *p, int stride, int i0, i
     return p[(int64_t)stride * i];
 }
 
-// Synthesis: lane i of tile t owns slots (t*256 + i)*T + u, u < T.
+// Synthesis of one m of one map over a tile of slots: thread li of the
+// threads sharing the tile owns slots slot0 + li*T + u, u < T.  The wave
+// works on its own (no cross-wave step), so a tile may be one wave's
+// (li = lane) or a workgroup's (li = thread index).
+
 template <int T>
-__global__ __launch_bounds__(kBlock, 4) void k_leg_syn(int lmax, int mmax, int nslots, int tiles,
-                                                    int nrings, int64_t nalm,
-                                                    const double2 *__restrict__ ap,
-                                                    const double *__restrict__ alpha,
-                                                    const int32_t *__restrict__ lstart,
-                                                    const double2 *__restrict__ state,
-                                                    const double *__restrict__ sx,
-                                                    const int32_t *__restrict__ rn,
-                                                    const int32_t *__restrict__ rsouth,
-                                                    double2 *__restrict__ delta) {
-    const MPart mp = xcd_m_part(tiles);
-    const int m = mp.m, tile = mp.part;
-    if (m > mmax) return;  // padding of the m range
-    const int map = blockIdx.y;
+__device__ __forceinline__ void syn_tile(const SynArgs &A, int m, int map, int slot0, int li) {
+    const int lmax = A.lmax, mmax = A.mmax, nslots = A.nslots, nrings = A.nrings;
+    const double *__restrict__ sx = A.sx;
+    const int32_t *__restrict__ lstart = A.lstart;
+    const double2 *__restrict__ state = A.state;
+    const int32_t *__restrict__ rn = A.rn;
+    const int32_t *__restrict__ rsouth = A.rsouth;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;  // (l, m) lives at base + l
-    const double2 *__restrict__ a = ap + (int64_t)map * nalm + base;
-    const double *__restrict__ al = alpha + base;
-    const double warm_a = warm_l2(reinterpret_cast<const double *>(a), 2, m, lmax);
-    const double warm_al = warm_l2(al, 1, m, lmax);
+    const double2 *__restrict__ a = A.ap + (int64_t)map * A.nalm + base;
+    const double *__restrict__ al = A.alpha + base;
 
     double x[T], q1[T], q2[T], er[T], ei[T], orr[T], oi[T];
     int ls[T];
@@ -180,7 +175,7 @@ __global__ __launch_bounds__(kBlock, 4) void k_leg_syn(int lmax, int mmax, int n
     int lo = lmax + 1, hi = m;
 #pragma unroll
     for (int u = 0; u < T; ++u) {
-        const int slot = (tile * kBlock + (int)threadIdx.x) * T + u;
+        const int slot = slot0 + li * T + u;
         const bool act = slot < nslots;
         x[u] = act ? sx[slot] : 0.0;
         ls[u] = act ? lstart[(int64_t)m * nslots + slot] : lmax + 1;
@@ -289,16 +284,147 @@ __global__ __launch_bounds__(kBlock, 4) void k_leg_syn(int lmax, int mmax, int n
         acc_e(a[l]);
     }
 
-    double2 *d = delta + (int64_t)map * nrings * (mmax + 1);
+    double2 *d = A.delta + (int64_t)map * nrings * (mmax + 1);
 #pragma unroll
     for (int u = 0; u < T; ++u) {
-        const int slot = (tile * kBlock + (int)threadIdx.x) * T + u;
+        const int slot = slot0 + li * T + u;
         if (slot < nslots) {
             d[(int64_t)rn[slot] * (mmax + 1) + m] = make_double2(er[u] + orr[u], ei[u] + oi[u]);
             const int r2 = rsouth[slot];
             if (r2 >= 0) d[(int64_t)r2 * (mmax + 1) + m] = make_double2(er[u] - orr[u], ei[u] - oi[u]);
         }
     }
+}
+
+// Synthesis of M maps at once (FP64): each (m, slot) recurrence value
+// serves all M maps of the workgroup's map group (grid.y), so a slot and l
+// cost 2 + 2M operations instead of 4M.  Per map the arithmetic is that of
+// syn_tile (the same fused multiply-adds in the same order), so the results
+// are the same bits.  Maps past nmaps of the last group repeat the last map
+// and are not stored.
+template <int T, int M>
+__global__ __launch_bounds__(kBlock, 4) void k_leg_syn_mm(SynArgs A, int tiles, int nmaps) {
+    const MPart mp = xcd_m_part(tiles);
+    const int m = mp.m, tile = mp.part;
+    if (m > A.mmax) return;  // padding of the m range
+    const int lmax = A.lmax, mmax = A.mmax, nslots = A.nslots;
+    const int map0 = blockIdx.y * M;
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;  // (l, m) lives at base + l
+    const double *__restrict__ al = A.alpha + base;
+    const double2 *__restrict__ a[M];
+#pragma unroll
+    for (int k = 0; k < M; ++k) a[k] = A.ap + (int64_t)min(map0 + k, nmaps - 1) * A.nalm + base;
+    const double warm_a = warm_l2(reinterpret_cast<const double *>(a[0]), 2, m, lmax);
+    const double warm_al = warm_l2(al, 1, m, lmax);
+
+    double x[T], q1[T], q2[T], er[T][M], ei[T][M], orr[T][M], oi[T][M];
+    int ls[T];
+    double2 st[T];
+    int lo = lmax + 1, hi = m;
+#pragma unroll
+    for (int u = 0; u < T; ++u) {
+        const int slot = (tile * kBlock + (int)threadIdx.x) * T + u;
+        const bool act = slot < nslots;
+        x[u] = act ? A.sx[slot] : 0.0;
+        ls[u] = act ? A.lstart[(int64_t)m * nslots + slot] : lmax + 1;
+        st[u] = act ? A.state[(int64_t)m * nslots + slot] : make_double2(0.0, 0.0);
+        q1[u] = q2[u] = 0.0;  // a slot carries zeros until it starts
+#pragma unroll
+        for (int k = 0; k < M; ++k) er[u][k] = ei[u][k] = orr[u][k] = oi[u][k] = 0.0;
+        lo = min(lo, ls[u]);
+        if (ls[u] <= lmax) hi = max(hi, ls[u]);
+    }
+    lo = wave_min(lo);
+    hi = wave_max(hi);
+
+    auto rec = [&](double av) {
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const double q = fma(av * x[u], q1[u], -q2[u]);
+            q2[u] = q1[u];
+            q1[u] = q;
+        }
+    };
+    // one l of even (l - m): E += a q; odd: O += a q
+    auto step = [&](int l, bool odd) {
+        rec(al[l]);
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const double2 c = a[k][l];
+#pragma unroll
+            for (int u = 0; u < T; ++u) {
+                if (odd) {
+                    orr[u][k] = fma(c.x, q1[u], orr[u][k]);
+                    oi[u][k] = fma(c.y, q1[u], oi[u][k]);
+                } else {
+                    er[u][k] = fma(c.x, q1[u], er[u][k]);
+                    ei[u][k] = fma(c.y, q1[u], ei[u][k]);
+                }
+            }
+        }
+    };
+    auto inject = [&](int l) {
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            if (ls[u] == l) {
+                q2[u] = st[u].x;
+                q1[u] = st[u].y;
+            }
+        }
+    };
+
+    // start positions are m + kStartStep k: walk whole blocks while lanes join
+    int l = lo;
+    for (; l <= hi && l + kStartStep - 1 <= lmax; l += kStartStep) {
+        inject(l);
+#pragma unroll 1
+        for (int i = 0; i < kStartStep; i += 2) {
+            step(l + i, false);
+            step(l + i + 1, true);
+        }
+    }
+    if (l <= hi) inject(l);  // the last start lies in the ragged tail
+    l = __builtin_amdgcn_readfirstlane(l);
+    // (loops kept rolled: unrolled, their hoisted scalar loads of M a_lm
+    // columns spill)
+#pragma unroll 1
+    for (; l + 1 <= lmax; l += 2) {
+        step(l, false);
+        step(l + 1, true);
+    }
+    if (l == lmax) step(l, false);  // one trailing step with even (l - m)
+
+#pragma unroll
+    for (int k = 0; k < M; ++k) {
+        if (map0 + k >= nmaps) break;
+        double2 *d = A.delta + (int64_t)(map0 + k) * A.nrings * (mmax + 1);
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            const int slot = (tile * kBlock + (int)threadIdx.x) * T + u;
+            if (slot < nslots) {
+                d[(int64_t)A.rn[slot] * (mmax + 1) + m] =
+                    make_double2(er[u][k] + orr[u][k], ei[u][k] + oi[u][k]);
+                const int r2 = A.rsouth[slot];
+                if (r2 >= 0)
+                    d[(int64_t)r2 * (mmax + 1) + m] = make_double2(er[u][k] - orr[u][k], ei[u][k] - oi[u][k]);
+            }
+        }
+    }
+    asm volatile("" ::"v"(warm_a), "v"(warm_al));  // the warming loads are waited for only here
+}
+
+// Synthesis kernel: grid.x = (m, 256T-slot tile) in the XCD-aware order,
+// grid.y = map; thread i of tile t owns slots (t*256 + i)*T + u, u < T.
+template <int T>
+__global__ __launch_bounds__(kBlock, 4) void k_leg_syn(SynArgs A, int tiles) {
+    const MPart mp = xcd_m_part(tiles);
+    const int m = mp.m, tile = mp.part;
+    if (m > A.mmax) return;  // padding of the m range
+    const int64_t base = (int64_t)m * (2 * A.lmax + 1 - m) / 2;
+    const double warm_a = warm_l2(reinterpret_cast<const double *>(A.ap + (int64_t)blockIdx.y * A.nalm + base), 2,
+                                  m, A.lmax);
+    const double warm_al = warm_l2(A.alpha + base, 1, m, A.lmax);
+    syn_tile<T>(A, m, (int)blockIdx.y, tile * kBlock * T, (int)threadIdx.x);
     asm volatile("" ::"v"(warm_a), "v"(warm_al));  // the warming loads are waited for only here
 }
 
@@ -352,77 +478,116 @@ __device__ __forceinline__ double quad_sum(double v) {
     return v + w;
 }
 
-// Analysis: workgroups of 4 waves; wave w of group g of m owns slots
-// ((g*4 + w) * 64 + lane) * T + t.  Per chunk of kChunk l values each lane
-// sums its T slots; the wave sums its 64 lanes through its own LDS rows (no
-// barrier); every kFlush chunks the 4 wave sums are added in wave order after
-// one barrier.  The workgroup starts at the earliest start of its slots (a_lm
-// before it get no term); a wave adds zeros until its own first start.  With
-// one group the finished a_lm (times c_lm) is written; otherwise the group's
-// partial goes to part[(map * groups + group) * nalm + idx] for k_ana_combine.
-template <int T>
-__global__ __launch_bounds__(kAnaThreads) void k_leg_ana(int lmax, int mmax, int nslots, int nrings,
-                                                    int64_t nalm, int groups,
-                                                    const double2 *__restrict__ delta,
-                                                    const double *__restrict__ alpha,
-                                                    const double *__restrict__ cfac,
-                                                    const int32_t *__restrict__ lstart,
-                                                    const double2 *__restrict__ state,
-                                                    const double *__restrict__ sx,
-                                                    const int32_t *__restrict__ rn,
-                                                    const int32_t *__restrict__ rsouth,
-                                                    double2 *__restrict__ alm,
-                                                    double2 *__restrict__ part) {
-    constexpr int kVals = 2 * kChunk;                 // (l, re/im) values per chunk
-    constexpr int kWaves = kAnaThreads / 64;
-    __shared__ double tbuf[kWaves][kVals][kTRow];     // wave-private transpose rows
-    __shared__ double ring[2][kFlush][kWaves][kVals]; // per-wave chunk sums awaiting the flush
-    __shared__ int wstart[kWaves];
-    static_assert(kFlush * kVals <= kAnaThreads, "one thread per flushed value");
-    const MPart mp = xcd_m_part(groups);
-    const int m = mp.m, grp = mp.part;
-    if (m > mmax) return;  // padding of the m range (before any barrier)
-    const int map = blockIdx.y;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
-    const double *__restrict__ al = alpha + base;
-    const double2 *__restrict__ d = delta + (int64_t)map * nrings * (mmax + 1);
-    double2 *__restrict__ dst = (groups == 1) ? alm + (int64_t)map * nalm + base
-                                              : part + ((int64_t)map * groups + grp) * nalm + base;
 
+constexpr int kVals = 2 * kChunk;            // (l, re/im) values per chunk
+constexpr int kAnaWaves = kAnaThreads / 64;
+// LDS of the analysis tiles: wave-private transpose rows, the per-wave chunk
+// sums awaiting a cross-wave flush, and the waves' first starts.
+struct AnaLds {
+    double tbuf[kAnaWaves][kVals][kTRow];
+    double ring[2][kFlush][kAnaWaves][kVals];
+    int wstart[kAnaWaves];
+};
+static_assert(kFlush * kVals <= kAnaThreads, "one thread per flushed value");
+
+// The slot operands of one lane: x, start, start state and the pair sums
+// D+ = north + south (even l+m) and D- = north - south (odd) of Delta_m.
+template <int T>
+struct AnaSlots {
     double x[T], q1[T], q2[T], pr[T], pi[T], mr[T], mi[T];
     int ls[T];
     double2 st[T];
-    int lo = lmax + 1, hi = m;
+    int lo, hi;  // wave-uniform: earliest start, latest start (m if none)
+
+    __device__ __forceinline__ void load(const AnaArgs &A, int m, const double2 *__restrict__ d, int slot0) {
+        const int lmax = A.lmax, nslots = A.nslots;
+        lo = lmax + 1;
+        hi = m;
 #pragma unroll
-    for (int t = 0; t < T; ++t) {
-        const int slot = ((grp * kWaves + wave) * 64 + lane) * T + t;
-        const bool act = slot < nslots;
-        x[t] = act ? sx[slot] : 0.0;
-        ls[t] = act ? lstart[(int64_t)m * nslots + slot] : lmax + 1;
-        st[t] = act ? state[(int64_t)m * nslots + slot] : make_double2(0.0, 0.0);
-        double2 dn = make_double2(0.0, 0.0), ds = make_double2(0.0, 0.0);
-        if (ls[t] <= lmax) {
-            dn = d[(int64_t)rn[slot] * (mmax + 1) + m];
-            const int r2 = rsouth[slot];
-            if (r2 >= 0) ds = d[(int64_t)r2 * (mmax + 1) + m];
+        for (int t = 0; t < T; ++t) {
+            const int slot = slot0 + t;
+            const bool act = slot < nslots;
+            x[t] = act ? A.sx[slot] : 0.0;
+            ls[t] = act ? A.lstart[(int64_t)m * nslots + slot] : lmax + 1;
+            st[t] = act ? A.state[(int64_t)m * nslots + slot] : make_double2(0.0, 0.0);
+            double2 dn = make_double2(0.0, 0.0), ds = make_double2(0.0, 0.0);
+            if (ls[t] <= lmax) {
+                dn = d[(int64_t)A.rn[slot] * (A.mmax + 1) + m];
+                const int r2 = A.rsouth[slot];
+                if (r2 >= 0) ds = d[(int64_t)r2 * (A.mmax + 1) + m];
+            }
+            // even (l+m): north + south; odd: north - south
+            pr[t] = dn.x + ds.x;
+            pi[t] = dn.y + ds.y;
+            mr[t] = dn.x - ds.x;
+            mi[t] = dn.y - ds.y;
+            q1[t] = q2[t] = 0.0;  // a slot carries zeros until it starts
+            lo = min(lo, ls[t]);
+            if (ls[t] <= lmax) hi = max(hi, ls[t]);
         }
-        // even (l+m): north + south; odd: north - south
-        pr[t] = dn.x + ds.x;
-        pi[t] = dn.y + ds.y;
-        mr[t] = dn.x - ds.x;
-        mi[t] = dn.y - ds.y;
-        q1[t] = q2[t] = 0.0;  // a slot carries zeros until it starts
-        lo = min(lo, ls[t]);
-        if (ls[t] <= lmax) hi = max(hi, ls[t]);
+        lo = wave_min(lo);
+        hi = wave_max(hi);
     }
-    lo = wave_min(lo);
-    hi = wave_max(hi);
-    if (lane == 0) wstart[wave] = lo;
+    __device__ __forceinline__ void inject(int l0) {
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+            const bool now = (ls[t] == l0);
+            q2[t] = now ? st[t].x : q2[t];
+            q1[t] = now ? st[t].y : q1[t];
+        }
+    }
+};
+
+// Wave sum of one chunk: each lane writes its 16 values as one column of the
+// wave's rows; lane (j = lane/4, q = lane%4) adds lanes 16q..16q+15 of row j,
+// and the quad of lanes 4j..4j+3 combines by DPP.  Returns the sum of value
+// j in lanes with q == 0 (j = 2i + part: l = l0 + i, part 0 re / 1 im).
+__device__ __forceinline__ double wave_sum16(double (*tb)[kTRow], const double (&accr)[kChunk],
+                                             const double (&acci)[kChunk]) {
+    const int lane = threadIdx.x & 63;
+    const int lane_w = (lane >> 4) * kQStride + (lane & 15);  // this lane's column
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i) {
+        tb[2 * i][lane_w] = accr[i];
+        tb[2 * i + 1][lane_w] = acci[i];
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int j = lane >> 2, q = lane & 3;
+    const double *row = &tb[j][q * kQStride];
+    double v = row[0];
+#pragma unroll
+    for (int k = 1; k < 16; ++k) v += row[k];
+    v = quad_sum(v);
+    __builtin_amdgcn_wave_barrier();
+    return v;
+}
+
+// Analysis of one m of one map by a workgroup of 4 waves: wave w of group g
+// owns slots ((g*4 + w) * 64 + lane) * T + t.  Per chunk of kChunk l values
+// each lane sums its T slots; the wave sums its 64 lanes through its own LDS
+// rows (no barrier); every kFlush chunks the 4 wave sums are added in wave
+// order after one barrier.  The workgroup starts at the earliest start of
+// its slots (a_lm before it get no term); a wave adds zeros until its own
+// first start.  With one group the finished a_lm (times c_lm) is written;
+// otherwise the group's partial goes to part[(map * groups + group) * nalm +
+// idx] for k_ana_combine.  Every thread of the workgroup must call it.
+template <int T>
+__device__ __forceinline__ void ana_group(const AnaArgs &A, int m, int grp, int map, int groups, AnaLds &L) {
+    const int lmax = A.lmax;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const double *__restrict__ al = A.alpha + base;
+    const double2 *__restrict__ d = A.delta + (int64_t)map * A.nrings * (A.mmax + 1);
+    double2 *__restrict__ dst = (groups == 1) ? A.alm + (int64_t)map * A.nalm + base
+                                              : A.part + ((int64_t)map * groups + grp) * A.nalm + base;
+    AnaSlots<T> S;
+    S.load(A, m, d, ((grp * kAnaWaves + wave) * 64 + lane) * T);
+    const int lo = S.lo, hi = S.hi;
+    if (lane == 0) L.wstart[wave] = lo;
     __syncthreads();
     int l0s = lmax + 1;
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) l0s = min(l0s, wstart[w]);
+    for (int w = 0; w < kAnaWaves; ++w) l0s = min(l0s, L.wstart[w]);
     l0s = __builtin_amdgcn_readfirstlane(l0s);  // the same in every lane
 
     for (int l = m + tid; l < l0s; l += kAnaThreads) dst[l] = make_double2(0.0, 0.0);
@@ -433,7 +598,7 @@ __global__ __launch_bounds__(kAnaThreads) void k_leg_ana(int lmax, int mmax, int
         if (tid < nchunks * kVals) {
             double v = 0.0;
 #pragma unroll
-            for (int w = 0; w < kWaves; ++w) v += ring[par][fk][w][fj];
+            for (int w = 0; w < kAnaWaves; ++w) v += L.ring[par][fk][w][fj];
             const int l = lbase + fk * kChunk + (fj >> 1);
             if (l <= lmax) {
                 if (groups == 1) v = (m == 0 && (fj & 1)) ? 0.0 : v * cval;
@@ -443,7 +608,7 @@ __global__ __launch_bounds__(kAnaThreads) void k_leg_ana(int lmax, int mmax, int
     };
     auto cfac_for = [&](int lbase) {
         const int l = lbase + fk * kChunk + (fj >> 1);
-        return (groups == 1 && tid < kFlush * kVals && l <= lmax) ? cfac[base + l] : 0.0;
+        return (groups == 1 && tid < kFlush * kVals && l <= lmax) ? A.cfac[base + l] : 0.0;
     };
 
     // alpha is read in whole chunks: entries past lmax belong to the next
@@ -457,7 +622,6 @@ __global__ __launch_bounds__(kAnaThreads) void k_leg_ana(int lmax, int mmax, int
         av[i] = al[l0s + i];
         avn[i] = al[l0s + kChunk + i];
     }
-    const int lane_w = (lane >> 4) * kQStride + (lane & 15);  // this lane's column in tbuf
     int par = 0, kc = 0, lbase = l0s;
     double cval = cfac_for(lbase);
 
@@ -481,32 +645,9 @@ __global__ __launch_bounds__(kAnaThreads) void k_leg_ana(int lmax, int mmax, int
             kc = 0;
         }
     };
-    // wave sum: each lane writes its 16 values as one column of the wave's
-    // rows; lane (j = lane/4, q = lane%4) adds lanes 16q..16q+15 of row j,
-    // and the quad of lanes 4j..4j+3 combines by DPP (lane 4j holds the sum)
-    auto wave_sum = [&](const double (&accr)[kChunk], const double (&acci)[kChunk]) {
-#pragma unroll
-        for (int i = 0; i < kChunk; ++i) {
-            tbuf[wave][2 * i][lane_w] = accr[i];
-            tbuf[wave][2 * i + 1][lane_w] = acci[i];
-        }
-        __builtin_amdgcn_wave_barrier();
-        const int j = lane >> 2, q = lane & 3;
-        const double *row = &tbuf[wave][j][q * kQStride];
-        double v = row[0];
-#pragma unroll
-        for (int k = 1; k < 16; ++k) v += row[k];
-        v = quad_sum(v);
-        if (q == 0) ring[par][kc][wave][j] = v;
-        __builtin_amdgcn_wave_barrier();
-    };
-    auto inject = [&](int l0) {
-#pragma unroll
-        for (int t = 0; t < T; ++t) {
-            const bool now = (ls[t] == l0);
-            q2[t] = now ? st[t].x : q2[t];
-            q1[t] = now ? st[t].y : q1[t];
-        }
+    auto to_ring = [&](const double (&accr)[kChunk], const double (&acci)[kChunk]) {
+        const double v = wave_sum16(L.tbuf[wave], accr, acci);
+        if ((lane & 3) == 0) L.ring[par][kc][wave][lane >> 2] = v;
     };
 
     // Three phases, each a loop without branches between chunk kinds, so the
@@ -515,26 +656,86 @@ __global__ __launch_bounds__(kAnaThreads) void k_leg_ana(int lmax, int mmax, int
     int l0 = l0s;
 #pragma unroll 1
     for (; l0 < lo && l0 <= lmax; l0 += kChunk) {
-        if ((lane & 3) == 0) ring[par][kc][wave][lane >> 2] = 0.0;
+        if ((lane & 3) == 0) L.ring[par][kc][wave][lane >> 2] = 0.0;
         next_chunk(l0);
     }
     // (2) whole chunks; slots join at their tabulated start
 #pragma unroll 1
     for (; l0 + kChunk - 1 <= lmax; l0 += kChunk) {
-        if (l0 <= hi) inject(l0);
+        if (l0 <= hi) S.inject(l0);
         double accr[kChunk], acci[kChunk];
-        ana_chunk<T, true>(l0, lmax, av, x, q1, q2, pr, pi, mr, mi, accr, acci);
-        wave_sum(accr, acci);
+        ana_chunk<T, true>(l0, lmax, av, S.x, S.q1, S.q2, S.pr, S.pi, S.mr, S.mi, accr, acci);
+        to_ring(accr, acci);
         next_chunk(l0);
     }
     // (3) the ragged last chunk
     if (l0 <= lmax) {
-        if (l0 <= hi) inject(l0);
+        if (l0 <= hi) S.inject(l0);
         double accr[kChunk], acci[kChunk];
-        ana_chunk<T, false>(l0, lmax, av, x, q1, q2, pr, pi, mr, mi, accr, acci);
-        wave_sum(accr, acci);
+        ana_chunk<T, false>(l0, lmax, av, S.x, S.q1, S.q2, S.pr, S.pi, S.mr, S.mi, accr, acci);
+        to_ring(accr, acci);
         next_chunk(l0);
     }
+}
+
+// Analysis of one m of one map by one wave holding every slot (nslots <=
+// 64 T; lane i owns slots i*T + t): per chunk the wave's sum goes straight
+// to a_lm (times c_lm), with no step across waves, so the four waves of a
+// workgroup may each work on their own m.  tb: the wave's transpose rows.
+template <int T>
+__device__ __forceinline__ void ana_wave(const AnaArgs &A, int m, int map, double (*tb)[kTRow]) {
+    const int lmax = A.lmax;
+    const int lane = threadIdx.x & 63;
+    const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
+    const double *__restrict__ al = A.alpha + base;
+    const double2 *__restrict__ d = A.delta + (int64_t)map * A.nrings * (A.mmax + 1);
+    double2 *__restrict__ dst = A.alm + (int64_t)map * A.nalm + base;
+    AnaSlots<T> S;
+    S.load(A, m, d, lane * T);
+    const int lo = S.lo, hi = S.hi;
+    for (int l = m + lane; l < lo && l <= lmax; l += 64) dst[l] = make_double2(0.0, 0.0);
+    if (lo > lmax) return;
+    double av[kChunk], avn[kChunk];
+#pragma unroll
+    for (int i = 0; i < kChunk; ++i) {
+        av[i] = al[lo + i];
+        avn[i] = al[lo + kChunk + i];
+    }
+    const int j = lane >> 2;
+    auto out = [&](int l0, const double (&accr)[kChunk], const double (&acci)[kChunk]) {
+        const double v = wave_sum16(tb, accr, acci);
+        const int l = l0 + (j >> 1);
+        if ((lane & 3) == 0 && l <= lmax)
+            reinterpret_cast<double *>(dst + l)[j & 1] = (m == 0 && (j & 1)) ? 0.0 : v * A.cfac[base + l];
+#pragma unroll
+        for (int i = 0; i < kChunk; ++i) {
+            av[i] = avn[i];
+            avn[i] = al[l0 + 2 * kChunk + i];
+        }
+    };
+    int l0 = lo;
+#pragma unroll 1
+    for (; l0 + kChunk - 1 <= lmax; l0 += kChunk) {
+        if (l0 <= hi) S.inject(l0);
+        double accr[kChunk], acci[kChunk];
+        ana_chunk<T, true>(l0, lmax, av, S.x, S.q1, S.q2, S.pr, S.pi, S.mr, S.mi, accr, acci);
+        out(l0, accr, acci);
+    }
+    if (l0 <= lmax) {
+        if (l0 <= hi) S.inject(l0);
+        double accr[kChunk], acci[kChunk];
+        ana_chunk<T, false>(l0, lmax, av, S.x, S.q1, S.q2, S.pr, S.pi, S.mr, S.mi, accr, acci);
+        out(l0, accr, acci);
+    }
+}
+
+// Analysis kernel: grid.x = (m, slot group) in the XCD-aware order, grid.y = map.
+template <int T>
+__global__ __launch_bounds__(kAnaThreads) void k_leg_ana(AnaArgs A, int groups) {
+    __shared__ AnaLds L;
+    const MPart mp = xcd_m_part(groups);
+    if (mp.m > A.mmax) return;  // padding of the m range (whole workgroup, before any barrier)
+    ana_group<T>(A, mp.m, mp.part, (int)blockIdx.y, groups, L);
 }
 
 // a_lm = c_lm * sum_{g < groups} part[map][g][idx], groups summed in order.
@@ -558,7 +759,132 @@ __global__ __launch_bounds__(kBlock) void k_ana_combine(int64_t nalm, int lmax, 
     }
 }
 
+// ---------------------------------------------------------------- uneven batches
+// The Legendre stage of a whole batch of requests (any lmax and geometry, both
+// directions) in one persistent launch.  Each workgroup takes the next item of
+// a device work queue (one atomic add by one thread, broadcast through LDS)
+// until the queue is empty, then exits; the host lists the items longest
+// first, so that the cheap ones (high m, small requests) fill the end of the
+// run on every CU.  Every item's work is that of the ordinary kernels, so
+// which workgroup takes it does not change a result.
+__global__ __launch_bounds__(kBlock, 3) void k_leg_batch(const BatchReq *__restrict__ reqs,
+                                                       const BatchItem *__restrict__ items, int nitems,
+                                                       int *__restrict__ head) {
+    __shared__ AnaLds L;
+    __shared__ int s_idx;
+    const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    for (;;) {
+        if (threadIdx.x == 0) s_idx = atomicAdd(head, 1);
+        __syncthreads();
+        const int idx = __builtin_amdgcn_readfirstlane(s_idx);
+        __syncthreads();  // every thread has read s_idx before it is written again
+        if (idx >= nitems) return;  // the whole workgroup: the queue is empty
+        const BatchItem it = items[idx];
+        const BatchReq &R = reqs[it.req];
+        const int T = R.T;
+        if (R.kind == 0) {
+            const int u = it.u0 + wave;
+            if (u < R.nunits) {
+                const int m = __builtin_amdgcn_readfirstlane(u / R.tiles);
+                const int slot0 = (u - m * R.tiles) * 64 * T;
+                if (T == 1) syn_tile<1>(R.syn, m, 0, slot0, lane);
+                else if (T == 2) syn_tile<2>(R.syn, m, 0, slot0, lane);
+                else syn_tile<4>(R.syn, m, 0, slot0, lane);
+            }
+        } else if (R.shape == 0) {
+            const int m = it.u0 + wave;
+            if (m <= R.ana.mmax) {
+                if (T == 1) ana_wave<1>(R.ana, m, 0, L.tbuf[wave]);
+                else if (T == 2) ana_wave<2>(R.ana, m, 0, L.tbuf[wave]);
+                else ana_wave<4>(R.ana, m, 0, L.tbuf[wave]);
+            }
+        } else {
+            const int m = it.u0 / R.groups, grp = it.u0 - m * R.groups;
+            if (T == 1) ana_group<1>(R.ana, m, grp, 0, R.groups, L);
+            else if (T == 2) ana_group<2>(R.ana, m, grp, 0, R.groups, L);
+            else ana_group<4>(R.ana, m, grp, 0, R.groups, L);
+        }
+        __syncthreads();  // the item's LDS use is over before the next one starts
+    }
+}
+
+__global__ void k_batch_reset(int *head) { *head = 0; }
+
+// c-scaled a_lm of every synthesis request of a batch: grid.y = request (of
+// the list), grid.x strides over its a_lm.
+__global__ __launch_bounds__(kBlock) void k_prescale_batch(const BatchReq *__restrict__ reqs,
+                                                            const int32_t *__restrict__ list) {
+    const BatchReq &R = reqs[list[blockIdx.y]];
+    const int64_t nalm = R.syn.nalm;
+    const int lmax = R.syn.lmax;
+    const double *__restrict__ cfac = R.ana.cfac;
+    double2 *out = const_cast<double2 *>(R.syn.ap);
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < nalm; k += (int64_t)gridDim.x * kBlock) {
+        const double c = cfac[k];
+        const double2 a = R.alm_in[k];
+        out[k] = make_double2(a.x * c, k <= lmax ? 0.0 : a.y * c);  // Im a_l0 is ignored
+    }
+}
+
+// a_lm = c_lm * sum of the group partials (groups in order) for every
+// analysis request of the list that has several groups.
+__global__ __launch_bounds__(kBlock) void k_combine_batch(const BatchReq *__restrict__ reqs,
+                                                           const int32_t *__restrict__ list) {
+    const BatchReq &R = reqs[list[blockIdx.y]];
+    const int64_t nalm = R.ana.nalm;
+    const int lmax = R.ana.lmax, groups = R.groups;
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < nalm; k += (int64_t)gridDim.x * kBlock) {
+        double sr = 0.0, si = 0.0;
+        for (int g = 0; g < groups; ++g) {
+            const double2 v = R.ana.part[(int64_t)g * nalm + k];
+            sr += v.x;
+            si += v.y;
+        }
+        const double c = R.ana.cfac[k];
+        R.ana.alm[k] = make_double2(sr * c, k <= lmax ? 0.0 : si * c);
+    }
+}
+
 }  // namespace
+
+int leg_batch_grid(int *grid) {
+    int dev = 0, per_cu = 0;
+    SHT_HIP(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    SHT_HIP(hipGetDeviceProperties(&prop, dev));
+    SHT_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_leg_batch, kBlock, 0));
+    *grid = std::max(1, per_cu) * prop.multiProcessorCount;
+    return SHT_OK;
+}
+
+int launch_leg_batch(const BatchReq *reqs, const BatchItem *items, int nitems, int *head, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, st, head);
+    SHT_HIP(hipGetLastError());
+    if (nitems <= 0) return SHT_OK;
+    hipLaunchKernelGGL(k_leg_batch, dim3((unsigned)std::min(grid, nitems)), dim3(kBlock), 0, st, reqs, items, nitems,
+                       head);
+    SHT_HIP(hipGetLastError());
+    return SHT_OK;
+}
+
+int launch_prescale_batch(const BatchReq *reqs, const int32_t *syn_reqs, int nsyn, int max_chunks, hipStream_t st) {
+    if (nsyn <= 0) return SHT_OK;
+    if (nsyn > 65535) return SHT_EUNSUPPORTED;
+    hipLaunchKernelGGL(k_prescale_batch, dim3((unsigned)std::max(1, std::min(max_chunks, 4096)), (unsigned)nsyn),
+                       dim3(kBlock), 0, st, reqs, syn_reqs);
+    SHT_HIP(hipGetLastError());
+    return SHT_OK;
+}
+
+int launch_combine_batch(const BatchReq *reqs, const int32_t *comb_reqs, int ncomb, int max_chunks, hipStream_t st) {
+    if (ncomb <= 0) return SHT_OK;
+    if (ncomb > 65535) return SHT_EUNSUPPORTED;
+    hipLaunchKernelGGL(k_combine_batch, dim3((unsigned)std::max(1, std::min(max_chunks, 4096)), (unsigned)ncomb),
+                       dim3(kBlock), 0, st, reqs, comb_reqs);
+    SHT_HIP(hipGetLastError());
+    return SHT_OK;
+}
 
 int launch_leg_start(const CoefTables &c, const GeomPlan &p, int32_t *lstart, void *state, hipStream_t st) {
     const int tiles = (p.nslots + kBlock - 1) / kBlock;
@@ -580,15 +906,31 @@ int launch_prescale(const CoefTables &c, const void *alm, void *aprime, int nmap
 
 constexpr int kSynSlotsPerLane = 4;
 
+template <int M>
+static int launch_syn_mm(const SynArgs &A, int nslots, int mmax, int nmaps, hipStream_t st) {
+    const int tiles = (nslots + kBlock - 1) / kBlock;  // one slot per lane
+    const int64_t gx = (int64_t)tiles * padded_m(mmax);
+    if (!grid_ok(gx)) return SHT_EUNSUPPORTED;
+    hipLaunchKernelGGL((k_leg_syn_mm<1, M>), dim3((unsigned)gx, (unsigned)((nmaps + M - 1) / M)), dim3(kBlock), 0, st,
+                       A, tiles, nmaps);
+    SHT_HIP(hipGetLastError());
+    return SHT_OK;
+}
+
 int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *aprime, void *delta,
                    int nmaps, hipStream_t st) {
+    const SynArgs A{c.lmax, c.mmax, p.nslots, p.nrings, c.nalm, static_cast<const double2 *>(aprime), c.alpha,
+                    s.lstart, s.state, p.slot_x, p.slot_north, p.slot_south, static_cast<double2 *>(delta)};
+    if (nmaps > 65535) return SHT_EUNSUPPORTED;
+    // several maps share each recurrence: 8 (4, 2) maps per workgroup, one slot per lane
+    if (nmaps >= 8) return launch_syn_mm<8>(A, p.nslots, c.mmax, nmaps, st);
+    if (nmaps >= 3) return launch_syn_mm<4>(A, p.nslots, c.mmax, nmaps, st);
+    if (nmaps == 2) return launch_syn_mm<2>(A, p.nslots, c.mmax, nmaps, st);
     constexpr int T = kSynSlotsPerLane;
     const int tiles = (p.nslots + kBlock * T - 1) / (kBlock * T);
     const int64_t gx = (int64_t)tiles * padded_m(c.mmax);
-    if (!grid_ok(gx) || nmaps > 65535) return SHT_EUNSUPPORTED;
-    hipLaunchKernelGGL(k_leg_syn<T>, dim3((unsigned)gx, (unsigned)nmaps), dim3(kBlock), 0, st, c.lmax, c.mmax,
-                       p.nslots, tiles, p.nrings, c.nalm, static_cast<const double2 *>(aprime), c.alpha, s.lstart,
-                       s.state, p.slot_x, p.slot_north, p.slot_south, static_cast<double2 *>(delta));
+    if (!grid_ok(gx)) return SHT_EUNSUPPORTED;
+    hipLaunchKernelGGL(k_leg_syn<T>, dim3((unsigned)gx, (unsigned)nmaps), dim3(kBlock), 0, st, A, tiles);
     SHT_HIP(hipGetLastError());
     return SHT_OK;
 }
@@ -596,10 +938,11 @@ int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const StartTable &s, 
 template <int T>
 static void launch_ana_t(const CoefTables &c, const GeomPlan &p, const StartTable &s, int groups,
                          const void *delta, void *alm, void *part, int nmaps, hipStream_t st) {
+    const AnaArgs A{c.lmax, c.mmax, p.nslots, p.nrings, c.nalm, static_cast<const double2 *>(delta), c.alpha,
+                    c.cfac, s.lstart, s.state, p.slot_x, p.slot_north, p.slot_south, static_cast<double2 *>(alm),
+                    static_cast<double2 *>(part)};
     hipLaunchKernelGGL(k_leg_ana<T>, dim3((unsigned)(padded_m(c.mmax) * groups), (unsigned)nmaps), dim3(kAnaThreads), 0,
-                       st, c.lmax, c.mmax, p.nslots, p.nrings, c.nalm, groups, static_cast<const double2 *>(delta),
-                       c.alpha, c.cfac, s.lstart, s.state, p.slot_x, p.slot_north, p.slot_south,
-                       static_cast<double2 *>(alm), static_cast<double2 *>(part));
+                       st, A, groups);
 }
 
 int launch_leg_ana(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *delta, void *alm,

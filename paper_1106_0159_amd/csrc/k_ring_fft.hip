@@ -357,14 +357,28 @@ __device__ __forceinline__ void transform(double2 *buf, const FftDesc *__restric
     fft_forward<MAXL, NT>(buf, d, tw);
 }
 
+// Bluestein chirp b_t = e^{i pi t^2 / n}, t < n, computed in place: the
+// angle's numerator t^2 mod 2n is an exact integer, taken into (-n, n] so
+// that the argument pi q / n of the reduced-range sin/cos lies in (-pi, pi].
+// (No table: the chirp of every ring length would otherwise be read from
+// memory per job.)
+__device__ __forceinline__ double2 chirp_at(int n, int t) {
+    const int n2 = 2 * n;
+    int q = (int)(((int64_t)t * t) % n2);
+    if (q > n) q -= n2;
+    double sn, cs;
+    sincos_small(3.141592653589793 * (double)q / (double)n, sn, cs);
+    return make_double2(cs, sn);
+}
+
 __device__ __forceinline__ double2 result_at(const double2 *buf, const FftDesc *__restrict__ d, int k) {
     if (!d->bluestein) return buf[pd(k)];
     // X_k = conj(b_k) * conj(y_k), y = conj(second transform)
-    return conj2(cmul(d->chirp[k], buf[pd(k)]));
+    return conj2(cmul(chirp_at(d->n, k), buf[pd(k)]));
 }
 
 __device__ __forceinline__ double2 input_point(double2 v, const FftDesc *__restrict__ d, int t) {
-    return d->bluestein ? cmul(v, conj2(d->chirp[t])) : v;
+    return d->bluestein ? cmul(v, conj2(chirp_at(d->n, t))) : v;
 }
 
 // ---------------------------------------------------------------- ring jobs
@@ -638,17 +652,21 @@ int allow_max_lds() {
     return SHT_OK;
 }
 
-bool g_attr_set = false;
-
 // every class may use up to the whole LDS (the 4096 class needs more than the
-// 64 KB default: twiddle tables plus 4096 points)
+// 64 KB default: twiddle tables plus 4096 points); set once per device
 int set_lds_attr() {
-    if (g_attr_set) return SHT_OK;
+    static std::mutex mu;
+    static uint64_t done = 0;  // bit d: device d
+    int dev = 0;
+    SHT_HIP(hipGetDevice(&dev));
+    const uint64_t bit = dev < 64 ? (uint64_t)1 << dev : 0;
+    std::lock_guard<std::mutex> lk(mu);
+    if (bit && (done & bit)) return SHT_OK;
     int rc;
     if ((rc = allow_max_lds<1024>()) || (rc = allow_max_lds<2048>()) || (rc = allow_max_lds<4096>()) ||
         (rc = allow_max_lds<8192>()))
         return rc;
-    g_attr_set = true;
+    done |= bit;
     return SHT_OK;
 }
 
@@ -704,15 +722,24 @@ static bool grid_fits(const GeomPlan &p, int nmaps, int map_minor) {
 
 // The length classes are independent: they run concurrently, the largest on
 // the caller's stream and the others on side streams (fork_join).
+// Runs launch(i, stream) for the n classes: concurrently through fork_join,
+// or one after another on st.
+static int each_class(hipStream_t st, int n, bool fork, const std::function<int(int, hipStream_t)> &launch) {
+    if (fork) return fork_join(st, n, launch);
+    int rc = SHT_OK;
+    for (int i = 0; i < n && rc == SHT_OK; ++i) rc = launch(i, st);
+    return rc;
+}
+
 int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, DeltaLayout dl, double *map, int nmaps,
-                   hipStream_t st) {
+                   hipStream_t st, bool fork) {
     if (nmaps > 65535 || !grid_fits(p, nmaps, dl.map_minor)) return SHT_EUNSUPPORTED;
     int rc = set_lds_attr();
     if (rc) return rc;
     int cls[kFftClasses], n = 0;
     for (int c = kFftClasses - 1; c >= 0; --c)
         if (p.class_count[c]) cls[n++] = c;
-    return fork_join(st, n, [&](int i, hipStream_t s) {
+    return each_class(st, n, fork, [&](int i, hipStream_t s) {
         switch (cls[i]) {
             case 0: launch_syn_class<1024>(p, 0, mmax, delta, dl, map, nmaps, s); break;
             case 1: launch_syn_class<2048>(p, 1, mmax, delta, dl, map, nmaps, s); break;
@@ -725,7 +752,7 @@ int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, DeltaLayout d
 }
 
 int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, DeltaLayout dl, int nmaps,
-                   hipStream_t st) {
+                   hipStream_t st, bool fork) {
     if (nmaps > 65535 || !grid_fits(p, nmaps, dl.map_minor)) return SHT_EUNSUPPORTED;
     if (!p.weight) return SHT_EINVAL;
     int rc = set_lds_attr();
@@ -733,7 +760,7 @@ int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, 
     int cls[kFftClasses], n = 0;
     for (int c = kFftClasses - 1; c >= 0; --c)
         if (p.class_count[c]) cls[n++] = c;
-    return fork_join(st, n, [&](int i, hipStream_t s) {
+    return each_class(st, n, fork, [&](int i, hipStream_t s) {
         switch (cls[i]) {
             case 0: launch_ana_class<1024>(p, 0, mmax, map, delta, dl, nmaps, s); break;
             case 1: launch_ana_class<2048>(p, 1, mmax, map, delta, dl, nmaps, s); break;

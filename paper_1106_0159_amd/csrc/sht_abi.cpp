@@ -52,6 +52,13 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
 
 hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
 
+// After a call has enqueued its kernels (status rc): notes the stream's use
+// of the tables, so that an eviction waits for this work before freeing them.
+int fenced(int rc, hipStream_t st, std::initializer_list<const Fenced *> tables) {
+    const int rf = note_uses(st, tables);
+    return rc ? rc : rf;
+}
+
 // Delta layout of a stage call; the FP64 Legendre kernels take ring-major only
 DeltaLayout stage_layout(const HostGeom &h, int mmax, int nmaps, uint32_t flags) {
     return delta_layout(h.nrings, mmax, nmaps, (flags & SHT_DELTA_MAP_MINOR) != 0);
@@ -68,6 +75,35 @@ int check_common(int lmax, int mmax, const sht_geom *g, int nmaps, uint32_t flag
 }
 
 }  // namespace
+
+namespace sht {
+
+size_t ws_aux_offset(int nrings, int mmax, int nmaps) { return round256(delta_bytes(nrings, mmax, nmaps)); }
+
+int check_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, const double *map, int nmaps,
+                  uint32_t flags, HostGeom *h, size_t *ws_bytes_needed) {
+    int rc = check_common(lmax, mmax, g, nmaps, flags, false, h);
+    if (rc) return rc;
+    if (!alm || !map || !aligned(alm, 16) || !aligned(map, 8)) return SHT_EINVAL;
+    const size_t ab = alm_bytes(lmax, mmax, nmaps), mb = (size_t)h->npix * 8u * nmaps;
+    if (overlap(alm, ab, map, mb)) return SHT_EINVAL;
+    *ws_bytes_needed = ws_need(lmax, mmax, *h, nmaps, flags);
+    return SHT_OK;
+}
+
+int enqueue_alm2map(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm, void *aprime,
+                    void *delta, DeltaLayout dl, double *map, int nmaps, uint32_t flags, hipStream_t st, bool fork) {
+    int rc;
+    if (flags & SHT_MIXED) {
+        if ((rc = launch_leg_syn_mx(c, p, s, alm, aprime, delta, dl, nmaps, st))) return rc;
+    } else {
+        if ((rc = launch_prescale(c, alm, aprime, nmaps, st))) return rc;
+        if ((rc = launch_leg_syn(c, p, s, aprime, delta, nmaps, st))) return rc;
+    }
+    return launch_fft_syn(p, c.mmax, delta, dl, map, nmaps, st, fork);
+}
+
+}  // namespace sht
 
 extern "C" {
 
@@ -97,10 +133,11 @@ int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *
         (rc = get_start(*c, p, as_stream(stream), &s)))
         return rc;
     if (flags & SHT_MIXED)
-        return launch_leg_syn_mx(*c, *p, *s, alm, workspace, delta, stage_layout(h, mmax, nmaps, flags), nmaps,
-                                 as_stream(stream));
-    if ((rc = launch_prescale(*c, alm, workspace, nmaps, as_stream(stream)))) return rc;
-    return launch_leg_syn(*c, *p, *s, workspace, delta, nmaps, as_stream(stream));
+        rc = launch_leg_syn_mx(*c, *p, *s, alm, workspace, delta, stage_layout(h, mmax, nmaps, flags), nmaps,
+                               as_stream(stream));
+    else if (!(rc = launch_prescale(*c, alm, workspace, nmaps, as_stream(stream))))
+        rc = launch_leg_syn(*c, *p, *s, workspace, delta, nmaps, as_stream(stream));
+    return fenced(rc, as_stream(stream), {c.get(), p.get(), s.get()});
 }
 
 int sht_delta2map(int mmax, const sht_geom *g, const void *delta, double *map, int nmaps,
@@ -113,7 +150,8 @@ int sht_delta2map(int mmax, const sht_geom *g, const void *delta, double *map, i
         return SHT_EINVAL;
     GeomRef p;
     if ((rc = get_geom(h, mmax, &p))) return rc;
-    return launch_fft_syn(*p, mmax, delta, stage_layout(h, mmax, nmaps, flags), map, nmaps, as_stream(stream));
+    rc = launch_fft_syn(*p, mmax, delta, stage_layout(h, mmax, nmaps, flags), map, nmaps, as_stream(stream));
+    return fenced(rc, as_stream(stream), {p.get()});
 }
 
 int sht_map2delta(int mmax, const sht_geom *g, const double *map, void *delta, int nmaps,
@@ -126,7 +164,8 @@ int sht_map2delta(int mmax, const sht_geom *g, const double *map, void *delta, i
         return SHT_EINVAL;
     GeomRef p;
     if ((rc = get_geom(h, mmax, &p))) return rc;
-    return launch_fft_ana(*p, mmax, map, delta, stage_layout(h, mmax, nmaps, flags), nmaps, as_stream(stream));
+    rc = launch_fft_ana(*p, mmax, map, delta, stage_layout(h, mmax, nmaps, flags), nmaps, as_stream(stream));
+    return fenced(rc, as_stream(stream), {p.get()});
 }
 
 int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void *alm, int nmaps,
@@ -149,24 +188,23 @@ int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void
         (rc = get_start(*c, p, as_stream(stream), &s)))
         return rc;
     if (flags & SHT_MIXED)
-        return launch_leg_ana_mx(*c, *p, *s, delta, stage_layout(h, mmax, nmaps, flags), alm, nmaps, workspace,
-                                 as_stream(stream));
-    return launch_leg_ana(*c, *p, *s, delta, alm, nmaps, workspace, as_stream(stream));
+        rc = launch_leg_ana_mx(*c, *p, *s, delta, stage_layout(h, mmax, nmaps, flags), alm, nmaps, workspace,
+                               as_stream(stream));
+    else
+        rc = launch_leg_ana(*c, *p, *s, delta, alm, nmaps, workspace, as_stream(stream));
+    return fenced(rc, as_stream(stream), {c.get(), p.get(), s.get()});
 }
 
 int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *map, int nmaps,
                 void *workspace, size_t ws_bytes, uint32_t flags, void *stream) {
     HostGeom h;
-    int rc = check_common(lmax, mmax, g, nmaps, flags, false, &h);
+    size_t need = 0;
+    int rc = check_alm2map(lmax, mmax, g, alm, map, nmaps, flags, &h, &need);
     if (rc) return rc;
-    if (!alm || !map || !aligned(alm, 16) || !aligned(map, 8)) return SHT_EINVAL;
     const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
     const size_t mb = (size_t)h.npix * 8u * nmaps;
-    if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps, flags))
-        return SHT_EWORKSPACE;
-    if (overlap(alm, ab, map, mb) || overlap(workspace, ws_bytes, alm, ab) ||
-        overlap(workspace, ws_bytes, map, mb))
-        return SHT_EINVAL;
+    if (!workspace || !aligned(workspace, 16) || ws_bytes < need) return SHT_EWORKSPACE;
+    if (overlap(workspace, ws_bytes, alm, ab) || overlap(workspace, ws_bytes, map, mb)) return SHT_EINVAL;
     hipStream_t st = as_stream(stream);
     CoefRef c;
     GeomRef p;
@@ -175,19 +213,9 @@ int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *
         return rc;
     char *ws = static_cast<char *>(workspace);
     void *delta = ws, *aprime = ws + round256(db);
-    // mixed precision keeps the workspace Delta map-minor from 8 maps on: the
-    // matrix-core kernel then stores whole 128-byte lines per (ring, m), which
-    // saves more than the ring FFT loses on its strided reads.  With fewer
-    // maps there are no whole lines to gain, and the ring-major FFT transforms
-    // a mirror pair per workgroup instead of one ring.
-    const DeltaLayout dl = delta_layout(h.nrings, mmax, nmaps, (flags & SHT_MIXED) != 0 && nmaps >= 8);
-    if (flags & SHT_MIXED) {
-        if ((rc = launch_leg_syn_mx(*c, *p, *s, alm, aprime, delta, dl, nmaps, st))) return rc;
-    } else {
-        if ((rc = launch_prescale(*c, alm, aprime, nmaps, st))) return rc;
-        if ((rc = launch_leg_syn(*c, *p, *s, aprime, delta, nmaps, st))) return rc;
-    }
-    return launch_fft_syn(*p, mmax, delta, dl, map, nmaps, st);
+    const DeltaLayout dl = alm2map_layout(h.nrings, mmax, nmaps, flags);
+    rc = enqueue_alm2map(*c, *p, *s, alm, aprime, delta, dl, map, nmaps, flags, st, true);
+    return fenced(rc, st, {c.get(), p.get(), s.get()});
 }
 
 int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *alm, int nmaps,
@@ -214,14 +242,18 @@ int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *
     // ring-major here also with SHT_MIXED: with map-minor Delta the ring FFT
     // loses about what the analysis kernel gains on its reads
     const DeltaLayout dl = delta_layout(h.nrings, mmax, nmaps, false);
-    if ((rc = launch_fft_ana(*p, mmax, map, delta, dl, nmaps, st))) return rc;
-    if (flags & SHT_MIXED) return launch_leg_ana_mx(*c, *p, *s, delta, dl, alm, nmaps, partials, st);
-    return launch_leg_ana(*c, *p, *s, delta, alm, nmaps, partials, st);
+    if (!(rc = launch_fft_ana(*p, mmax, map, delta, dl, nmaps, st))) {
+        if (flags & SHT_MIXED)
+            rc = launch_leg_ana_mx(*c, *p, *s, delta, dl, alm, nmaps, partials, st);
+        else
+            rc = launch_leg_ana(*c, *p, *s, delta, alm, nmaps, partials, st);
+    }
+    return fenced(rc, st, {c.get(), p.get(), s.get()});
 }
 
 int sht_prepare(int lmax, int mmax, const sht_geom *g, uint32_t flags, void *stream) {
     HostGeom h;
-    int rc = check_common(lmax, mmax, g, 1, flags, false, &h);
+    int rc = check_common(lmax, mmax, g, 1, flags & ~SHT_PIN, false, &h);
     if (rc) return rc;
     CoefRef c;
     GeomRef p;
@@ -229,7 +261,22 @@ int sht_prepare(int lmax, int mmax, const sht_geom *g, uint32_t flags, void *str
     if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p)) ||
         (rc = get_start(*c, p, as_stream(stream), &s)))
         return rc;
-    return SHT_OK;
+    // pinned by key: if another call evicted these entries between the
+    // lookups above and here, they are built again
+    for (int tries = 0; (flags & SHT_PIN) && tries < 4; ++tries) {
+        if ((rc = pin_plan(lmax, mmax, h, +1)) != SHT_ENOPLAN) return rc;
+        if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p)) ||
+            (rc = get_start(*c, p, as_stream(stream), &s)))
+            return rc;
+    }
+    return (flags & SHT_PIN) ? SHT_ENOMEM : SHT_OK;
+}
+
+int sht_unpin(int lmax, int mmax, const sht_geom *g) {
+    HostGeom h;
+    int rc = check_common(lmax, mmax, g, 1, 0, false, &h);
+    if (rc) return rc;
+    return pin_plan(lmax, mmax, h, -1);
 }
 
 int sht_plan_cache_limits(int max_coef_tables, int max_geom_plans) {
@@ -249,6 +296,7 @@ const char *sht_strerror(int code) {
         }
         case SHT_ENOMEM: return "out of memory for plan tables";
         case SHT_EUNSUPPORTED: return "unsupported flag or size";
+        case SHT_ENOPLAN: return "plan tables not resident and pinned (sht_prepare with SHT_PIN first)";
         default: return "unknown status code";
     }
 }

@@ -6,6 +6,8 @@
 
 #include <cstdint>
 #include <functional>
+#include <initializer_list>
+#include <mutex>
 #include <memory>
 #include <string>
 #include <vector>
@@ -53,9 +55,26 @@ constexpr int kMxL = 32;
 constexpr int kAnaMxGroup = 2048;  // ring pairs per workgroup of the mixed analysis
 __host__ __device__ inline int mx_blocks(int lmax, int m) { return (lmax - m + kMxL) / kMxL; }
 
+// Streams that enqueued work reading a cached table.  Each transform call,
+// after enqueuing its kernels, re-records one event per (device, stream)
+// and notes that stream on every table it used; a table that is evicted is
+// freed once the host has waited for that event of each stream that used it
+// (no device-wide synchronisation).
+struct StreamUse {
+    int dev;
+    hipStream_t stream;
+    hipEvent_t ev;
+};
+struct Fenced {
+    mutable std::mutex fence_mu;
+    mutable std::vector<StreamUse *> users;
+    void note_use(StreamUse *u) const;
+    void wait_users() const;  // host waits for the last recorded use on each stream
+};
+
 // Coefficient tables for one (lmax, mmax) on one device.  Packed (l, m)
 // index as for a_lm.  p_lm = cfac_lm * q_lm, q_lm = alpha_lm x q_{l-1,m} - q_{l-2,m}.
-struct CoefTables {
+struct CoefTables : Fenced {
     int dev = -1;             // device holding the tables
     int lmax = -1, mmax = -1;
     int64_t nalm = 0;
@@ -68,7 +87,7 @@ struct CoefTables {
     CoefTables() = default;
     CoefTables(const CoefTables &) = delete;
     CoefTables &operator=(const CoefTables &) = delete;
-    ~CoefTables();            // waits for the device, then frees
+    ~CoefTables();            // waits for the streams that used it, then frees
 };
 
 // One FFT length (device view).  Points of length n are transformed in LDS
@@ -81,8 +100,8 @@ struct FftDesc {
     int bluestein;
     int rad[kMaxRadices];
     const double2 *tw;     // W_L[t] = exp(-2 pi i t / L), t < L
-    const double2 *chirp;  // b_t = exp(i pi t^2 / n), t < n          (Bluestein)
-    const double2 *kern;   // FFT_L of the extended chirp, divided by L (Bluestein)
+    const double2 *kern;   // Bluestein: FFT_L of the extended chirp b_t = exp(i pi t^2 / n)
+                           // (b_{L-t} = b_t, zero between), divided by L
 };
 
 // Where each (m, slot) recurrence starts, for one coefficient set on one
@@ -90,20 +109,21 @@ struct FftDesc {
 // kStartStep steps in which |q_lm| first reaches 2^-100 (lmax + 1 if it never
 // does) and state[m * nslots + slot] = (q_{l-2}, q_{l-1}) before that step.
 // A table built for (lmax', mmax') serves every lmax <= lmax', mmax <= mmax'.
-struct StartTable {
+struct StartTable : Fenced {
     int dev = -1;
     int lmax = -1, mmax = -1;
     int32_t *lstart = nullptr;
     double2 *state = nullptr;
-    uint64_t last_use = 0;
+    uint64_t last_use = 0;    // guarded by the cache lock
+    int pins = 0;             // guarded by the cache lock; pinned tables are never evicted
     StartTable() = default;
     StartTable(const StartTable &) = delete;
     StartTable &operator=(const StartTable &) = delete;
-    ~StartTable();            // waits for the device, then frees
+    ~StartTable();            // waits for the streams that used it, then frees
 };
 
 // Geometry plan for one (ring set) on one device.
-struct GeomPlan {
+struct GeomPlan : Fenced {
     int dev = -1;
     int nrings = 0;
     int nslots = 0;
@@ -131,7 +151,7 @@ struct GeomPlan {
     GeomPlan() = default;
     GeomPlan(const GeomPlan &) = delete;
     GeomPlan &operator=(const GeomPlan &) = delete;
-    ~GeomPlan();                     // waits for the device, then frees
+    ~GeomPlan();                     // waits for the streams that used it, then frees
 };
 
 // Element (map, ring, m) of a Delta array lies at
@@ -149,6 +169,15 @@ inline DeltaLayout delta_layout(int nrings, int mmax, int nmaps, bool map_minor)
     return DeltaLayout{(int64_t)nrings * nm, nm, 1, 0};
 }
 
+// Delta layout of sht_alm2map's workspace: with SHT_MIXED map-minor from 8
+// maps on (the matrix-core kernel then stores whole 128-byte lines per (ring,
+// m), which saves more than the ring FFT loses on its strided reads; with
+// fewer maps there are no whole lines to gain, and the ring-major FFT
+// transforms a mirror pair per workgroup instead of one ring).
+inline DeltaLayout alm2map_layout(int nrings, int mmax, int nmaps, uint32_t flags) {
+    return delta_layout(nrings, mmax, nmaps, (flags & SHT_MIXED) != 0 && nmaps >= 8);
+}
+
 // Validated, normalised copy of the caller's geometry.
 struct HostGeom {
     int nrings = 0;
@@ -164,10 +193,12 @@ int validate_geom(const sht_geom *g, bool need_weight, HostGeom *out);
 int count_slots(const HostGeom &h);
 int validate_sizes(int lmax, int mmax, int nmaps);
 
-// Plan lookup (builds on first use).  Thread safe.  A call holds the
-// references for as long as it uses the tables: an entry evicted from a cache
-// meanwhile is freed only when its last reference goes (after waiting for the
-// device, so kernels already enqueued with it finish first).
+// Plan lookup (builds on first use, outside the cache lock).  Thread safe.
+// A call holds the references for as long as it uses the tables: an entry
+// evicted from a cache meanwhile is freed only when its last reference goes,
+// after the host has waited for the last recorded use of each stream that
+// enqueued work reading it (note_uses), so kernels already enqueued with it
+// finish first.  Pinned entries (pin_plan) are never evicted.
 using CoefRef = std::shared_ptr<const CoefTables>;
 using GeomRef = std::shared_ptr<const GeomPlan>;
 using StartRef = std::shared_ptr<const StartTable>;
@@ -175,6 +206,17 @@ int get_coef(int lmax, int mmax, CoefRef *out);
 int get_geom(const HostGeom &hg, int mmax_for_fft, GeomRef *out);
 // Start table of (c, p), built on the stream st and waited for on first use.
 int get_start(const CoefTables &c, const GeomRef &p, hipStream_t st, StartRef *out);
+// Records the use event of stream st (re-recorded per call) and notes st on
+// the given tables; nothing is recorded while st is capturing a graph (a
+// captured graph needs its plan pinned instead).
+int note_uses(hipStream_t st, std::initializer_list<const Fenced *> tables);
+// Adds delta (+1 or -1) to the pin counts of the resident tables of
+// (lmax, mmax, geometry); SHT_ENOPLAN if they are not resident (or, for -1,
+// not pinned).
+int pin_plan(int lmax, int mmax, const HostGeom &hg, int delta);
+// The pinned resident tables of (lmax, mmax, geometry), looked up without
+// building, evicting or allocating anything; SHT_ENOPLAN if there are none.
+int find_pinned(int lmax, int mmax, const HostGeom &hg, CoefRef *c, GeomRef *p, StartRef *s);
 
 // Runs launch(i, stream_i) for i < n (n <= kSideStreams + 1): piece 0 on st,
 // the others on the library's side streams of the current device (default
@@ -193,6 +235,54 @@ void set_hip_error(hipError_t e, const char *where);
         }                                                    \
     } while (0)
 
+// Arguments of the FP64 Legendre tiles (k_legendre.hip) for one (lmax, mmax,
+// geometry): synthesis reads the c-scaled a_lm (ap) and writes ring-major
+// Delta; analysis reads Delta and writes a_lm (or per-group partials).
+struct SynArgs {
+    int lmax, mmax, nslots, nrings;
+    int64_t nalm;
+    const double2 *__restrict__ ap;
+    const double *__restrict__ alpha;
+    const int32_t *__restrict__ lstart;
+    const double2 *__restrict__ state;
+    const double *__restrict__ sx;
+    const int32_t *__restrict__ rn;
+    const int32_t *__restrict__ rsouth;
+    double2 *__restrict__ delta;
+};
+
+struct AnaArgs {
+    int lmax, mmax, nslots, nrings;
+    int64_t nalm;
+    const double2 *__restrict__ delta;
+    const double *__restrict__ alpha;
+    const double *__restrict__ cfac;
+    const int32_t *__restrict__ lstart;
+    const double2 *__restrict__ state;
+    const double *__restrict__ sx;
+    const int32_t *__restrict__ rn;
+    const int32_t *__restrict__ rsouth;
+    double2 *__restrict__ alm;
+    double2 *__restrict__ part;
+};
+
+// One request of an uneven batch (sht_batch_*), as the persistent Legendre
+// kernel reads it.  kind 0: synthesis, in wave units (m, tile of 64 T
+// slots), nunits = (mmax+1) * tiles; kind 1: analysis, shape 0 one wave per
+// m holding every slot (nslots <= 64 T), shape 1 one workgroup per (m, group
+// of 256 T slots), groups > 1 writing partials summed by a combine kernel.
+struct BatchReq {
+    SynArgs syn;
+    AnaArgs ana;
+    const double2 *alm_in;  // synthesis: the caller's a_lm (prescaled into syn.ap)
+    int kind, shape, T, tiles, nunits, groups;
+};
+// One work item: request `req`, first unit u0 (wave units: the item's four
+// waves take u0 .. u0+3; group shape: u0 = m * groups + group).
+struct BatchItem {
+    int32_t req, u0;
+};
+
 // Kernel launchers (k_legendre.hip, k_ring_fft.hip).  They enqueue only.
 int launch_leg_start(const CoefTables &c, const GeomPlan &p, int32_t *lstart, void *state, hipStream_t st);
 int launch_prescale(const CoefTables &c, const void *alm, void *aprime, int nmaps, hipStream_t st);
@@ -208,13 +298,38 @@ int launch_leg_syn_mx(const CoefTables &c, const GeomPlan &p, const StartTable &
                       void *aprime, void *delta, DeltaLayout dl, int nmaps, hipStream_t st);
 int launch_leg_ana_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *delta,
                       DeltaLayout dl, void *alm, int nmaps, void *partials, hipStream_t st);
+// Uneven batches: the persistent Legendre kernel over the items (queue head
+// *head reset to 0 first, in the same launch sequence), the prescale of
+// every synthesis request, and the combine of analysis requests with
+// several groups.  leg_batch_grid: resident workgroups of the persistent
+// kernel on the current device.
+int leg_batch_grid(int *grid);
+int launch_leg_batch(const BatchReq *reqs, const BatchItem *items, int nitems, int *head, int grid, hipStream_t st);
+int launch_prescale_batch(const BatchReq *reqs, const int32_t *syn_reqs, int nsyn, int max_chunks, hipStream_t st);
+int launch_combine_batch(const BatchReq *reqs, const int32_t *comb_reqs, int ncomb, int max_chunks, hipStream_t st);
+constexpr int kBatchMaxSynT = 4, kBatchMaxAnaT = 4;
+
 // a_lm = c_lm * (sum of the per-group partials, groups in order); Im a_l0 = 0.
 int launch_ana_combine(const CoefTables &c, int nmaps, int groups, const void *partials, void *alm,
                        hipStream_t st);
+// Ring stages: the length classes run concurrently on side streams of st
+// (fork_join), or with fork = false one after another on st (no side streams).
 int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, DeltaLayout dl, double *map, int nmaps,
-                   hipStream_t st);
+                   hipStream_t st, bool fork = true);
 int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, DeltaLayout dl, int nmaps,
-                   hipStream_t st);
+                   hipStream_t st, bool fork = true);
+
+// sht_alm2map's host-side validation (sizes, flags, geometry, alm and map
+// pointers); sets the workspace bytes the call needs.
+int check_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, const double *map, int nmaps,
+                  uint32_t flags, HostGeom *h, size_t *ws_bytes_needed);
+// The kernels of sht_alm2map on stream st: Legendre synthesis into the
+// workspace Delta (aprime: the workspace's aux part), then the ring FFTs,
+// their length classes on side streams of st (fork) or one after another on st.
+int enqueue_alm2map(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm, void *aprime,
+                    void *delta, DeltaLayout dl, double *map, int nmaps, uint32_t flags, hipStream_t st, bool fork);
+// Workspace offset of the aux part (after Delta), for the layout [Delta][aux].
+size_t ws_aux_offset(int nrings, int mmax, int nmaps);
 
 inline int64_t nalm_of(int lmax, int mmax) {
     return (int64_t)(mmax + 1) * (2 * (int64_t)lmax + 2 - mmax) / 2;

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -83,7 +84,30 @@ static std::mutex g_bytes_mu;
 static auto &g_sizes = *new std::unordered_map<void *, size_t>();
 static size_t g_plan_bytes = 0;
 
+// Test hook for the failure paths of plan builds: with SHT_TEST_FAIL_ALLOC=n
+// in the environment, the n-th plan-table allocation counted from when that
+// value was first seen fails as if the device were out of memory.  Read only
+// here, during plan builds.
+static bool injected_failure() {
+    static std::mutex mu;
+    static std::string seen;
+    static long count = 0;
+    const char *v = std::getenv("SHT_TEST_FAIL_ALLOC");
+    std::lock_guard<std::mutex> lk(mu);
+    if (!v || !*v) {
+        seen.clear();
+        count = 0;
+        return false;
+    }
+    if (seen != v) {
+        seen = v;
+        count = 0;
+    }
+    return ++count == std::strtol(v, nullptr, 10);
+}
+
 static bool dev_alloc(void **p, size_t bytes) {
+    if (injected_failure()) return false;
     if (hipMalloc(p, bytes) != hipSuccess) {
         (void)hipGetLastError();
         return false;
@@ -117,8 +141,8 @@ static int upload(const std::vector<T> &v, T **dst, std::vector<void *> &owned) 
     const size_t bytes = std::max<size_t>(1, v.size()) * sizeof(T);
     if (!dev_alloc(&p, bytes)) return SHT_ENOMEM;
     owned.push_back(p);
+    *dst = static_cast<T *>(p);  // set before the copy: a failed copy still hands the allocation back
     if (!v.empty()) SHT_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
-    *dst = static_cast<T *>(p);
     return SHT_OK;
 }
 
@@ -127,31 +151,71 @@ static int current_device(int *dev) {
     return SHT_OK;
 }
 
-// Frees device allocations of a table on its device once the device is idle:
-// kernels enqueued by other calls may still read the table.
-static void release_device(int dev, std::vector<void *> &ptrs) {
+// ------------------------------------------------------------------ use fences
+static std::mutex g_use_mu;
+static auto &g_uses = *new std::map<std::pair<int, hipStream_t>, StreamUse *>();
+
+void Fenced::note_use(StreamUse *u) const {
+    std::lock_guard<std::mutex> lk(fence_mu);
+    for (StreamUse *v : users)
+        if (v == u) return;
+    users.push_back(u);
+}
+
+void Fenced::wait_users() const {
+    std::lock_guard<std::mutex> lk(fence_mu);
+    for (StreamUse *u : users) (void)hipEventSynchronize(u->ev);
+    users.clear();
+}
+
+int note_uses(hipStream_t st, std::initializer_list<const Fenced *> tables) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    SHT_HIP(hipStreamIsCapturing(st, &cs));
+    if (cs != hipStreamCaptureStatusNone) return SHT_OK;  // captured graphs pin their plans
+    int dev = 0;
+    SHT_HIP(hipGetDevice(&dev));
+    StreamUse *u = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_use_mu);
+        auto &slot = g_uses[std::make_pair(dev, st)];
+        if (!slot) {
+            hipEvent_t ev = nullptr;
+            SHT_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            slot = new StreamUse{dev, st, ev};
+        }
+        u = slot;
+        SHT_HIP(hipEventRecord(u->ev, st));
+    }
+    for (const Fenced *t : tables)
+        if (t) t->note_use(u);
+    return SHT_OK;
+}
+
+// Frees device allocations of a table on its device once the work that used
+// it is done (see Fenced).
+static void release_device(int dev, const Fenced &f, std::vector<void *> &ptrs) {
+    f.wait_users();
     if (ptrs.empty()) return;
     int cur = -1;
     (void)hipGetDevice(&cur);
     if (dev >= 0 && cur != dev) (void)hipSetDevice(dev);
-    (void)hipDeviceSynchronize();
     for (void *q : ptrs) dev_free(q);
     ptrs.clear();
     if (dev >= 0 && cur >= 0 && cur != dev) (void)hipSetDevice(cur);
 }
 
-CoefTables::~CoefTables() { release_device(dev, owned); }
+CoefTables::~CoefTables() { release_device(dev, *this, owned); }
 
 StartTable::~StartTable() {
     std::vector<void *> v;
     if (lstart) v.push_back(lstart);
     if (state) v.push_back(state);
-    release_device(dev, v);
+    release_device(dev, *this, v);
 }
 
 GeomPlan::~GeomPlan() {
     starts.clear();  // each start table frees itself when its last user is done
-    release_device(dev, owned);
+    release_device(dev, *this, owned);
 }
 
 // ------------------------------------------------------------------ coefficient tables
@@ -183,10 +247,14 @@ static void coef_column(int lmax, int m, double *alpha, double *cfac) {
 
 // The caches are created on first use and never destroyed at process exit
 // (their destructors would call into the HIP runtime after it has gone);
-// sht_shutdown empties them.
+// sht_shutdown empties them.  Tables are built outside the cache lock (a
+// concurrent build of the same key keeps the first one inserted), and
+// evicted entries are dropped after the lock is released, so that no call
+// waits on another's build or free.
 struct CoefEntry {
     std::shared_ptr<CoefTables> t;
     uint64_t last_use = 0;
+    int pins = 0;
 };
 static std::mutex g_mu;
 static uint64_t g_clock = 0;
@@ -195,24 +263,7 @@ static auto &g_coef = *new std::map<std::tuple<int, int, int>, CoefEntry>();
 static size_t g_max_coef = 8;
 static size_t g_max_geom = 32;
 
-int get_coef(int lmax, int mmax, CoefRef *out) {
-    int dev = 0;
-    int rc = current_device(&dev);
-    if (rc) return rc;
-    std::lock_guard<std::mutex> lk(g_mu);
-    auto key = std::make_tuple(dev, lmax, mmax);
-    auto it = g_coef.find(key);
-    if (it != g_coef.end()) {
-        it->second.last_use = ++g_clock;
-        *out = it->second.t;
-        return SHT_OK;
-    }
-    while (g_coef.size() >= g_max_coef) {
-        auto lru = std::min_element(g_coef.begin(), g_coef.end(), [](const auto &a, const auto &b) {
-            return a.second.last_use < b.second.last_use;
-        });
-        g_coef.erase(lru);  // freed when its last user is done
-    }
+static int build_coef(int dev, int lmax, int mmax, std::shared_ptr<CoefTables> *out) {
     auto t = std::make_shared<CoefTables>();
     t->dev = dev;
     const int64_t na = nalm_of(lmax, mmax);
@@ -235,10 +286,49 @@ int get_coef(int lmax, int mmax, CoefRef *out) {
     std::vector<int64_t> mxofs(mmax + 2, 0);
     for (int m = 0; m <= mmax; ++m) mxofs[m + 1] = mxofs[m] + mx_blocks(lmax, m);
     t->mxblocks = mxofs[mmax + 1];
+    int rc;
     if ((rc = upload(alpha, &t->alpha, t->owned)) || (rc = upload(cfac, &t->cfac, t->owned)) ||
         (rc = upload(mu, &t->mu, t->owned)) || (rc = upload(mxofs, &t->mxofs, t->owned)))
         return rc;  // t frees what was uploaded
-    g_coef[key] = CoefEntry{t, ++g_clock};
+    *out = std::move(t);
+    return SHT_OK;
+}
+
+int get_coef(int lmax, int mmax, CoefRef *out) {
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc) return rc;
+    const auto key = std::make_tuple(dev, lmax, mmax);
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        auto it = g_coef.find(key);
+        if (it != g_coef.end()) {
+            it->second.last_use = ++g_clock;
+            *out = it->second.t;
+            return SHT_OK;
+        }
+    }
+    std::shared_ptr<CoefTables> t;
+    if ((rc = build_coef(dev, lmax, mmax, &t))) return rc;
+    std::vector<std::shared_ptr<CoefTables>> dropped;  // freed after the lock is released
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_coef.find(key);
+    if (it != g_coef.end()) {  // built meanwhile by another call: keep that one
+        it->second.last_use = ++g_clock;
+        *out = it->second.t;
+        dropped.push_back(std::move(t));
+        return SHT_OK;
+    }
+    // make room: least recently used unpinned entries first
+    while (g_coef.size() >= g_max_coef) {
+        auto lru = g_coef.end();
+        for (auto e = g_coef.begin(); e != g_coef.end(); ++e)
+            if (e->second.pins == 0 && (lru == g_coef.end() || e->second.last_use < lru->second.last_use)) lru = e;
+        if (lru == g_coef.end()) break;  // all pinned
+        dropped.push_back(std::move(lru->second.t));
+        g_coef.erase(lru);
+    }
+    g_coef[key] = CoefEntry{t, ++g_clock, 0};
     *out = t;
     return SHT_OK;
 }
@@ -303,8 +393,25 @@ struct FftCache {
     std::vector<void *> owned;
 };
 static auto &g_fft = *new std::map<int, std::unique_ptr<FftCache>>();  // by device
+static std::mutex g_fft_mu;  // guards g_fft and its entries
 
-static int twiddle_table(FftCache &fc, int L, const double2 **out) {
+// What one geometry build added to an FftCache, so that a failed build can
+// take it all out again (the cache then holds only complete entries).
+struct FftAdded {
+    std::vector<int> lengths, twiddle_L;
+    std::vector<void *> ptrs;
+};
+static void fft_rollback(FftCache &fc, FftAdded &a) {
+    for (int n : a.lengths) fc.descs.erase(n);
+    for (int L : a.twiddle_L) fc.twiddles.erase(L);
+    for (void *p : a.ptrs) {
+        fc.owned.erase(std::remove(fc.owned.begin(), fc.owned.end(), p), fc.owned.end());
+        dev_free(p);
+    }
+    a = FftAdded{};
+}
+
+static int twiddle_table(FftCache &fc, int L, const double2 **out, FftAdded &added) {
     auto it = fc.twiddles.find(L);
     if (it != fc.twiddles.end()) {
         *out = it->second;
@@ -316,14 +423,17 @@ static int twiddle_table(FftCache &fc, int L, const double2 **out) {
         w[t] = make_double2((double)cosl(a), (double)sinl(a));
     }
     double2 *d = nullptr;
+    const size_t before = fc.owned.size();
     int rc = upload(w, &d, fc.owned);
+    if (fc.owned.size() > before) added.ptrs.push_back(fc.owned.back());
     if (rc) return rc;
     fc.twiddles[L] = d;
+    added.twiddle_L.push_back(L);
     *out = d;
     return SHT_OK;
 }
 
-static int fft_desc(FftCache &fc, int n, FftDesc *out) {
+static int fft_desc(FftCache &fc, int n, FftDesc *out, FftAdded &added) {
     auto it = fc.descs.find(n);
     if (it != fc.descs.end()) {
         *out = it->second;
@@ -358,13 +468,13 @@ static int fft_desc(FftCache &fc, int n, FftDesc *out) {
         d.bluestein = 1;
         factor_small(L, rad);
         // chirp b_t = exp(i pi t^2 / n), angle reduced exactly: t^2 mod 2n
-        std::vector<double2> b(n);
+        // (the kernels compute b_t themselves; the plan keeps the spectrum of
+        // its extension to length L)
         std::vector<cld> ext(L, cld(0, 0));
         for (int t = 0; t < n; ++t) {
             const long long q = (long long)t * t % (2LL * n);
             const long double a = kPiL * (long double)q / (long double)n;
             const cld v(cosl(a), sinl(a));
-            b[t] = make_double2((double)v.real(), (double)v.imag());
             ext[t] = v;
             if (t > 0) ext[L - t] = v;
         }
@@ -372,16 +482,18 @@ static int fft_desc(FftCache &fc, int n, FftDesc *out) {
         std::vector<double2> k(L);
         for (int t = 0; t < L; ++t)
             k[t] = make_double2((double)(ext[t].real() / L), (double)(ext[t].imag() / L));
-        double2 *db = nullptr, *dk = nullptr;
-        if ((rc = upload(b, &db, fc.owned)) || (rc = upload(k, &dk, fc.owned))) return rc;
-        d.chirp = db;
+        double2 *dk = nullptr;
+        rc = upload(k, &dk, fc.owned);
+        if (dk) added.ptrs.push_back(dk);
+        if (rc) return rc;
         d.kern = dk;
     }
     if (d.L > kMaxFftLen) return SHT_EUNSUPPORTED;
     d.nrad = (int)rad.size();
     for (int i = 0; i < d.nrad; ++i) d.rad[i] = rad[i];
-    if ((rc = twiddle_table(fc, d.L, &d.tw))) return rc;
+    if ((rc = twiddle_table(fc, d.L, &d.tw, added))) return rc;
     fc.descs[n] = d;
+    added.lengths.push_back(n);
     *out = d;
     return SHT_OK;
 }
@@ -392,6 +504,7 @@ struct GeomEntry {
     HostGeom key;
     std::shared_ptr<GeomPlan> plan;
     uint64_t last_use;
+    int pins;
 };
 static auto &g_geom = *new std::vector<GeomEntry>();
 
@@ -400,12 +513,15 @@ static bool same_geom(const HostGeom &a, const HostGeom &b) {
            a.nphi == b.nphi && a.phi0 == b.phi0 && a.ofs == b.ofs && a.weight == b.weight;
 }
 
-// Mirror pairs: rings r, r' with |theta_r + theta_r' - pi| <= tol share one
-// recurrence (lambda_lm(-x) = (-1)^(l+m) lambda_lm(x)); the northern ring's
-// cos and sin are used for both.
+// Mirror pairs: rings r, r' with |theta_r + theta_r' - pi| <= kMirrorTol,
+// the sum taken exactly in long double, share one recurrence
+// (lambda_lm(-x) = (-1)^(l+m) lambda_lm(x)); the northern ring's cos and sin
+// are used for both.  Two ulp of pi: a southern colatitude rounded from
+// pi - theta_n (once, or as double(pi) - theta_n) is within it, and a ring any
+// further off mirror is its own slot, evaluated at its own colatitude.
+constexpr long double kMirrorTol = 0x1p-50L;  // 2 ulp of pi = 8.9e-16 rad
 static void build_slots(const HostGeom &h, std::vector<double> &sx, std::vector<double> &ss,
                         std::vector<int32_t> &sn, std::vector<int32_t> &sso) {
-    const double tol = 1e-14;
     const int n = h.nrings;
     std::vector<int> ord(n);
     for (int r = 0; r < n; ++r) ord[r] = r;
@@ -421,8 +537,8 @@ static void build_slots(const HostGeom &h, std::vector<double> &sx, std::vector<
             slots.push_back({std::cos(h.theta[a]), std::sin(h.theta[a]), a, -1});
             break;
         }
-        const double d = h.theta[a] + h.theta[b] - M_PI;
-        if (std::fabs(d) <= tol) {
+        const long double d = ((long double)h.theta[a] + (long double)h.theta[b]) - kPiL;
+        if (fabsl(d) <= kMirrorTol) {
             slots.push_back({std::cos(h.theta[a]), std::sin(h.theta[a]), a, b});
             ++i;
             --j;
@@ -464,26 +580,52 @@ int count_slots(const HostGeom &h) {
     return n;
 }
 
+static GeomEntry *find_geom_locked(int dev, const HostGeom &hg) {
+    for (auto &e : g_geom)
+        if (e.dev == dev && same_geom(e.key, hg)) return &e;
+    return nullptr;
+}
+
+static int build_geom(int dev, const HostGeom &hg, std::shared_ptr<GeomPlan> *out);
+
 int get_geom(const HostGeom &hg, int /*mmax_for_fft*/, GeomRef *out) {
     int dev = 0;
     int rc = current_device(&dev);
     if (rc) return rc;
-    std::lock_guard<std::mutex> lk(g_mu);
-    for (auto &e : g_geom) {
-        if (e.dev == dev && same_geom(e.key, hg)) {
-            e.last_use = ++g_clock;
-            *out = e.plan;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (GeomEntry *e = find_geom_locked(dev, hg)) {
+            e->last_use = ++g_clock;
+            *out = e->plan;
             return SHT_OK;
         }
     }
+    std::shared_ptr<GeomPlan> plan;
+    if ((rc = build_geom(dev, hg, &plan))) return rc;
+    std::vector<std::shared_ptr<GeomPlan>> dropped;  // freed after the lock is released
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (GeomEntry *e = find_geom_locked(dev, hg)) {  // built meanwhile by another call
+        e->last_use = ++g_clock;
+        *out = e->plan;
+        dropped.push_back(std::move(plan));
+        return SHT_OK;
+    }
     while (g_geom.size() >= g_max_geom) {
-        // drop the least recently used plan; it is freed when its last user is done
-        auto lru = std::min_element(g_geom.begin(), g_geom.end(),
-                                    [](const GeomEntry &a, const GeomEntry &b) { return a.last_use < b.last_use; });
+        // the least recently used unpinned plan goes; it is freed when its last user is done
+        auto lru = g_geom.end();
+        for (auto e = g_geom.begin(); e != g_geom.end(); ++e)
+            if (e->pins == 0 && (lru == g_geom.end() || e->last_use < lru->last_use)) lru = e;
+        if (lru == g_geom.end()) break;  // all pinned
+        dropped.push_back(std::move(lru->plan));
         g_geom.erase(lru);
     }
-    auto &fcp = g_fft[dev];
-    if (!fcp) fcp = std::make_unique<FftCache>();
+    g_geom.push_back(GeomEntry{dev, hg, plan, ++g_clock, 0});
+    *out = plan;
+    return SHT_OK;
+}
+
+static int build_geom(int dev, const HostGeom &hg, std::shared_ptr<GeomPlan> *out) {
+    int rc;
     auto plan = std::make_shared<GeomPlan>();
     GeomPlan &p = *plan;  // on an error return below, plan frees what was uploaded
     p.dev = dev;
@@ -497,20 +639,34 @@ int get_geom(const HostGeom &hg, int /*mmax_for_fft*/, GeomRef *out) {
     std::map<int, int> desc_index;
     std::vector<int32_t> ring_desc(hg.nrings);
     int maxL = 1, maxn = 1;
-    for (int r = 0; r < hg.nrings; ++r) {
-        const int n = hg.nphi[r];
-        auto it = desc_index.find(n);
-        if (it == desc_index.end()) {
-            FftDesc d;
-            rc = fft_desc(*fcp, n, &d);
-            if (rc) return rc;
-            desc_index[n] = (int)descs.size();
-            descs.push_back(d);
-            it = desc_index.find(n);
+    std::unique_lock<std::mutex> fft_lk(g_fft_mu);  // held until the plan is complete (or rolled back)
+    auto &fcp = g_fft[dev];
+    if (!fcp) fcp = std::make_unique<FftCache>();
+    FftAdded added;
+    struct Rollback {
+        FftCache &fc;
+        FftAdded &a;
+        bool done = false;
+        ~Rollback() {
+            if (!done) fft_rollback(fc, a);
         }
-        ring_desc[r] = it->second;
-        maxL = std::max(maxL, descs[it->second].L);
-        maxn = std::max(maxn, n);
+    } rollback{*fcp, added};
+    {
+        for (int r = 0; r < hg.nrings; ++r) {
+            const int n = hg.nphi[r];
+            auto it = desc_index.find(n);
+            if (it == desc_index.end()) {
+                FftDesc d;
+                rc = fft_desc(*fcp, n, &d, added);
+                if (rc) return rc;
+                desc_index[n] = (int)descs.size();
+                descs.push_back(d);
+                it = desc_index.find(n);
+            }
+            ring_desc[r] = it->second;
+            maxL = std::max(maxL, descs[it->second].L);
+            maxn = std::max(maxn, n);
+        }
     }
     p.max_L = maxL;
     p.all_nphi_max = maxn;
@@ -554,29 +710,31 @@ int get_geom(const HostGeom &hg, int /*mmax_for_fft*/, GeomRef *out) {
         (rc = upload(ring_desc, &p.ring_desc, p.owned)) || (rc = upload(descs, &p.descs, p.owned)))
         return rc;
     if (hg.has_weight && (rc = upload(hg.weight, &p.weight, p.owned))) return rc;
-    g_geom.push_back(GeomEntry{dev, hg, plan, ++g_clock});
-    *out = plan;
+    rollback.done = true;  // the new FFT lengths stay cached for every plan that needs them
+    *out = std::move(plan);
     return SHT_OK;
 }
 
-constexpr size_t kMaxStartTables = 4;  // per geometry plan
+constexpr size_t kMaxStartTables = 4;  // per geometry plan (unpinned ones may go beyond it)
+
+// a start table of p that serves (lmax, mmax); with pinned_only, a pinned one
+static std::shared_ptr<StartTable> find_start_locked(const GeomPlan &p, int lmax, int mmax, bool pinned_only) {
+    for (const auto &t : p.starts)
+        if (t->lmax >= lmax && t->mmax >= mmax && (!pinned_only || t->pins > 0)) return t;
+    return nullptr;
+}
 
 int get_start(const CoefTables &c, const GeomRef &pref, hipStream_t st, StartRef *out) {
-    std::lock_guard<std::mutex> lk(g_mu);
-    const GeomPlan &p = *pref;  // its start list is only touched under the lock
-    for (const auto &t : p.starts) {
-        if (t->lmax >= c.lmax && t->mmax >= c.mmax) {
+    const GeomPlan &p = *pref;  // its start list is only touched under the cache lock
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (auto t = find_start_locked(p, c.lmax, c.mmax, false)) {
             t->last_use = ++g_clock;
             *out = t;
             return SHT_OK;
         }
     }
-    if (p.starts.size() >= kMaxStartTables) {
-        // drop the least recently used table; it is freed when its last user is done
-        auto lru = std::min_element(p.starts.begin(), p.starts.end(),
-                                    [](const auto &a, const auto &b) { return a->last_use < b->last_use; });
-        p.starts.erase(lru);
-    }
+    // built and waited for outside the cache lock
     auto t = std::make_shared<StartTable>();
     t->dev = p.dev;
     t->lmax = c.lmax;
@@ -590,20 +748,74 @@ int get_start(const CoefTables &c, const GeomRef &pref, hipStream_t st, StartRef
     int rc = launch_leg_start(c, p, t->lstart, t->state, st);
     if (rc == SHT_OK && hipStreamSynchronize(st) != hipSuccess) rc = SHT_EDEVICE;
     if (rc) return rc;
+    std::vector<std::shared_ptr<StartTable>> dropped;  // freed after the lock is released
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (auto u = find_start_locked(p, c.lmax, c.mmax, false)) {  // built meanwhile by another call
+        u->last_use = ++g_clock;
+        *out = u;
+        dropped.push_back(std::move(t));
+        return SHT_OK;
+    }
+    while (p.starts.size() >= kMaxStartTables) {
+        // the least recently used unpinned table goes; it is freed when its last user is done
+        auto lru = p.starts.end();
+        for (auto e = p.starts.begin(); e != p.starts.end(); ++e)
+            if ((*e)->pins == 0 && (lru == p.starts.end() || (*e)->last_use < (*lru)->last_use)) lru = e;
+        if (lru == p.starts.end()) break;  // all pinned
+        dropped.push_back(std::move(*lru));
+        p.starts.erase(lru);
+    }
     t->last_use = ++g_clock;
     p.starts.push_back(t);
     *out = t;
     return SHT_OK;
 }
 
+int pin_plan(int lmax, int mmax, const HostGeom &hg, int delta) {
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto ce = g_coef.find(std::make_tuple(dev, lmax, mmax));
+    GeomEntry *ge = find_geom_locked(dev, hg);
+    if (ce == g_coef.end() || !ge) return SHT_ENOPLAN;
+    auto st = find_start_locked(*ge->plan, lmax, mmax, delta < 0);
+    if (!st) return SHT_ENOPLAN;
+    if (delta < 0 && (ce->second.pins <= 0 || ge->pins <= 0)) return SHT_ENOPLAN;
+    ce->second.pins += delta;
+    ge->pins += delta;
+    st->pins += delta;
+    return SHT_OK;
+}
+
+int find_pinned(int lmax, int mmax, const HostGeom &hg, CoefRef *c, GeomRef *p, StartRef *s) {
+    int dev = 0;
+    int rc = current_device(&dev);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto ce = g_coef.find(std::make_tuple(dev, lmax, mmax));
+    GeomEntry *ge = find_geom_locked(dev, hg);
+    if (ce == g_coef.end() || ce->second.pins <= 0 || !ge || ge->pins <= 0) return SHT_ENOPLAN;
+    auto st = find_start_locked(*ge->plan, lmax, mmax, true);
+    if (!st) return SHT_ENOPLAN;
+    *c = ce->second.t;
+    *p = ge->plan;
+    *s = st;
+    return SHT_OK;
+}
+
 // ------------------------------------------------------------------ side streams
+// Each calling stream has its own side streams and fork/join events, so that
+// calls on different streams never share them: they neither serialise on a
+// lock nor join each other's graph captures.
 struct SideStreams {
     hipStream_t s[kSideStreams] = {};
     hipEvent_t fork = nullptr;
     hipEvent_t join[kSideStreams] = {};
+    std::mutex mu;  // one call at a time per calling stream
 };
 static std::mutex g_side_mu;
-static auto &g_side = *new std::map<int, std::unique_ptr<SideStreams>>();  // by device
+static auto &g_side = *new std::map<std::pair<int, hipStream_t>, std::unique_ptr<SideStreams>>();
 
 static void free_side(SideStreams &p) {
     for (int i = 0; i < kSideStreams; ++i) {
@@ -619,24 +831,29 @@ int fork_join(hipStream_t st, int n, const std::function<int(int, hipStream_t)> 
     int dev = 0;
     int rc = current_device(&dev);
     if (rc) return rc;
-    // one caller at a time per process: the fork and join events are shared
-    std::lock_guard<std::mutex> lk(g_side_mu);
-    auto &p = g_side[dev];
-    if (!p) {
-        auto q = std::make_unique<SideStreams>();
-        // the events only order kernels of one device: a device-scope release
-        // suffices (no system-scope fence, which would write back for the host)
-        const unsigned ef = hipEventDisableTiming | hipEventDisableSystemFence;
-        bool ok = hipEventCreateWithFlags(&q->fork, ef) == hipSuccess;
-        for (int i = 0; ok && i < kSideStreams; ++i)
-            ok = hipStreamCreateWithFlags(&q->s[i], hipStreamNonBlocking) == hipSuccess &&
-                 hipEventCreateWithFlags(&q->join[i], ef) == hipSuccess;
-        if (!ok) {
-            free_side(*q);
-            return SHT_EDEVICE;
+    SideStreams *p = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_side_mu);
+        auto &slot = g_side[std::make_pair(dev, st)];
+        if (!slot) {
+            auto q = std::make_unique<SideStreams>();
+            // the events only order kernels of one device: a device-scope release
+            // suffices (no system-scope fence, which would write back for the host)
+            const unsigned ef = hipEventDisableTiming | hipEventDisableSystemFence;
+            bool ok = hipEventCreateWithFlags(&q->fork, ef) == hipSuccess;
+            for (int i = 0; ok && i < kSideStreams; ++i)
+                ok = hipStreamCreateWithFlags(&q->s[i], hipStreamNonBlocking) == hipSuccess &&
+                     hipEventCreateWithFlags(&q->join[i], ef) == hipSuccess;
+            if (!ok) {
+                free_side(*q);
+                g_side.erase(std::make_pair(dev, st));
+                return SHT_EDEVICE;
+            }
+            slot = std::move(q);
         }
-        p = std::move(q);
+        p = slot.get();
     }
+    std::lock_guard<std::mutex> lk(p->mu);
     SHT_HIP(hipEventRecord(p->fork, st));
     for (int i = 1; i < n; ++i) SHT_HIP(hipStreamWaitEvent(p->s[i - 1], p->fork, 0));
     for (int i = 0; i < n && rc == SHT_OK; ++i) rc = launch(i, i == 0 ? st : p->s[i - 1]);
@@ -650,33 +867,60 @@ int fork_join(hipStream_t st, int n, const std::function<int(int, hipStream_t)> 
 
 int set_cache_limits(int max_coef, int max_geom) {
     if (max_coef < 1 || max_geom < 1) return SHT_EINVAL;
+    std::vector<std::shared_ptr<CoefTables>> dc;  // freed after the lock is released
+    std::vector<std::shared_ptr<GeomPlan>> dg;
     std::lock_guard<std::mutex> lk(g_mu);
     g_max_coef = (size_t)max_coef;
     g_max_geom = (size_t)max_geom;
-    // entries beyond the new limits go now, least recently used first; each is
-    // freed when its last user is done
-    while (g_coef.size() > g_max_coef)
-        g_coef.erase(std::min_element(g_coef.begin(), g_coef.end(), [](const auto &a, const auto &b) {
-            return a.second.last_use < b.second.last_use;
-        }));
-    while (g_geom.size() > g_max_geom)
-        g_geom.erase(std::min_element(g_geom.begin(), g_geom.end(), [](const GeomEntry &a, const GeomEntry &b) {
-            return a.last_use < b.last_use;
-        }));
+    // unpinned entries beyond the new limits go now, least recently used
+    // first; each is freed when its last user is done
+    while (g_coef.size() > g_max_coef) {
+        auto lru = g_coef.end();
+        for (auto e = g_coef.begin(); e != g_coef.end(); ++e)
+            if (e->second.pins == 0 && (lru == g_coef.end() || e->second.last_use < lru->second.last_use)) lru = e;
+        if (lru == g_coef.end()) break;
+        dc.push_back(std::move(lru->second.t));
+        g_coef.erase(lru);
+    }
+    while (g_geom.size() > g_max_geom) {
+        auto lru = g_geom.end();
+        for (auto e = g_geom.begin(); e != g_geom.end(); ++e)
+            if (e->pins == 0 && (lru == g_geom.end() || e->last_use < lru->last_use)) lru = e;
+        if (lru == g_geom.end()) break;
+        dg.push_back(std::move(lru->plan));
+        g_geom.erase(lru);
+    }
     return SHT_OK;
 }
 
 void shutdown_all() {
-    std::lock_guard<std::mutex> lk(g_mu);
-    (void)hipDeviceSynchronize();
-    g_geom.clear();  // plans and their start tables free themselves
-    g_coef.clear();
-    for (auto &kv : g_fft)
-        for (void *p : kv.second->owned) dev_free(p);
-    g_fft.clear();
-    std::lock_guard<std::mutex> lk2(g_side_mu);
-    for (auto &kv : g_side) free_side(*kv.second);
-    g_side.clear();
+    std::vector<GeomEntry> geoms;
+    std::map<std::tuple<int, int, int>, CoefEntry> coefs;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        geoms.swap(g_geom);
+        coefs.swap(g_coef);
+    }
+    (void)hipDeviceSynchronize();  // calls in flight must have completed; this is the last check
+    geoms.clear();  // plans and their start tables free themselves
+    coefs.clear();
+    {
+        std::lock_guard<std::mutex> lk(g_fft_mu);
+        for (auto &kv : g_fft)
+            for (void *p : kv.second->owned) dev_free(p);
+        g_fft.clear();
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_side_mu);
+        for (auto &kv : g_side) free_side(*kv.second);
+        g_side.clear();
+    }
+    std::lock_guard<std::mutex> lk(g_use_mu);
+    for (auto &kv : g_uses) {
+        (void)hipEventDestroy(kv.second->ev);
+        delete kv.second;
+    }
+    g_uses.clear();
 }
 
 }  // namespace sht

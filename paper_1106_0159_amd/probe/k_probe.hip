@@ -1,10 +1,13 @@
-// Throughput probes (include/sht_probe.h): long runs of independent FP64
-// FMAs, FP32 16x16x4 and BF16 16x16x32 matrix instructions, with no memory
-// traffic in the loop.
-#include "sht_internal.h"
+// Throughput probes (sht_probe.h; a benchmark-only library, libsht_probe.so,
+// separate from the transform library): long runs of independent FP64 FMAs,
+// FP32 16x16x4 and BF16 16x16x32 matrix instructions, with no memory traffic
+// in the loop.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
 #include "sht_probe.h"
 
-namespace sht {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -55,9 +58,6 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_mfma(int iters, double 
 }
 
 }  // namespace
-}  // namespace sht
-
-using namespace sht;
 
 extern "C" {
 
@@ -73,7 +73,7 @@ double sht_probe_flops(int kind, int blocks, int iters) {
 }
 
 int sht_probe_run(int kind, int blocks, int iters, void *out, void *stream) {
-    if (sht_probe_flops(kind, blocks, iters) == 0.0 || !out) return SHT_EINVAL;
+    if (sht_probe_flops(kind, blocks, iters) == 0.0 || !out) return -1;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
     double *o = static_cast<double *>(out);
     switch (kind) {
@@ -89,8 +89,7 @@ int sht_probe_run(int kind, int blocks, int iters, void *out, void *stream) {
                                st, iters, o);
             break;
     }
-    SHT_HIP(hipGetLastError());
-    return SHT_OK;
+    return hipGetLastError() == hipSuccess ? 0 : -3;
 }
 
 }  // extern "C"

@@ -1,6 +1,7 @@
 /*
- * sht_probe.h -- throughput probes of libsht.so for the roofline of the
- * benchmark (not part of the transform API).  They measure what one MI355X
+ * sht_probe.h -- throughput probes for the roofline of the benchmark,
+ * libsht_probe.so (built beside, not into, the transform library libsht.so;
+ * not part of the transform API).  They measure what one MI355X
  * (gfx950) attains on the instruction kinds the transform kernels use, with
  * no memory traffic in the timed loop: the benchmark reports its roofline
  * fractions against the nominal peaks and these measured rates beside them.
@@ -31,8 +32,8 @@ double sht_probe_flops(int kind, int blocks, int iters);
  * stream) and returns without waiting.
  *   out  DEVICE buffer of at least blocks * 256 * 8 bytes, written with one
  *        value per thread so that the work is not optimised away
- * Returns 0, -1 (SHT_EINVAL: invalid arguments, nothing enqueued) or -3
- * (SHT_EDEVICE: the launch failed). */
+ * Returns 0, -1 (invalid arguments, nothing enqueued) or -3 (the launch
+ * failed). */
 int sht_probe_run(int kind, int blocks, int iters, void *out, void *stream);
 
 #ifdef __cplusplus

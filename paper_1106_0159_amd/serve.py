@@ -48,6 +48,7 @@ class Request:
     result: object = None
     t_admit: float = 0.0
     t_done: float = 0.0
+    ready: object = None  # event on the submitting stream: the input is complete there
 
     def __post_init__(self):
         if self.kind not in KINDS:
@@ -154,9 +155,15 @@ class Server:
 
     # -- requests
     def submit(self, req: Request) -> bool:
-        """Queue a request; False (status 'rejected') if it can never fit."""
+        """Queue a request; False (status 'rejected') if it can never fit.
+
+        The input may still be in production on the caller's current stream:
+        an event recorded there now orders the request's own stream after it
+        (the request's transform waits for it on the device, not the host)."""
         if req.arrival is None:
             req.arrival = time.perf_counter()
+        req.ready = self.torch.cuda.Event()
+        req.ready.record(self.torch.cuda.current_stream(req.data.device))
         req.rid = self._next_id
         self._next_id += 1
         req.need, req.ws_bytes = request_bytes(req.kind, req.lmax, req.mmax, req.geom, req.nmaps, self.flags)
@@ -175,6 +182,10 @@ class Server:
         req.t_admit = time.perf_counter()
         try:
             with torch.cuda.stream(s):
+                # the slot stream runs after the input's producer, and the
+                # input's memory is not reused while this stream may read it
+                s.wait_event(req.ready)
+                req.data.record_stream(s)
                 ws = torch.empty(req.ws_bytes, dtype=torch.uint8, device=req.data.device)
                 f = alm2map if req.kind == "alm2map" else map2alm
                 req.result = f(req.data, req.geom, req.lmax, req.mmax, ws=ws, stream=s, flags=self.flags)

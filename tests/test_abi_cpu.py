@@ -155,7 +155,8 @@ def test_invalid_arguments_rejected_on_host(L):
     assert L.sht_alm2map(4, 5, g.ref(), a, m, 1, w, big, 0, None) == sht.SHT_EINVAL
     assert L.sht_alm2map(4, 4, g.ref(), a, m, 0, w, big, 0, None) == sht.SHT_EINVAL
     # flags: unknown bits; the map-minor Delta layout needs SHT_MIXED in the Legendre stage calls
-    assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, big, 4, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, big, 8, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, big, sht.SHT_PIN, None) == sht.SHT_EUNSUPPORTED  # sht_prepare only
     assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, big, 1 << 31, None) == sht.SHT_EUNSUPPORTED
     assert L.sht_map2alm(4, 4, g.ref(), m, a, 1, w, big, sht.SHT_MIXED | 4, None) == sht.SHT_EUNSUPPORTED
     assert L.sht_delta2alm(4, 4, g.ref(), m, a, 1, w, big, 8, None) == sht.SHT_EUNSUPPORTED
@@ -186,16 +187,36 @@ def test_invalid_arguments_rejected_on_host(L):
     assert L.sht_alm2delta(4, 4, g.ref(), a, m, 1, w, 8, 0, None) == sht.SHT_EWORKSPACE
 
 
-def test_probe_flop_counts_and_argument_checks(L):
-    """The throughput probes' flop counts (include/sht_probe.h): 256 threads per
-    workgroup, 8 chains; FP64 FMA 2 flops per lane and step, matrix
-    instructions 2*16*16*K per wave and step (K = 4 for FP32, 32 for BF16)."""
+def test_plan_calls_checked_on_host(L):
+    """sht_prepare and sht_unpin validate their arguments before any device
+    call."""
+    g = sht.GeomHandle(si.healpix(2))
+    assert L.sht_prepare(4, 4, g.ref(), 8, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_prepare(4, 5, g.ref(), sht.SHT_PIN, None) == sht.SHT_EINVAL
+    assert L.sht_unpin(4, 5, g.ref()) == sht.SHT_EINVAL
+    assert L.sht_unpin(4, 4, None) == sht.SHT_EINVAL
+    assert L.sht_strerror(sht.SHT_ENOPLAN).startswith(b"plan tables not resident")
+
+
+def test_probe_library_is_separate_and_checks_arguments():
+    """The throughput probes live in their own benchmark-only library
+    (libsht_probe.so, probe/sht_probe.h), not in the transform library.  Flop
+    counts: 256 threads per workgroup, 8 chains; FP64 FMA 2 flops per lane
+    and step, matrix instructions 2*16*16*K per wave and step (K = 4 for FP32,
+    32 for BF16)."""
+    from paper_1106_0159_amd import probe
+    if not os.path.exists(probe.LIB_PATH):
+        pytest.skip("libsht_probe.so not built")
+    if os.path.exists(sht.LIB_PATH):
+        nm = os.popen(f"nm -D --defined-only {sht.LIB_PATH}").read()
+        assert "sht_probe" not in nm
+    P = probe.lib()
     blocks, iters = 3, 5
-    assert L.sht_probe_flops(0, blocks, iters) == blocks * 256 * iters * 8 * 2
-    assert L.sht_probe_flops(1, blocks, iters) == blocks * 4 * iters * 8 * 2 * 16 * 16 * 4
-    assert L.sht_probe_flops(2, blocks, iters) == blocks * 4 * iters * 8 * 2 * 16 * 16 * 32
+    assert P.sht_probe_flops(0, blocks, iters) == blocks * 256 * iters * 8 * 2
+    assert P.sht_probe_flops(1, blocks, iters) == blocks * 4 * iters * 8 * 2 * 16 * 16 * 4
+    assert P.sht_probe_flops(2, blocks, iters) == blocks * 4 * iters * 8 * 2 * 16 * 16 * 32
     for kind, b, it in [(3, 1, 1), (-1, 1, 1), (0, 0, 1), (0, 1, 0)]:
-        assert L.sht_probe_flops(kind, b, it) == 0.0
+        assert P.sht_probe_flops(kind, b, it) == 0.0
     # rejected on the host, before any device call
-    assert L.sht_probe_run(0, 1, 1, None, None) == sht.SHT_EINVAL
-    assert L.sht_probe_run(7, 1, 1, ctypes.c_void_p(0x1000), None) == sht.SHT_EINVAL
+    assert P.sht_probe_run(0, 1, 1, None, None) == -1
+    assert P.sht_probe_run(7, 1, 1, ctypes.c_void_p(0x1000), None) == -1

@@ -217,3 +217,85 @@ def test_uneven_gauss_legendre_batch(env, flags):
         err = ((got - w).norm() / w.norm()).item()
         tol = (0.0 if r.kind == "alm2map" else 1e-12) if flags == 0 else 1e-6
         assert err <= tol, (r.kind, r.lmax, err)
+
+
+def test_pinned_plan_is_not_evicted(env):
+    """sht_prepare(..., SHT_PIN) keeps a plan resident through LRU eviction
+    at cache limits of 1 (the cache grows past its limit instead); once
+    unpinned it is evicted like any other.  Residency is read through
+    sht_plan_cache_bytes: preparing a resident plan builds nothing."""
+    sht, serve, grids, inputs = env
+    g1, L1 = si.healpix(8), 16
+    gh1 = sht.GeomHandle(g1)
+    others = [sht.GeomHandle(si.gauss_legendre(9, 17 + k)) for k in range(4)]
+    say("pinned plan under cache limits of 1")
+    sht.shutdown()
+    try:
+        sht.plan_cache_limits(1, 1)
+        sht.prepare(gh1, L1, pin=True)
+        for gh in others:
+            sht.prepare(gh, 8)  # each evicts the previous unpinned plan, never the pinned one
+        held = sht.plan_cache_bytes()
+        sht.prepare(gh1, L1)  # resident: nothing is built
+        assert sht.plan_cache_bytes() == held
+        a = si.powerlaw_alm(L1, L1, 3)
+        import torch
+        got = sht.alm2map(torch.from_numpy(a).cuda(), gh1, L1)
+        torch.cuda.synchronize()
+        ref = oracle.alm2map(L1, L1, g1, a)
+        assert np.linalg.norm(got.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-12
+        sht.unpin(gh1, L1)
+        sht.plan_cache_limits(1, 1)  # now the unpinned extras go
+        assert sht.plan_cache_bytes() < held
+        with pytest.raises(sht.ShtError) as e:
+            sht.unpin(gh1, L1)
+        assert e.value.code == sht.SHT_ENOPLAN
+    finally:
+        sht.plan_cache_limits(8, 32)
+
+
+def test_injected_allocation_failure_leaves_no_leak_and_no_partial_plan(env):
+    """Every plan-table allocation of a fresh build in turn fails (the
+    library's SHT_TEST_FAIL_ALLOC test hook): the build returns SHT_ENOMEM,
+    the cache keeps only complete entries and loses no bytes (after a
+    shutdown the plan bytes are 0 again), and a build without the failure
+    then gives the same cache size as a clean one and correct results."""
+    import os
+    import torch
+    sht, serve, grids, inputs = env
+    L, g = 24, si.healpix(8)
+    gh = sht.GeomHandle(g)
+    a = si.powerlaw_alm(L, L, 31)
+    ref = oracle.alm2map(L, L, g, a)
+    sht.shutdown()
+    assert sht.plan_cache_bytes() == 0
+    sht.prepare(gh, L)
+    clean = sht.plan_cache_bytes()
+    say(f"allocation failure injection: clean plan {clean} bytes")
+    k, failures = 1, 0
+    try:
+        while k < 200:
+            sht.shutdown()
+            assert sht.plan_cache_bytes() == 0, k  # nothing leaked by the last attempt
+            os.environ["SHT_TEST_FAIL_ALLOC"] = str(k)
+            try:
+                sht.prepare(gh, L)
+                ok = True
+            except sht.ShtError as e:
+                assert e.code == sht.SHT_ENOMEM, (k, e.code)
+                ok = False
+            del os.environ["SHT_TEST_FAIL_ALLOC"]
+            if ok:
+                break
+            failures += 1
+            assert sht.plan_cache_bytes() <= clean, k  # only complete entries stay
+            sht.prepare(gh, L)
+            assert sht.plan_cache_bytes() == clean, k
+            got = sht.alm2map(torch.from_numpy(a).cuda(), gh, L)
+            torch.cuda.synchronize()
+            assert np.linalg.norm(got.cpu().numpy() - ref) / np.linalg.norm(ref) <= 1e-12, k
+            k += 1
+    finally:
+        os.environ.pop("SHT_TEST_FAIL_ALLOC", None)
+    say(f"allocation failure injection: {failures} failing allocations checked")
+    assert failures >= 10  # coefficient, geometry, FFT and start tables all took their turn

@@ -103,5 +103,23 @@ def test_plan_entry_points_reject_bad_arguments(L):
     assert L.sht_prepare(-1, 0, g.ref(), 0, None) == sht.SHT_EINVAL
     assert L.sht_prepare(4, 5, g.ref(), 0, None) == sht.SHT_EINVAL
     assert L.sht_prepare(4, 4, None, 0, None) == sht.SHT_EINVAL
-    assert L.sht_prepare(4, 4, g.ref(), 4, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_prepare(4, 4, g.ref(), 8, None) == sht.SHT_EUNSUPPORTED  # (4 is SHT_PIN)
     assert L.sht_plan_cache_bytes() == 0  # nothing built in this process
+
+
+def test_autotune_table_lookup():
+    """The tile table's buckets and admissible candidates (no GPU): wave
+    tiles of analysis must hold every ring slot of one m."""
+    from paper_1106_0159_amd import autotune, ring_slots
+    assert autotune.bucket(100, 51) == "l128_s64"
+    assert autotune.bucket(5000, 9000) == "l4096_s4096"
+    assert autotune.candidates("alm2map", 1000) == [1, 2, 4]
+    assert autotune.candidates("map2alm", 100) == [2, 4, 17, 18, 20]
+    assert autotune.candidates("map2alm", 300) == [17, 18, 20]
+    table = {"alm2map": {"l128_s64": 2}, "map2alm": {"l128_s64": 4, "l512_s512": 4}}
+    assert autotune.choose(table, "alm2map", 100, 51) == 2
+    assert autotune.choose(table, "map2alm", 100, 51) == 4
+    assert autotune.choose(table, "map2alm", 400, 300) == 0  # a wave of 256 slots cannot hold 300
+    assert autotune.choose({}, "map2alm", 100, 51) == 0
+    assert ring_slots(si.gauss_legendre(129, 257).theta) == 65
+    assert ring_slots(si.healpix(16).theta) == 32
