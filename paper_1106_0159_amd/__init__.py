@@ -28,7 +28,7 @@ EXPORTS = ("sht_workspace_bytes", "sht_alm2map", "sht_map2alm", "sht_alm2delta",
            "sht_map2delta", "sht_delta2alm", "sht_strerror", "sht_shutdown",
            "sht_prepare", "sht_unpin", "sht_plan_cache_limits", "sht_plan_cache_bytes",
            "sht_batch_workspace_bytes", "sht_batch_create", "sht_batch_run",
-           "sht_batch_destroy")
+           "sht_batch_destroy", "sht_alm2map_noalloc")
 SHT_ALM2MAP, SHT_MAP2ALM = 0, 1  # sht_request.kind
 
 
@@ -91,6 +91,8 @@ def lib() -> ctypes.CDLL:
         L.sht_batch_run.argtypes = [P, P]
         L.sht_batch_destroy.restype = None
         L.sht_batch_destroy.argtypes = [P]
+        L.sht_alm2map_noalloc.restype = I
+        L.sht_alm2map_noalloc.argtypes = [I, I, GP, P, P, I, U, P]
         L.sht_plan_cache_limits.restype = I
         L.sht_plan_cache_limits.argtypes = [I, I]
         L.sht_plan_cache_bytes.restype = S
@@ -198,6 +200,24 @@ def map2alm(mp, geom, lmax: int, mmax: int | None = None, out=None, ws=None, str
     rc = lib().sht_map2alm(lmax, mmax, g.ref(), mp.data_ptr(), out.data_ptr(), nm, ws.data_ptr(),
                            ws.numel() * ws.element_size(), flags, _stream_ptr(stream))
     _check(rc, "sht_map2alm")
+    return out
+
+
+def alm2map_noalloc(alm, geom, lmax: int, mmax: int | None = None, out=None, stream=None, flags: int = 0):
+    """sht_alm2map_noalloc (include/sht_noalloc.h): synthesis whose workspace
+    is the library's fixed device scratch array.  The plan of (lmax, mmax,
+    geom) must be prepared and pinned first (prepare(..., pin=True)) with the
+    same geometry handle; pass `out` for a call that allocates nothing."""
+    torch = _torch()
+    mmax = lmax if mmax is None else mmax
+    g = _gh(geom, with_weight=False)
+    nm = _nmaps_of(alm, nalm(lmax, mmax))
+    if out is None:
+        alloc = torch.empty if g.covers_all else torch.zeros
+        out = alloc(alm.shape[:-1] + (g.npix,), dtype=torch.float64, device=alm.device)
+    rc = lib().sht_alm2map_noalloc(lmax, mmax, g.ref(), alm.data_ptr(), out.data_ptr(), nm, flags,
+                                   _stream_ptr(stream))
+    _check(rc, "sht_alm2map_noalloc")
     return out
 
 

@@ -16,7 +16,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OBJ = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libsht.so")
-SOURCES = ["sht_abi.cpp", "sht_plan.cpp", "sht_batch.cpp", "k_legendre.hip", "k_legendre_mx.hip", "k_ring_fft.hip"]
+SOURCES = ["sht_abi.cpp", "sht_plan.cpp", "sht_batch.cpp", "sht_noalloc.hip", "k_legendre.hip", "k_legendre_mx.hip",
+           "k_ring_fft.hip"]
 PROBE_DIR = os.path.join(PKG, "probe")
 PROBE_LIB = os.path.join(PKG, "libsht_probe.so")
 PROBE_SOURCES = ["k_probe.hip"]

@@ -89,8 +89,8 @@ def test_library_host_code_under_asan_ubsan(tmp_path):
     if not rt or not os.path.exists(HIPCC):
         pytest.skip("clang ASan runtime or hipcc not found")
     csrc = os.path.join(ROOT, "paper_1106_0159_amd", "csrc")
-    srcs = [os.path.join(csrc, s) for s in ("sht_abi.cpp", "sht_plan.cpp", "sht_batch.cpp",
-                                            "k_legendre.hip", "k_legendre_mx.hip", "k_ring_fft.hip")]
+    from paper_1106_0159_amd import _build
+    srcs = [os.path.join(csrc, s) for s in _build.SOURCES]
     lib = str(tmp_path / "libsht_asan.so")
     cmd = [HIPCC, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

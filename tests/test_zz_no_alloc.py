@@ -1,0 +1,88 @@
+"""sht_alm2map_noalloc (include/sht_noalloc.h): the synthesis with the
+library's fixed device scratch array as its workspace, against sht_alm2map
+with a caller workspace -- the same kernels, so the same bits -- on two calls
+in a row, the second with a smaller input (the scratch keeps the first call's
+contents).  Called through the C ABI."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import sht_inputs as si
+
+
+def _lib():
+    import paper_1106_0159_amd as sht
+    return sht, sht.lib()
+
+
+def test_noalloc_rejects_oversize_and_bad_arguments_before_any_device_call():
+    # validation happens on the host before the device is touched, so this
+    # runs without a GPU: fake (never dereferenced) aligned device addresses
+    sht, L = _lib()
+    big = sht.GeomHandle(si.healpix(1024), with_weight=False)
+    need = L.sht_workspace_bytes(2048, 2048, big.ref(), 1, 0)
+    assert need > (64 << 20)
+    alm, mp = ctypes.c_void_p(1 << 40), ctypes.c_void_p(1 << 41)
+    rc = L.sht_alm2map_noalloc(2048, 2048, big.ref(), alm, mp, 1, 0, None)
+    assert rc == sht.SHT_EWORKSPACE
+    small = sht.GeomHandle(si.healpix(8), with_weight=False)
+    assert L.sht_alm2map_noalloc(16, 17, small.ref(), alm, mp, 1, 0, None) == sht.SHT_EINVAL  # mmax > lmax
+    assert L.sht_alm2map_noalloc(16, 16, small.ref(), alm, mp, 0, 0, None) == sht.SHT_EINVAL  # no maps
+    assert L.sht_alm2map_noalloc(16, 16, small.ref(), None, mp, 1, 0, None) == sht.SHT_EINVAL
+    assert L.sht_alm2map_noalloc(16, 16, small.ref(), alm, mp, 1, 8, None) == sht.SHT_EUNSUPPORTED
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("flags,nmaps", [(0, 1), (0, 3), (1, 8)], ids=["fp64", "fp64-3maps", "mixed-8maps"])
+def test_noalloc_matches_alm2map_on_two_calls(flags, nmaps):
+    import torch
+    sht, L = _lib()
+    torch.cuda.set_device(0)
+    # first call larger than the second: the second reads a scratch array
+    # that still holds the first one's Delta and a_lm
+    cases = [(96, 48), (40, 16)]  # (lmax, nside)
+    for lmax, nside in cases:
+        print(f"noalloc case lmax={lmax} nside={nside} flags={flags} nmaps={nmaps}", flush=True)
+        gh = sht.GeomHandle(si.healpix(nside), with_weight=False)
+        alm = torch.from_numpy(np.stack([si.powerlaw_alm(lmax, lmax, si.config_seed(1, 50 + i))
+                                         for i in range(nmaps)])).cuda()
+        sht.prepare(gh, lmax, pin=True)
+        try:
+            ref = sht.alm2map(alm, gh, lmax, flags=flags)
+            out = torch.full((nmaps, gh.npix), float("nan"), dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            rc = L.sht_alm2map_noalloc(lmax, lmax, gh.ref(), ctypes.c_void_p(alm.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()), nmaps, flags,
+                                       ctypes.c_void_p(torch.cuda.current_stream().cuda_stream))
+            assert rc == sht.SHT_OK, sht.lib().sht_strerror(rc)
+            torch.cuda.synchronize()
+            assert torch.equal(out, ref), float((out - ref).abs().max())
+        finally:
+            sht.unpin(gh, lmax)
+
+
+@pytest.mark.gpu
+def test_noalloc_needs_a_pinned_plan():
+    import torch
+    sht, L = _lib()
+    torch.cuda.set_device(0)
+    lmax = 24
+    gh = sht.GeomHandle(si.healpix(12), with_weight=False)
+    alm = torch.from_numpy(si.powerlaw_alm(lmax, lmax, 5)).cuda()
+    out = torch.zeros(gh.npix, dtype=torch.float64, device="cuda")
+    sht.prepare(gh, lmax)  # resident but not pinned
+    rc = L.sht_alm2map_noalloc(lmax, lmax, gh.ref(), ctypes.c_void_p(alm.data_ptr()),
+                               ctypes.c_void_p(out.data_ptr()), 1, 0, None)
+    assert rc == sht.SHT_ENOPLAN
+    sht.prepare(gh, lmax, pin=True)
+    try:
+        rc = L.sht_alm2map_noalloc(lmax, lmax, gh.ref(), ctypes.c_void_p(alm.data_ptr()),
+                                   ctypes.c_void_p(out.data_ptr()), 1, 0, None)
+        assert rc == sht.SHT_OK
+        torch.cuda.synchronize()
+        ref = sht.alm2map(alm, gh, lmax)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+    finally:
+        sht.unpin(gh, lmax)
