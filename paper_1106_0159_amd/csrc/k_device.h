@@ -47,6 +47,27 @@ __device__ __forceinline__ int wave_max(int v) {
     return __builtin_amdgcn_readfirstlane(v);
 }
 
+// Read-only coefficient data (recurrence coefficients, scaled a_lm) seen
+// through the constant address space: nothing a kernel stores may alias it,
+// so loads at wave-uniform addresses become scalar (SGPR) loads.  (Pointers
+// taken from a struct lose the __restrict__ that tells the compiler so.)
+template <class T>
+using const_ptr = const __attribute__((address_space(4))) T *;
+template <class T>
+__device__ __forceinline__ const_ptr<T> ro(const T *p) {
+    return (const_ptr<T>)p;
+}
+// complex entries of such an array (re, im interleaved), loaded 16 bytes at a time
+typedef double dvec2 __attribute__((ext_vector_type(2)));
+struct ConstC {
+    const_ptr<dvec2> p;
+    __device__ __forceinline__ double2 operator[](int64_t i) const {
+        const dvec2 v = p[i];
+        return make_double2(v.x, v.y);
+    }
+};
+__device__ __forceinline__ ConstC ro(const double2 *p) { return ConstC{ro(reinterpret_cast<const dvec2 *>(p))}; }
+
 // A wave-uniform 64-bit value restated as such (for addresses that must stay
 // on scalar registers).
 __device__ __forceinline__ int64_t uniform64(int64_t v) {

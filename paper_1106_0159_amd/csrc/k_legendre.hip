@@ -166,8 +166,8 @@ __device__ __forceinline__ void syn_tile(const SynArgs &A, int m, int map, int s
     const int32_t *__restrict__ rn = A.rn;
     const int32_t *__restrict__ rsouth = A.rsouth;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;  // (l, m) lives at base + l
-    const double2 *__restrict__ a = A.ap + (int64_t)map * A.nalm + base;
-    const double *__restrict__ al = A.alpha + base;
+    const ConstC a = ro(A.ap + (int64_t)map * A.nalm + base);
+    const const_ptr<double> al = ro(A.alpha + base);
 
     double x[T], q1[T], q2[T], er[T], ei[T], orr[T], oi[T];
     int ls[T];
@@ -310,12 +310,12 @@ __global__ __launch_bounds__(kBlock, 4) void k_leg_syn_mm(SynArgs A, int tiles, 
     const int lmax = A.lmax, mmax = A.mmax, nslots = A.nslots;
     const int map0 = blockIdx.y * M;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;  // (l, m) lives at base + l
-    const double *__restrict__ al = A.alpha + base;
-    const double2 *__restrict__ a[M];
+    const const_ptr<double> al = ro(A.alpha + base);
+    ConstC a[M];
 #pragma unroll
-    for (int k = 0; k < M; ++k) a[k] = A.ap + (int64_t)min(map0 + k, nmaps - 1) * A.nalm + base;
-    const double warm_a = warm_l2(reinterpret_cast<const double *>(a[0]), 2, m, lmax);
-    const double warm_al = warm_l2(al, 1, m, lmax);
+    for (int k = 0; k < M; ++k) a[k] = ro(A.ap + (int64_t)min(map0 + k, nmaps - 1) * A.nalm + base);
+    const double warm_a = warm_l2(reinterpret_cast<const double *>(A.ap + (int64_t)map0 * A.nalm + base), 2, m, lmax);
+    const double warm_al = warm_l2(A.alpha + base, 1, m, lmax);
 
     double x[T], q1[T], q2[T], er[T][M], ei[T][M], orr[T][M], oi[T][M];
     int ls[T];
@@ -576,7 +576,7 @@ __device__ __forceinline__ void ana_group(const AnaArgs &A, int m, int grp, int 
     const int lmax = A.lmax;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
-    const double *__restrict__ al = A.alpha + base;
+    const const_ptr<double> al = ro(A.alpha + base);
     const double2 *__restrict__ d = A.delta + (int64_t)map * A.nrings * (A.mmax + 1);
     double2 *__restrict__ dst = (groups == 1) ? A.alm + (int64_t)map * A.nalm + base
                                               : A.part + ((int64_t)map * groups + grp) * A.nalm + base;
@@ -687,7 +687,7 @@ __device__ __forceinline__ void ana_wave(const AnaArgs &A, int m, int map, doubl
     const int lmax = A.lmax;
     const int lane = threadIdx.x & 63;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
-    const double *__restrict__ al = A.alpha + base;
+    const const_ptr<double> al = ro(A.alpha + base);
     const double2 *__restrict__ d = A.delta + (int64_t)map * A.nrings * (A.mmax + 1);
     double2 *__restrict__ dst = A.alm + (int64_t)map * A.nalm + base;
     AnaSlots<T> S;
