@@ -24,10 +24,13 @@
 //   X_k = conj(b_k) sum_n (x_n conj(b_n)) b_{k-n},  b_t = e^{i pi t^2/N},
 // as a cyclic convolution of 5-smooth length L >= 2N-1 done with two forward
 // transforms (the filter spectrum, scaled by 1/L, is a plan table).
-#include "sht_internal.h"
+#include "k_device.h"
 
 namespace sht {
 namespace {
+
+// plan descriptors are read through the constant address space (scalar loads)
+using DescP = const_ptr<FftDesc>;
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
     return make_double2(fma(a.x, b.x, -a.y * b.y), fma(a.x, b.y, a.y * b.x));
@@ -322,7 +325,7 @@ __device__ __forceinline__ void fft_stage_generic(double2 *buf, int L, int Ns, i
 
 // Forward FFT of length d->L (<= MAXL) in LDS (natural order in and out).
 template <int MAXL, int NT>
-__device__ __forceinline__ void fft_forward(double2 *buf, const FftDesc *__restrict__ d, TwLds tw) {
+__device__ __forceinline__ void fft_forward(double2 *buf, DescP d, TwLds tw) {
     const int L = d->L, nrad = d->nrad;
     int Ns = 1;
     for (int s = 0; s < nrad; ++s) {
@@ -342,13 +345,13 @@ __device__ __forceinline__ void fft_forward(double2 *buf, const FftDesc *__restr
 // DFT of the n points already placed in buf[0..n) (pre-multiplied by
 // conj(chirp) when Bluestein): afterwards X_k is at_k(buf, d, k).
 template <int MAXL, int NT>
-__device__ __forceinline__ void transform(double2 *buf, const FftDesc *__restrict__ d, TwLds tw) {
+__device__ __forceinline__ void transform(double2 *buf, DescP d, TwLds tw) {
     if (!d->bluestein) {
         fft_forward<MAXL, NT>(buf, d, tw);
         return;
     }
     const int L = d->L;
-    const double2 *kern = d->kern;
+    const double2 *__restrict__ kern = d->kern;
     for (int t = d->n + threadIdx.x; t < L; t += NT) buf[pd(t)] = make_double2(0.0, 0.0);
     __syncthreads();
     fft_forward<MAXL, NT>(buf, d, tw);
@@ -371,13 +374,13 @@ __device__ __forceinline__ double2 chirp_at(int n, int t) {
     return make_double2(cs, sn);
 }
 
-__device__ __forceinline__ double2 result_at(const double2 *buf, const FftDesc *__restrict__ d, int k) {
+__device__ __forceinline__ double2 result_at(const double2 *buf, DescP d, int k) {
     if (!d->bluestein) return buf[pd(k)];
     // X_k = conj(b_k) * conj(y_k), y = conj(second transform)
     return conj2(cmul(chirp_at(d->n, k), buf[pd(k)]));
 }
 
-__device__ __forceinline__ double2 input_point(double2 v, const FftDesc *__restrict__ d, int t) {
+__device__ __forceinline__ double2 input_point(double2 v, DescP d, int t) {
     return d->bluestein ? cmul(v, conj2(chirp_at(d->n, t))) : v;
 }
 
@@ -391,19 +394,22 @@ __device__ __forceinline__ double2 input_point(double2 v, const FftDesc *__restr
 // s_a = Re z, s_b = Im z.  Analysis: z = s_a + i s_b, Z = FFT(z),
 // S_a,k = (Z_k + conj Z_{-k}) / 2, S_b,k = (Z_k - conj Z_{-k}) / (2i).
 
-// c_k of one ring: sum over m = k mod n (m <= mmax) of w_m Delta_m e^{i m phi0}
-__device__ __forceinline__ double2 fold_bin(const double2 *__restrict__ D, int64_t sm, int k, int n, int mmax,
-                                            const Phase &ph) {
-    double cr = 0.0, ci = 0.0;
-    for (int m = k; m <= mmax; m += n) {
-        const double2 dv = D[m * sm];
-        if (m == 0) {
-            cr += dv.x;
-        } else {
-            const double2 e = ph(m);
-            cr += 2.0 * fma(dv.x, e.x, -dv.y * e.y);
-            ci += 2.0 * fma(dv.x, e.y, dv.y * e.x);
-        }
+// w_m Delta_m e^{i m phi0} (w_0 = 1, real part only; w_m = 2)
+__device__ __forceinline__ double2 bin_term(double2 dv, int m, const Phase &ph) {
+    if (m == 0) return make_double2(dv.x, 0.0);
+    const double2 e = ph(m);
+    return make_double2(2.0 * fma(dv.x, e.x, -dv.y * e.y), 2.0 * fma(dv.x, e.y, dv.y * e.x));
+}
+
+// c_k of one ring: sum over m = k mod n (m <= mmax) of w_m Delta_m e^{i m phi0},
+// in increasing m, given the term of m = k (first, zero if k > mmax)
+__device__ __forceinline__ double2 fold_bin(double2 first, const double2 *__restrict__ D, int64_t sm, int k, int n,
+                                            int mmax, const Phase &ph) {
+    double cr = first.x, ci = first.y;
+    for (int m = k + n; m <= mmax; m += n) {
+        const double2 t = bin_term(D[m * sm], m, ph);
+        cr += t.x;
+        ci += t.y;
     }
     return make_double2(cr, ci);
 }
@@ -488,6 +494,45 @@ __device__ __forceinline__ bool job_seqs(int njobs, int nmaps, int map_minor, co
     js = JobSeqs{r, r, ma, ma + 1 < nmaps ? ma + 1 : ma, ma + 1 < nmaps};
     return true;
 }
+// The plan entry and sequences of this workgroup.  BATCH: workgroup b takes
+// entry bjobs[b] = (plan, job) of a batch table (one map; the entry is read
+// with scalar loads); otherwise the kernel argument's plan, with the grid over
+// its jobs and maps as job_seqs.  False: nothing to do.
+template <bool BATCH>
+__device__ __forceinline__ bool ring_task(const RingPlan &one, const RingPlan *plans, const int2 *bjobs,
+                                          RingPlan &P, JobSeqs &js) {
+    if constexpr (BATCH) {
+        const const_ptr<int> bj = ro(reinterpret_cast<const int *>(bjobs)) + 2 * (int64_t)blockIdx.x;
+        const const_ptr<RingPlan> q = ro(plans) + bj[0];
+        P.mmax = q->mmax;
+        P.nmaps = 1;
+        P.njobs = q->njobs;
+        P.fold_rows = q->fold_rows;
+        P.ph_tab = q->ph_tab;
+        P.npix = q->npix;
+        P.dl.s_map = q->dl.s_map;
+        P.dl.s_ring = q->dl.s_ring;
+        P.dl.s_m = q->dl.s_m;
+        P.dl.map_minor = 0;
+        P.jobs = q->jobs;
+        P.ring_desc = q->ring_desc;
+        P.descs = q->descs;
+        P.phi0 = q->phi0;
+        P.weight = q->weight;
+        P.ofs = q->ofs;
+        P.din = q->din;
+        P.mout = q->mout;
+        P.min = q->min;
+        P.dout = q->dout;
+        const const_ptr<int> job = ro(reinterpret_cast<const int *>(P.jobs)) + 2 * (int64_t)bj[1];
+        const int a = job[0], b = job[1];
+        js = JobSeqs{a, b >= 0 ? b : a, 0, 0, b >= 0};
+        return true;
+    } else {
+        P = one;
+        return job_seqs(P.njobs, P.nmaps, P.dl.map_minor, P.jobs, js);
+    }
+}
 // workgroups of one class launch: njobs * nmaps, or for map-minor Delta 32 per
 // 8 units of (job, ring of the job, 8 maps)
 inline int64_t fft_grid(int njobs, int nmaps, int map_minor) {
@@ -499,29 +544,25 @@ inline int64_t fft_grid(int njobs, int nmaps, int map_minor) {
 // Synthesis.  LDS: the twiddle tables, buf[L], plus (fold_rows != 0) two
 // rows of mmax+1 phased terms used when the ring folds many m per bin,
 // n < (mmax+1)/2.
-template <int MAXL, int NT>
-__global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int njobs, int64_t npix, int nmaps, DeltaLayout dl,
-                                                int fold_rows, int ph_tab,
-                                                const int2 *__restrict__ jobs,
-                                                const int32_t *__restrict__ ring_desc,
-                                                const FftDesc *__restrict__ descs,
-                                                const double *__restrict__ phi0,
-                                                const int64_t *__restrict__ ofs,
-                                                const double2 *__restrict__ delta,
-                                                double *__restrict__ map) {
+template <int MAXL, int NT, bool BATCH>
+__global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan *__restrict__ plans,
+                                                   const int2 *__restrict__ bjobs) {
     extern __shared__ double2 lds[];
     double2 *tlo = lds, *thi = lds + kTwLo, *buf = lds + tw_entries<MAXL>();
+    RingPlan P;
     JobSeqs js;
-    if (!job_seqs(njobs, nmaps, dl.map_minor, jobs, js)) return;  // whole workgroup
+    if (!ring_task<BATCH>(one, plans, bjobs, P, js)) return;  // whole workgroup
+    const int mmax = P.mmax, fold_rows = P.fold_rows;
+    const DeltaLayout dl = P.dl;
     const bool two = js.two;
-    const FftDesc *d = descs + ring_desc[js.ra];
+    const DescP d = ro(P.descs) + P.ring_desc[js.ra];
     const int N = d->n, L = d->L;
     load_twiddles<NT>(tlo, thi, d->tw, L);
-    const double2 *__restrict__ Da = delta + js.ma * dl.s_map + js.ra * dl.s_ring;
-    const double2 *__restrict__ Db = delta + js.mb * dl.s_map + js.rb * dl.s_ring;
-    const double pa = phi0[js.ra], pb = phi0[js.rb];
+    const double2 *__restrict__ Da = P.din + js.ma * dl.s_map + js.ra * dl.s_ring;
+    const double2 *__restrict__ Db = P.din + js.mb * dl.s_map + js.rb * dl.s_ring;
+    const double pa = P.phi0[js.ra], pb = P.phi0[js.rb];
     Phase pha{nullptr, nullptr, pa}, phb{nullptr, nullptr, pb};
-    if (ph_tab) {
+    if (P.ph_tab) {
         double2 *tab = buf + padded_len<MAXL>() + (fold_rows ? 2 * (mmax + 1) : 0);
         pha = load_phases<NT>(tab, mmax, pa);
         phb = pha;
@@ -542,26 +583,12 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int njobs, int64_t npi
             __syncthreads();
         }
     }
-    // thread handles the bin pair (k, n-k), k = 0..n/2
-    for (int k = threadIdx.x; 2 * k <= N; k += NT) {
+    // thread handles the bin pairs (k, n-k), k = threadIdx.x + u NT <= n/2:
+    // u < U for every thread, and k = U NT (only when n = MAXL) by thread 0
+    constexpr int U = MAXL / (2 * NT);
+    const double2 z = make_double2(0.0, 0.0);
+    auto put = [&](int k, double2 a0, double2 a1, double2 b0, double2 b1) {
         const int kn = (N - k) % N;
-        double2 a0, a1, b0 = make_double2(0.0, 0.0), b1 = make_double2(0.0, 0.0);
-        if (lds_fold) {
-            const double2 *ta = buf + pd(L), *tb = buf + pd(L) + (mmax + 1);
-            a0 = fold_terms(ta, k, N, lim);
-            a1 = fold_terms(ta, kn, N, lim);
-            if (two) {
-                b0 = fold_terms(tb, k, N, lim);
-                b1 = fold_terms(tb, kn, N, lim);
-            }
-        } else {
-            a0 = fold_bin(Da, dl.s_m, k, N, mmax, pha);
-            a1 = fold_bin(Da, dl.s_m, kn, N, mmax, pha);
-            if (two) {
-                b0 = fold_bin(Db, dl.s_m, k, N, mmax, phb);
-                b1 = fold_bin(Db, dl.s_m, kn, N, mmax, phb);
-            }
-        }
         // h_k = (c_k + conj c_{n-k}) / 2, h_{n-k} = conj h_k
         const double2 ha = make_double2(0.5 * (a0.x + a1.x), 0.5 * (a0.y - a1.y));
         const double2 hb = make_double2(0.5 * (b0.x + b1.x), 0.5 * (b0.y - b1.y));
@@ -570,11 +597,60 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int njobs, int64_t npi
         const double2 gn = make_double2(ha.x + hb.y, -ha.y + hb.x);  // h_a* + i h_b* at n-k
         buf[pd(k)] = input_point(conj2(gk), d, k);
         if (kn != k) buf[pd(kn)] = input_point(conj2(gn), d, kn);
+    };
+    // the four folded bins of one k: c_a(k), c_a(n-k), c_b(k), c_b(n-k)
+    auto bins = [&](int k, double2 &a0, double2 &a1, double2 &b0, double2 &b1) {
+        const int kn = (N - k) % N;
+        if (lds_fold) {
+            const double2 *ta = buf + pd(L), *tb = buf + pd(L) + (mmax + 1);
+            a0 = fold_terms(ta, k, N, lim);
+            a1 = fold_terms(ta, kn, N, lim);
+            b0 = two ? fold_terms(tb, k, N, lim) : z;
+            b1 = two ? fold_terms(tb, kn, N, lim) : z;
+        } else {
+            // a0..b1 hold the first Delta of each bin (m = k, m = n-k) on entry
+            a0 = fold_bin(k <= mmax ? bin_term(a0, k, pha) : z, Da, dl.s_m, k, N, mmax, pha);
+            a1 = fold_bin(kn <= mmax ? bin_term(a1, kn, pha) : z, Da, dl.s_m, kn, N, mmax, pha);
+            b0 = two ? fold_bin(k <= mmax ? bin_term(b0, k, phb) : z, Db, dl.s_m, k, N, mmax, phb) : z;
+            b1 = two ? fold_bin(kn <= mmax ? bin_term(b1, kn, phb) : z, Db, dl.s_m, kn, N, mmax, phb) : z;
+        }
+    };
+    auto first = [&](int k, double2 &a0, double2 &a1, double2 &b0, double2 &b1) {
+        const int kn = (N - k) % N;
+        const bool ok = !lds_fold && 2 * k <= N;
+        a0 = (ok && k <= mmax) ? Da[k * dl.s_m] : z;
+        a1 = (ok && kn <= mmax) ? Da[kn * dl.s_m] : z;
+        b0 = (ok && two && k <= mmax) ? Db[k * dl.s_m] : z;
+        b1 = (ok && two && kn <= mmax) ? Db[kn * dl.s_m] : z;
+    };
+    // the first Delta of each of G bins of this thread is loaded before any
+    // is used (all loads in flight together); aliases m + n <= mmax after
+    constexpr int G = U < 2 ? U : 2;  // registers: 16 per bin
+    static_assert(U % G == 0, "whole groups of bins");
+#pragma unroll
+    for (int u0 = 0; u0 < U; u0 += G) {
+        double2 a0[G], a1[G], b0[G], b1[G];
+#pragma unroll
+        for (int u = 0; u < G; ++u) first(threadIdx.x + (u0 + u) * NT, a0[u], a1[u], b0[u], b1[u]);
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const int k = threadIdx.x + (u0 + u) * NT;
+            if (2 * k <= N) {
+                bins(k, a0[u], a1[u], b0[u], b1[u]);
+                put(k, a0[u], a1[u], b0[u], b1[u]);
+            }
+        }
+    }
+    if (threadIdx.x == 0 && 2 * U * NT <= N) {
+        double2 a0, a1, b0, b1;
+        first(U * NT, a0, a1, b0, b1);
+        bins(U * NT, a0, a1, b0, b1);
+        put(U * NT, a0, a1, b0, b1);
     }
     __syncthreads();
     transform<MAXL, NT>(buf, d, TwLds{tlo, thi});
-    double *outa = map + (int64_t)js.ma * npix + ofs[js.ra];
-    double *outb = map + (int64_t)js.mb * npix + ofs[js.rb];
+    double *outa = P.mout + (int64_t)js.ma * P.npix + P.ofs[js.ra];
+    double *outb = P.mout + (int64_t)js.mb * P.npix + P.ofs[js.rb];
     for (int j = threadIdx.x; j < N; j += NT) {
         const double2 z = result_at(buf, d, j);  // FFT(conj g)_j; IDFT(g)_j = conj of it
         outa[j] = z.x;
@@ -582,42 +658,50 @@ __global__ __launch_bounds__(NT) void k_fft_syn(int mmax, int njobs, int64_t npi
     }
 }
 
-template <int MAXL, int NT>
-__global__ __launch_bounds__(NT) void k_fft_ana(int mmax, int njobs, int64_t npix, int nmaps, DeltaLayout dl, int ph_tab,
-                                                const int2 *__restrict__ jobs,
-                                                const int32_t *__restrict__ ring_desc,
-                                                const FftDesc *__restrict__ descs,
-                                                const double *__restrict__ phi0,
-                                                const double *__restrict__ weight,
-                                                const int64_t *__restrict__ ofs,
-                                                const double *__restrict__ map,
-                                                double2 *__restrict__ delta) {
+template <int MAXL, int NT, bool BATCH>
+__global__ __launch_bounds__(NT, 4) void k_fft_ana(RingPlan one, const RingPlan *__restrict__ plans,
+                                                   const int2 *__restrict__ bjobs) {
     extern __shared__ double2 lds[];
     double2 *tlo = lds, *thi = lds + kTwLo, *buf = lds + tw_entries<MAXL>();
+    RingPlan P;
     JobSeqs js;
-    if (!job_seqs(njobs, nmaps, dl.map_minor, jobs, js)) return;  // whole workgroup
+    if (!ring_task<BATCH>(one, plans, bjobs, P, js)) return;  // whole workgroup
+    const int mmax = P.mmax;
+    const DeltaLayout dl = P.dl;
     const bool two = js.two;
-    const FftDesc *d = descs + ring_desc[js.ra];
+    const DescP d = ro(P.descs) + P.ring_desc[js.ra];
     const int N = d->n;
     load_twiddles<NT>(tlo, thi, d->tw, d->L);
-    const double pa = phi0[js.ra], wa = weight[js.ra];
-    const double pb = phi0[js.rb], wb = weight[js.rb];
+    const double pa = P.phi0[js.ra], wa = P.weight[js.ra];
+    const double pb = P.phi0[js.rb], wb = P.weight[js.rb];
     // phase tables: visible after the barrier that follows the input below
     Phase pha{nullptr, nullptr, pa}, phb{nullptr, nullptr, pb};
-    if (ph_tab) {
+    if (P.ph_tab) {
         double2 *tab = buf + padded_len<MAXL>();
         pha = load_phases<NT>(tab, mmax, pa);
         phb = pha;
         if (two && js.rb != js.ra) phb = load_phases<NT>(tab + kPhLo + phase_hi_entries(mmax), mmax, pb);
     }
-    const double *ina = map + (int64_t)js.ma * npix + ofs[js.ra];
-    const double *inb = map + (int64_t)js.mb * npix + ofs[js.rb];
-    for (int j = threadIdx.x; j < N; j += NT)
-        buf[pd(j)] = input_point(make_double2(ina[j], two ? inb[j] : 0.0), d, j);
+    const double *ina = P.min + (int64_t)js.ma * P.npix + P.ofs[js.ra];
+    const double *inb = P.min + (int64_t)js.mb * P.npix + P.ofs[js.rb];
+    // every pixel of this thread is loaded before any is used (N <= MAXL)
+    constexpr int U = MAXL / NT;
+    double va[U], vb[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = threadIdx.x + u * NT;
+        va[u] = j < N ? ina[j] : 0.0;
+        vb[u] = (two && j < N) ? inb[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int j = threadIdx.x + u * NT;
+        if (j < N) buf[pd(j)] = input_point(make_double2(va[u], vb[u]), d, j);
+    }
     __syncthreads();
     transform<MAXL, NT>(buf, d, TwLds{tlo, thi});
-    double2 *Da = delta + js.ma * dl.s_map + js.ra * dl.s_ring;
-    double2 *Db = delta + js.mb * dl.s_map + js.rb * dl.s_ring;
+    double2 *Da = P.dout + js.ma * dl.s_map + js.ra * dl.s_ring;
+    double2 *Db = P.dout + js.mb * dl.s_map + js.rb * dl.s_ring;
     for (int m = threadIdx.x; m <= mmax; m += NT) {
         const int k = m % N, kn = (N - k) % N;
         const double2 Z = result_at(buf, d, k), Zn = result_at(buf, d, kn);
@@ -645,10 +729,11 @@ constexpr int kMaxLds = 160 * 1024;  // LDS bytes per workgroup on gfx950
 template <int MAXL>
 int allow_max_lds() {
     constexpr int NT = fft_threads<MAXL>();
-    SHT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_syn<MAXL, NT>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds));
-    SHT_HIP(hipFuncSetAttribute(reinterpret_cast<const void *>(&k_fft_ana<MAXL, NT>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds));
+    const void *fns[] = {reinterpret_cast<const void *>(&k_fft_syn<MAXL, NT, false>),
+                         reinterpret_cast<const void *>(&k_fft_ana<MAXL, NT, false>),
+                         reinterpret_cast<const void *>(&k_fft_syn<MAXL, NT, true>),
+                         reinterpret_cast<const void *>(&k_fft_ana<MAXL, NT, true>)};
+    for (const void *f : fns) SHT_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLds));
     return SHT_OK;
 }
 
@@ -679,33 +764,40 @@ int phase_tables_fit(int mmax, size_t lds) {
     return phase_hi_entries(mmax) <= kPhHiMax && lds + phase_table_bytes(mmax) <= (size_t)kMaxLds;
 }
 
+// LDS bytes and layout flags of class MAXL for a plan of this mmax
 template <int MAXL>
-int launch_syn_class(const GeomPlan &p, int c, int mmax, const void *delta, DeltaLayout dl, double *map, int nmaps,
-                     hipStream_t st) {
-    constexpr int NT = fft_threads<MAXL>();
+size_t class_lds(int mmax, bool synthesis, int *fold_rows, int *ph_tab) {
     const size_t base = (size_t)(tw_entries<MAXL>() + padded_len<MAXL>()) * sizeof(double2);
     const size_t rows = 2 * (size_t)(mmax + 1) * sizeof(double2);
-    // the small-length class keeps the phased terms in LDS when they fit
-    const int fold_rows = (MAXL <= 1024 && base + rows <= kMaxLds) ? 1 : 0;
-    size_t lds = base + (fold_rows ? rows : 0);
-    const int ph_tab = phase_tables_fit(mmax, lds);
-    if (ph_tab) lds += phase_table_bytes(mmax);
-    hipLaunchKernelGGL((k_fft_syn<MAXL, NT>), dim3((unsigned)fft_grid(p.class_count[c], nmaps, dl.map_minor)),
-                       dim3(NT), lds, st, mmax, p.class_count[c], p.npix, nmaps, dl, fold_rows, ph_tab, p.class_jobs[c], p.ring_desc, p.descs, p.phi0,
-                       p.ofs, static_cast<const double2 *>(delta), map);
-    return SHT_OK;
+    // the small-length class of synthesis keeps the phased terms in LDS when they fit
+    *fold_rows = (synthesis && MAXL <= 1024 && base + rows <= kMaxLds) ? 1 : 0;
+    size_t lds = base + (*fold_rows ? rows : 0);
+    *ph_tab = phase_tables_fit(mmax, lds);
+    if (*ph_tab) lds += phase_table_bytes(mmax);
+    return lds;
 }
 
 template <int MAXL>
-void launch_ana_class(const GeomPlan &p, int c, int mmax, const double *map, void *delta, DeltaLayout dl, int nmaps,
-                      hipStream_t st) {
+void launch_class(const RingPlan &P, int64_t grid, size_t lds, bool synthesis, const RingPlan *plans,
+                  const int2 *bjobs, hipStream_t st) {
     constexpr int NT = fft_threads<MAXL>();
-    size_t lds = (size_t)(tw_entries<MAXL>() + padded_len<MAXL>()) * sizeof(double2);
-    const int ph_tab = phase_tables_fit(mmax, lds);
-    if (ph_tab) lds += phase_table_bytes(mmax);
-    hipLaunchKernelGGL((k_fft_ana<MAXL, NT>), dim3((unsigned)fft_grid(p.class_count[c], nmaps, dl.map_minor)),
-                       dim3(NT), lds, st, mmax, p.class_count[c], p.npix, nmaps, dl, ph_tab, p.class_jobs[c], p.ring_desc, p.descs, p.phi0, p.weight,
-                       p.ofs, map, static_cast<double2 *>(delta));
+    if (plans && synthesis)
+        hipLaunchKernelGGL((k_fft_syn<MAXL, NT, true>), dim3((unsigned)grid), dim3(NT), lds, st, P, plans, bjobs);
+    else if (plans)
+        hipLaunchKernelGGL((k_fft_ana<MAXL, NT, true>), dim3((unsigned)grid), dim3(NT), lds, st, P, plans, bjobs);
+    else if (synthesis)
+        hipLaunchKernelGGL((k_fft_syn<MAXL, NT, false>), dim3((unsigned)grid), dim3(NT), lds, st, P, plans, bjobs);
+    else
+        hipLaunchKernelGGL((k_fft_ana<MAXL, NT, false>), dim3((unsigned)grid), dim3(NT), lds, st, P, plans, bjobs);
+}
+void launch_class_any(int c, const RingPlan &P, int64_t grid, size_t lds, bool synthesis, const RingPlan *plans,
+                      const int2 *bjobs, hipStream_t st) {
+    switch (c) {
+        case 0: launch_class<1024>(P, grid, lds, synthesis, plans, bjobs, st); break;
+        case 1: launch_class<2048>(P, grid, lds, synthesis, plans, bjobs, st); break;
+        case 2: launch_class<4096>(P, grid, lds, synthesis, plans, bjobs, st); break;
+        default: launch_class<8192>(P, grid, lds, synthesis, plans, bjobs, st); break;
+    }
 }
 
 static_assert(kFftClasses == 4 && kFftClassLen[0] == 1024 && kFftClassLen[3] == kMaxFftLen,
@@ -720,10 +812,31 @@ static bool grid_fits(const GeomPlan &p, int nmaps, int map_minor) {
     return true;
 }
 
-// The length classes are independent: they run concurrently, the largest on
-// the caller's stream and the others on side streams (fork_join).
-// Runs launch(i, stream) for the n classes: concurrently through fork_join,
-// or one after another on st.
+RingPlan ring_plan(const GeomPlan &p, int c, int mmax, int nmaps, DeltaLayout dl, bool synthesis, size_t *lds) {
+    RingPlan P{};
+    P.mmax = mmax;
+    P.nmaps = nmaps;
+    P.njobs = p.class_count[c];
+    P.npix = p.npix;
+    P.dl = dl;
+    P.jobs = p.class_jobs[c];
+    P.ring_desc = p.ring_desc;
+    P.descs = p.descs;
+    P.phi0 = p.phi0;
+    P.weight = p.weight;
+    P.ofs = p.ofs;
+    switch (c) {
+        case 0: *lds = class_lds<1024>(mmax, synthesis, &P.fold_rows, &P.ph_tab); break;
+        case 1: *lds = class_lds<2048>(mmax, synthesis, &P.fold_rows, &P.ph_tab); break;
+        case 2: *lds = class_lds<4096>(mmax, synthesis, &P.fold_rows, &P.ph_tab); break;
+        default: *lds = class_lds<8192>(mmax, synthesis, &P.fold_rows, &P.ph_tab); break;
+    }
+    return P;
+}
+
+// Runs launch(i, stream) for the n classes: concurrently through fork_join
+// (the largest on the caller's stream, the others on side streams), or one
+// after another on st.
 static int each_class(hipStream_t st, int n, bool fork, const std::function<int(int, hipStream_t)> &launch) {
     if (fork) return fork_join(st, n, launch);
     int rc = SHT_OK;
@@ -731,45 +844,50 @@ static int each_class(hipStream_t st, int n, bool fork, const std::function<int(
     return rc;
 }
 
-int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, DeltaLayout dl, double *map, int nmaps,
-                   hipStream_t st, bool fork) {
+static int launch_fft(const GeomPlan &p, int mmax, const void *din, double *mout, const double *min, void *dout,
+                      DeltaLayout dl, int nmaps, bool synthesis, hipStream_t st, bool fork) {
     if (nmaps > 65535 || !grid_fits(p, nmaps, dl.map_minor)) return SHT_EUNSUPPORTED;
+    if (!synthesis && !p.weight) return SHT_EINVAL;
     int rc = set_lds_attr();
     if (rc) return rc;
     int cls[kFftClasses], n = 0;
     for (int c = kFftClasses - 1; c >= 0; --c)
         if (p.class_count[c]) cls[n++] = c;
     return each_class(st, n, fork, [&](int i, hipStream_t s) {
-        switch (cls[i]) {
-            case 0: launch_syn_class<1024>(p, 0, mmax, delta, dl, map, nmaps, s); break;
-            case 1: launch_syn_class<2048>(p, 1, mmax, delta, dl, map, nmaps, s); break;
-            case 2: launch_syn_class<4096>(p, 2, mmax, delta, dl, map, nmaps, s); break;
-            default: launch_syn_class<8192>(p, 3, mmax, delta, dl, map, nmaps, s); break;
-        }
+        const int c = cls[i];
+        size_t lds = 0;
+        RingPlan P = ring_plan(p, c, mmax, nmaps, dl, synthesis, &lds);
+        P.din = static_cast<const double2 *>(din);
+        P.mout = mout;
+        P.min = min;
+        P.dout = static_cast<double2 *>(dout);
+        launch_class_any(c, P, fft_grid(P.njobs, nmaps, dl.map_minor), lds, synthesis, nullptr, nullptr, s);
         SHT_HIP(hipGetLastError());
         return SHT_OK;
     });
 }
 
+int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, DeltaLayout dl, double *map, int nmaps,
+                   hipStream_t st, bool fork) {
+    return launch_fft(p, mmax, delta, map, nullptr, nullptr, dl, nmaps, true, st, fork);
+}
+
 int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, DeltaLayout dl, int nmaps,
                    hipStream_t st, bool fork) {
-    if (nmaps > 65535 || !grid_fits(p, nmaps, dl.map_minor)) return SHT_EUNSUPPORTED;
-    if (!p.weight) return SHT_EINVAL;
+    return launch_fft(p, mmax, nullptr, nullptr, map, delta, dl, nmaps, false, st, fork);
+}
+
+static int launch_batch(const RingBatch &b, bool synthesis, hipStream_t st) {
     int rc = set_lds_attr();
     if (rc) return rc;
-    int cls[kFftClasses], n = 0;
-    for (int c = kFftClasses - 1; c >= 0; --c)
-        if (p.class_count[c]) cls[n++] = c;
-    return each_class(st, n, fork, [&](int i, hipStream_t s) {
-        switch (cls[i]) {
-            case 0: launch_ana_class<1024>(p, 0, mmax, map, delta, dl, nmaps, s); break;
-            case 1: launch_ana_class<2048>(p, 1, mmax, map, delta, dl, nmaps, s); break;
-            case 2: launch_ana_class<4096>(p, 2, mmax, map, delta, dl, nmaps, s); break;
-            default: launch_ana_class<8192>(p, 3, mmax, map, delta, dl, nmaps, s); break;
-        }
+    for (int c = kFftClasses - 1; c >= 0; --c) {
+        if (!b.njobs[c]) continue;
+        launch_class_any(c, RingPlan{}, b.njobs[c], b.lds[c], synthesis, b.plans, b.jobs[c], st);
         SHT_HIP(hipGetLastError());
-        return SHT_OK;
-    });
+    }
+    return SHT_OK;
 }
+int launch_fft_syn_batch(const RingBatch &b, hipStream_t st) { return launch_batch(b, true, st); }
+int launch_fft_ana_batch(const RingBatch &b, hipStream_t st) { return launch_batch(b, false, st); }
 
 }  // namespace sht

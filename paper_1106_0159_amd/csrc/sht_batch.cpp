@@ -133,6 +133,8 @@ struct sht_batch {
     int syn_chunks = 1, comb_chunks = 1;
     int *head = nullptr;
     char *ws = nullptr;
+    // ring stages of all requests: one launch per length class and direction
+    RingBatch ring_ana, ring_syn;
     ~sht_batch() {
         for (void *p : owned) (void)hipFree(p);
         for (ReqPlan &r : q)
@@ -254,6 +256,46 @@ int sht_batch_create(int nreq, const sht_request *reqs, void *workspace, size_t 
         (rc = upload_vec(b.get(), syn_list, &b->syn_list)) || (rc = upload_vec(b.get(), comb_list, &b->comb_list)) ||
         (rc = leg_batch_grid(&b->grid)))
         return rc;
+    // ring stages: a plan entry per (request, length class), and per class and
+    // direction the list of (entry, job) of every request
+    std::vector<RingPlan> rplans;
+    std::vector<int2> rjobs[2][kFftClasses];  // [0] analysis, [1] synthesis
+    size_t rlds[2][kFftClasses] = {};
+    for (size_t i = 0; i < b->q.size(); ++i) {
+        const ReqPlan &q = b->q[i];
+        const bool syn = q.r.kind == SHT_ALM2MAP;
+        const DeltaLayout dl = delta_layout(q.h.nrings, q.r.mmax, 1, false);
+        for (int c = 0; c < kFftClasses; ++c) {
+            if (!q.p->class_count[c]) continue;
+            size_t lds = 0;
+            RingPlan P = ring_plan(*q.p, c, q.r.mmax, 1, dl, syn, &lds);
+            if (syn) {
+                P.din = reinterpret_cast<const double2 *>(b->ws + q.delta_off);
+                P.mout = static_cast<double *>(q.r.out);
+            } else {
+                P.min = static_cast<const double *>(q.r.in);
+                P.dout = reinterpret_cast<double2 *>(b->ws + q.delta_off);
+            }
+            const int e = (int)rplans.size();
+            rplans.push_back(P);
+            rlds[syn][c] = std::max(rlds[syn][c], lds);
+            for (int j = 0; j < q.p->class_count[c]; ++j) rjobs[syn][c].push_back(make_int2(e, j));
+        }
+    }
+    RingPlan *dplans = nullptr;
+    if ((rc = upload_vec(b.get(), rplans, &dplans))) return rc;
+    for (int dir = 0; dir < 2; ++dir) {
+        RingBatch &rb = dir ? b->ring_syn : b->ring_ana;
+        rb.plans = dplans;
+        for (int c = 0; c < kFftClasses; ++c) {
+            if (rjobs[dir][c].size() >= (size_t)INT32_MAX) return SHT_EUNSUPPORTED;
+            rb.njobs[c] = (int)rjobs[dir][c].size();
+            rb.lds[c] = rlds[dir][c];
+            int2 *dj = nullptr;
+            if (rb.njobs[c] && (rc = upload_vec(b.get(), rjobs[dir][c], &dj))) return rc;
+            rb.jobs[c] = dj;
+        }
+    }
     *out = b.release();
     return SHT_OK;
 }
@@ -267,25 +309,14 @@ int sht_batch_run(sht_batch *b, void *stream) {
     int rc;
     // ring analysis of the map2alm requests (Delta^S), then the Legendre stage
     // of every request in one persistent launch, then the ring synthesis of
-    // the alm2map requests
-    for (const ReqPlan &q : b->q) {
-        if (q.r.kind != SHT_MAP2ALM) continue;
-        DeltaLayout dl = delta_layout(q.h.nrings, q.r.mmax, 1, false);
-        if ((rc = launch_fft_ana(*q.p, q.r.mmax, static_cast<const double *>(q.r.in), b->ws + q.delta_off, dl, 1, st,
-                                 false)))
-            return rc;
-    }
-    if ((rc = launch_prescale_batch(b->reqs, b->syn_list, b->nsyn, b->syn_chunks, st)) ||
+    // the alm2map requests; each ring stage one launch per length class over
+    // the jobs of every request
+    if ((rc = launch_fft_ana_batch(b->ring_ana, st)) ||
+        (rc = launch_prescale_batch(b->reqs, b->syn_list, b->nsyn, b->syn_chunks, st)) ||
         (rc = launch_leg_batch(b->reqs, b->items, b->nitems, b->head, b->grid, st)) ||
-        (rc = launch_combine_batch(b->reqs, b->comb_list, b->ncomb, b->comb_chunks, st)))
+        (rc = launch_combine_batch(b->reqs, b->comb_list, b->ncomb, b->comb_chunks, st)) ||
+        (rc = launch_fft_syn_batch(b->ring_syn, st)))
         return rc;
-    for (const ReqPlan &q : b->q) {
-        if (q.r.kind != SHT_ALM2MAP) continue;
-        DeltaLayout dl = delta_layout(q.h.nrings, q.r.mmax, 1, false);
-        if ((rc = launch_fft_syn(*q.p, q.r.mmax, b->ws + q.delta_off, dl, static_cast<double *>(q.r.out), 1, st,
-                                 false)))
-            return rc;
-    }
     return SHT_OK;
 }
 

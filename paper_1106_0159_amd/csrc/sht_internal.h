@@ -178,6 +178,26 @@ inline DeltaLayout alm2map_layout(int nrings, int mmax, int nmaps, uint32_t flag
     return delta_layout(nrings, mmax, nmaps, (flags & SHT_MIXED) != 0 && nmaps >= 8);
 }
 
+// One length class of one plan's ring stage as the ring kernels read it: a
+// kernel argument for a single call, or an entry of a batch's device table
+// (the jobs of every request and class in one launch per class).  Ring-major
+// Delta unless dl.map_minor; nmaps maps per job (1 in batches).  fold_rows
+// and ph_tab: the LDS layout of this entry (rows of phased terms, phase tables).
+struct RingPlan {
+    int mmax, nmaps, njobs, fold_rows, ph_tab;
+    int64_t npix;
+    DeltaLayout dl;
+    const int2 *jobs;          // [njobs] (ring a, ring b or -1) of this class
+    const int32_t *ring_desc;  // [nrings] index into descs
+    const FftDesc *descs;
+    const double *phi0, *weight;
+    const int64_t *ofs;
+    const double2 *din;  // synthesis: Delta read
+    double *mout;        // synthesis: map written
+    const double *min;   // analysis: map read
+    double2 *dout;       // analysis: Delta written
+};
+
 // Validated, normalised copy of the caller's geometry.
 struct HostGeom {
     int nrings = 0;
@@ -318,6 +338,21 @@ int launch_fft_syn(const GeomPlan &p, int mmax, const void *delta, DeltaLayout d
                    hipStream_t st, bool fork = true);
 int launch_fft_ana(const GeomPlan &p, int mmax, const double *map, void *delta, DeltaLayout dl, int nmaps,
                    hipStream_t st, bool fork = true);
+
+// Ring stages of a batch: for each length class c, one launch over the
+// entries `jobs[c]` = (plan index into `plans`, job index of that plan),
+// with the LDS bytes the largest entry of the class needs.
+struct RingBatch {
+    const RingPlan *plans = nullptr;  // device table
+    const int2 *jobs[kFftClasses] = {nullptr, nullptr, nullptr, nullptr};
+    int njobs[kFftClasses] = {0, 0, 0, 0};
+    size_t lds[kFftClasses] = {0, 0, 0, 0};
+};
+// Host side: the RingPlan of class c of plan p for a call (din/mout or
+// min/dout filled by the caller), and the LDS bytes it needs.
+RingPlan ring_plan(const GeomPlan &p, int c, int mmax, int nmaps, DeltaLayout dl, bool synthesis, size_t *lds);
+int launch_fft_syn_batch(const RingBatch &b, hipStream_t st);
+int launch_fft_ana_batch(const RingBatch &b, hipStream_t st);
 
 // sht_alm2map's host-side validation (sizes, flags, geometry, alm and map
 // pointers); sets the workspace bytes the call needs.
