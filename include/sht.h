@@ -93,9 +93,9 @@ enum sht_flags {
      * north +- south Delta_m of a ring pair (analysis), and the per-m matrix
      * products of Sec. 3 (eq. matrix_vec and its transpose, one column per
      * map and real/imaginary part) run on the FP32 matrix cores: synthesis
-     * sums over l in FP32 (above lmax 2048 in two chains, the lower and the
-     * upper half of the l range, added in FP64); analysis sums 32 l at a time
-     * over up to 256 ring pairs in FP32 and adds those sums in FP64.  The
+     * sums over l in FP32 (with SHT_MIXED_FP64_SUMS, and above lmax 2048,
+     * 32 l at a time, those block sums added in FP64); analysis sums 32 l at
+     * a time over up to 256 ring pairs in FP32 and adds those sums in FP64.  The
      * Delta and FFT stages stay FP64.  Expected relative RMS error against
      * the FP64 transform: about 1e-7 to 1e-6.  Built for batches: a wave
      * covers 8 to 32 maps in synthesis (8 above lmax 2048) and 8 in analysis,
@@ -118,7 +118,13 @@ enum sht_flags {
      * sht_unpin calls have removed the pins; only sht_shutdown frees pinned
      * tables.  A pinned cache may hold more entries than its limits.  The
      * transforms reject this bit (SHT_EUNSUPPORTED). */
-    SHT_PIN = 4u
+    SHT_PIN = 4u,
+    /* With SHT_MIXED only (alone: SHT_EUNSUPPORTED): the synthesis sums each
+     * 32-l block on the matrix cores in a fresh FP32 accumulator and adds the
+     * block sums in FP64 (a compensated l-sum; analysis always does so), so
+     * the FP32 rounding no longer accumulates over the whole l range.  A wave
+     * then covers 8 maps.  Always in effect above lmax 2048. */
+    SHT_MIXED_FP64_SUMS = 8u
 };
 
 /* Bytes of device workspace needed by sht_alm2map, sht_map2alm,

@@ -14,11 +14,14 @@
 // Precision: the recurrence, its seeds, the start table and the coefficients
 // are those of the FP64 kernels and run in FP64.  Each q_lm and each
 // a'_lm = c_lm a_lm is rounded to FP32 once, and the products are summed in
-// FP32 over l by v_mfma_f32_16x16x4_f32.  The ring FFTs stay FP64.
+// FP32 by v_mfma_f32_16x16x4_f32: over all l (one FP32 chain), or, with
+// block sums in FP64 (F64S), over the 32 l of one block in a fresh FP32
+// accumulator whose sum is then added to FP64 totals -- the compensated form
+// of the l-sum, whose error no longer grows with the number of blocks.  The
+// ring FFTs stay FP64.
 //
 // Tiling: a wave owns 64 ring pairs (one recurrence per lane) and 16 NCF
-// columns (NCF = 1, 2, 4; 1 above lmax 2048, where the sum over l runs in two
-// FP32 chains added in FP64) of one m; a workgroup holds four such waves on 256 consecutive
+// columns (NCF = 1, 2, 4) of one m; a workgroup holds four such waves on 256 consecutive
 // pairs with the same columns, and the pair tiles of one m share one XCD's L2
 // (the mapping of the FP64 kernels).  l advances in blocks of kMxL = 32: each
 // lane runs 32 recurrence steps and writes its 16 even and 16 odd q (FP32) to
@@ -75,7 +78,7 @@ __global__ __launch_bounds__(kBlock) void k_prescale_mx(int lmax, int nmaps, int
     }
 }
 
-template <int NCF, int CH>
+template <int NCF, bool F64S>
 __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, int nslots, int tiles, DeltaLayout dl,
                                                         int nmaps, int64_t mxblocks,
                                                         const int64_t *__restrict__ mxofs,
@@ -110,22 +113,32 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
     const float *__restrict__ apm = ap + ((int64_t)cg * mxblocks + mxofs[m]) * kTile;
     const int nb = mx_blocks(lmax, m);
 
-    // CH FP32 accumulator chains: with two, the first half of the l-blocks
-    // and the second are summed apart and added in FP64 at the end (each
-    // chain then sums half the terms, the second only the small tail)
-    floatx4 acc[CH][2][4][NCF];
-#pragma unroll
-    for (int c = 0; c < CH; ++c)
+    // FP32 accumulators of the matrix instructions; with F64S they hold one
+    // block's sum, added to the FP64 totals dsum after the block
+    floatx4 acc[2][4][NCF];
+    double dsum[2][4][F64S ? NCF : 1][4];  // (unused without F64S)
+    auto zero_acc = [&]() {
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
             for (int rf = 0; rf < 4; ++rf)
 #pragma unroll
-                for (int cf = 0; cf < NCF; ++cf) acc[c][p][rf][cf] = floatx4{0.f, 0.f, 0.f, 0.f};
+                for (int cf = 0; cf < NCF; ++cf) acc[p][rf][cf] = floatx4{0.f, 0.f, 0.f, 0.f};
+    };
+    zero_acc();
+    if constexpr (F64S) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int rf = 0; rf < 4; ++rf)
+#pragma unroll
+                for (int cf = 0; cf < NCF; ++cf)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) dsum[p][rf][cf][r] = 0.0;
+    }
 
     double q1 = 0.0, q2 = 0.0;  // a pair carries zeros until it starts
     const int kb0 = lo <= lmax ? (lo - m) / kMxL : nb;
-    const int kb_mid = kb0 + (nb - kb0) / 2;
     // a' operands one block ahead: those of block kb are loaded while block
     // kb - 1 runs (the index is clamped, so the load after the last block
     // re-reads it and stays in bounds)
@@ -197,27 +210,35 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
 #pragma unroll
             for (int rf = 0; rf < 4; ++rf)
                 bv[p][rf] = pt[w][p][rf * 16 + c16][kq];
-        auto mma = [&](floatx4 (&a)[2][4][NCF]) {
 #pragma unroll
-            for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int p = 0; p < 2; ++p)
+            for (int p = 0; p < 2; ++p)
 #pragma unroll
-                    for (int rf = 0; rf < 4; ++rf)
+                for (int rf = 0; rf < 4; ++rf)
 #pragma unroll
-                        for (int cf = 0; cf < NCF; ++cf)
-                            a[p][rf][cf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[p][cf][j], bv[p][rf][j],
-                                                                                a[p][rf][cf], 0, 0, 0);
-        };
-        if constexpr (CH == 2) {
-            if (kb < kb_mid)
-                mma(acc[0]);
-            else
-                mma(acc[CH - 1]);
-        } else {
-            mma(acc[0]);
+                    for (int cf = 0; cf < NCF; ++cf)
+                        acc[p][rf][cf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[p][cf][j], bv[p][rf][j],
+                                                                              acc[p][rf][cf], 0, 0, 0);
+        if constexpr (F64S) {
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int rf = 0; rf < 4; ++rf)
+#pragma unroll
+                    for (int cf = 0; cf < NCF; ++cf)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) dsum[p][rf][cf][r] += (double)acc[p][rf][cf][r];
+            zero_acc();
         }
     }
+    // the l-sum of (parity p, tile rf, column group cf, row r)
+    auto total = [&](int p, int rf, int cf, int r) -> double {
+        if constexpr (F64S)
+            return dsum[p][rf][cf][r];
+        else
+            return (double)acc[p][rf][cf][r];
+    };
 
     // lane l holds rows (columns of the batch) 4 (l / 16) + r, r < 4, i.e. two
     // whole complex values, of ring pair 16 rf + l % 16 in each 16 x 16 tile
@@ -232,14 +253,8 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
             for (int h = 0; h < 2; ++h) {
                 const int map = cg * (NC / 2) + cf * 8 + 2 * kq + h;
                 if (map >= nmaps) continue;
-                double er = 0.0, ei = 0.0, orr = 0.0, oi = 0.0;
-#pragma unroll
-                for (int c = 0; c < CH; ++c) {
-                    er += acc[c][0][rf][cf][2 * h];
-                    ei += acc[c][0][rf][cf][2 * h + 1];
-                    orr += acc[c][1][rf][cf][2 * h];
-                    oi += acc[c][1][rf][cf][2 * h + 1];
-                }
+                const double er = total(0, rf, cf, 2 * h), ei = total(0, rf, cf, 2 * h + 1);
+                const double orr = total(1, rf, cf, 2 * h), oi = total(1, rf, cf, 2 * h + 1);
                 double2 *d = delta + map * dl.s_map + m * dl.s_m;
                 d[rN * dl.s_ring] = make_double2(er + orr, ei + oi);
                 if (rS >= 0) d[rS * dl.s_ring] = make_double2(er - orr, ei - oi);
@@ -449,7 +464,7 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
     }
 }
 
-template <int NCF, int CH>
+template <int NCF, bool F64S>
 int launch_syn_mx_t(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm, void *aprime,
                     void *delta, DeltaLayout dl, int nmaps, hipStream_t st) {
     constexpr int NC = 16 * NCF;
@@ -461,7 +476,7 @@ int launch_syn_mx_t(const CoefTables &c, const GeomPlan &p, const StartTable &s,
                        dim3(kBlock), 0, st, c.lmax, nmaps, c.nalm, c.mxblocks, c.mxofs,
                        static_cast<const double2 *>(alm), c.cfac, static_cast<float *>(aprime));
     SHT_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_leg_syn_mx<NCF, CH>), dim3((unsigned)gx, (unsigned)ncg), dim3(kBlock), 0, st, c.lmax, c.mmax,
+    hipLaunchKernelGGL((k_leg_syn_mx<NCF, F64S>), dim3((unsigned)gx, (unsigned)ncg), dim3(kBlock), 0, st, c.lmax, c.mmax,
                        p.nslots, tiles, dl, nmaps, c.mxblocks, c.mxofs, static_cast<const float *>(aprime),
                        c.alpha, s.lstart, s.state, p.slot_x, p.slot_north, p.slot_south,
                        static_cast<double2 *>(delta));
@@ -486,30 +501,32 @@ int launch_leg_ana_mx(const CoefTables &c, const GeomPlan &p, const StartTable &
     return groups > 1 ? launch_ana_combine(c, nmaps, groups, partials, alm, st) : SHT_OK;
 }
 
-// Above kMxOneChainLmax synthesis sums in two chains (the FP32 error of one
-// chain over more l would pass the 1e-6 target), which needs the accumulator
-// registers of two column groups: 8 maps per wave then (16 would spill).
+// Block sums in FP64 (the compensated l-sum) with SHT_MIXED_FP64_SUMS, and
+// always above kMxOneChainLmax, where one FP32 chain over the l range would
+// pass the 1e-6 target.  The FP64 totals take the registers of three more
+// column groups, so such a wave covers 8 maps.
 constexpr int kMxOneChainLmax = 2048;
-int mx_col_frags(int nmaps, int lmax) {
-    if (lmax > kMxOneChainLmax) return 1;
+bool mx_f64_sums(int lmax, uint32_t flags) { return lmax > kMxOneChainLmax || (flags & SHT_MIXED_FP64_SUMS); }
+int mx_col_frags(int nmaps, int lmax, uint32_t flags) {
+    if (mx_f64_sums(lmax, flags)) return 1;
     return nmaps <= 8 ? 1 : nmaps <= 16 ? 2 : 4;
 }
 
-size_t mx_aprime_bytes(int lmax, int mmax, int nmaps) {
+size_t mx_aprime_bytes(int lmax, int mmax, int nmaps, uint32_t flags) {
     int64_t blocks = 0;
     for (int m = 0; m <= mmax; ++m) blocks += mx_blocks(lmax, m);
-    const int nc = 16 * mx_col_frags(nmaps, lmax);
+    const int nc = 16 * mx_col_frags(nmaps, lmax, flags);
     const int64_t ncg = (nmaps + nc / 2 - 1) / (nc / 2);
     return (size_t)(ncg * blocks * 2 * nc * kMxHalf) * sizeof(float);
 }
 
 int launch_leg_syn_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm, void *aprime,
-                      void *delta, DeltaLayout dl, int nmaps, hipStream_t st) {
-    if (c.lmax > kMxOneChainLmax) return launch_syn_mx_t<1, 2>(c, p, s, alm, aprime, delta, dl, nmaps, st);
-    switch (mx_col_frags(nmaps, c.lmax)) {
-        case 1: return launch_syn_mx_t<1, 1>(c, p, s, alm, aprime, delta, dl, nmaps, st);
-        case 2: return launch_syn_mx_t<2, 1>(c, p, s, alm, aprime, delta, dl, nmaps, st);
-        default: return launch_syn_mx_t<4, 1>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+                      void *delta, DeltaLayout dl, int nmaps, uint32_t flags, hipStream_t st) {
+    if (mx_f64_sums(c.lmax, flags)) return launch_syn_mx_t<1, true>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+    switch (mx_col_frags(nmaps, c.lmax, flags)) {
+        case 1: return launch_syn_mx_t<1, false>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+        case 2: return launch_syn_mx_t<2, false>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+        default: return launch_syn_mx_t<4, false>(c, p, s, alm, aprime, delta, dl, nmaps, st);
     }
 }
 

@@ -15,7 +15,7 @@ using namespace sht;
 
 namespace {
 
-constexpr uint32_t kKnownFlags = SHT_MIXED | SHT_DELTA_MAP_MINOR;
+constexpr uint32_t kKnownFlags = SHT_MIXED | SHT_DELTA_MAP_MINOR | SHT_MIXED_FP64_SUMS;
 
 size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -37,7 +37,7 @@ size_t partial_bytes(int lmax, int mmax, int nslots, int nmaps) {
     return G > 1 ? (size_t)G * alm_bytes(lmax, mmax, nmaps) : 0;
 }
 size_t aux_bytes(int lmax, int mmax, int nslots, int nmaps, uint32_t flags) {
-    const size_t syn = (flags & SHT_MIXED) ? mx_aprime_bytes(lmax, mmax, nmaps)
+    const size_t syn = (flags & SHT_MIXED) ? mx_aprime_bytes(lmax, mmax, nmaps, flags)
                                            : alm_bytes(lmax, mmax, nmaps) + 16u * kCoefPad;
     return std::max(round256(syn), round256(partial_bytes(lmax, mmax, nslots, nmaps)));
 }
@@ -71,6 +71,7 @@ int check_common(int lmax, int mmax, const sht_geom *g, int nmaps, uint32_t flag
     int rc = validate_sizes(lmax, mmax, nmaps);
     if (rc) return rc;
     if (flags & ~kKnownFlags) return SHT_EUNSUPPORTED;
+    if ((flags & SHT_MIXED_FP64_SUMS) && !(flags & SHT_MIXED)) return SHT_EUNSUPPORTED;
     return validate_geom(g, need_weight, h);
 }
 
@@ -95,7 +96,7 @@ int enqueue_alm2map(const CoefTables &c, const GeomPlan &p, const StartTable &s,
                     void *delta, DeltaLayout dl, double *map, int nmaps, uint32_t flags, hipStream_t st, bool fork) {
     int rc;
     if (flags & SHT_MIXED) {
-        if ((rc = launch_leg_syn_mx(c, p, s, alm, aprime, delta, dl, nmaps, st))) return rc;
+        if ((rc = launch_leg_syn_mx(c, p, s, alm, aprime, delta, dl, nmaps, flags, st))) return rc;
     } else {
         if ((rc = launch_prescale(c, alm, aprime, nmaps, st))) return rc;
         if ((rc = launch_leg_syn(c, p, s, aprime, delta, nmaps, st))) return rc;
@@ -133,7 +134,7 @@ int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *
         (rc = get_start(*c, p, as_stream(stream), &s)))
         return rc;
     if (flags & SHT_MIXED)
-        rc = launch_leg_syn_mx(*c, *p, *s, alm, workspace, delta, stage_layout(h, mmax, nmaps, flags), nmaps,
+        rc = launch_leg_syn_mx(*c, *p, *s, alm, workspace, delta, stage_layout(h, mmax, nmaps, flags), nmaps, flags,
                                as_stream(stream));
     else if (!(rc = launch_prescale(*c, alm, workspace, nmaps, as_stream(stream))))
         rc = launch_leg_syn(*c, *p, *s, workspace, delta, nmaps, as_stream(stream));

@@ -312,10 +312,10 @@ int launch_leg_ana(const CoefTables &c, const GeomPlan &p, const StartTable &s, 
                    void *alm, int nmaps, void *partials, hipStream_t st);
 // Mixed precision (SHT_MIXED, k_legendre_mx.hip): prescale of a_lm into FP32
 // block tiles of mx_aprime_bytes(...) bytes, then the synthesis contraction.
-int mx_col_frags(int nmaps, int lmax);
-size_t mx_aprime_bytes(int lmax, int mmax, int nmaps);
+int mx_col_frags(int nmaps, int lmax, uint32_t flags);
+size_t mx_aprime_bytes(int lmax, int mmax, int nmaps, uint32_t flags);
 int launch_leg_syn_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm,
-                      void *aprime, void *delta, DeltaLayout dl, int nmaps, hipStream_t st);
+                      void *aprime, void *delta, DeltaLayout dl, int nmaps, uint32_t flags, hipStream_t st);
 int launch_leg_ana_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *delta,
                       DeltaLayout dl, void *alm, int nmaps, void *partials, hipStream_t st);
 // Uneven batches: the persistent Legendre kernel over the items (queue head

@@ -87,16 +87,20 @@ def test_workspace_bytes_mixed():
     r256 = lambda b: (b + 255) // 256 * 256
     delta = lambda lmax, n: r256(n * g.nrings * (lmax + 1) * 16)
 
-    def tiles(lmax, nmaps):
+    def tiles(lmax, nmaps, f64_sums=False):
         blocks = sum((lmax - m + 32) // 32 for m in range(lmax + 1))
         ncf = 1 if nmaps <= 8 else 2 if nmaps <= 16 else 4
-        if lmax > 2048:  # two accumulator chains: 8 maps per wave
+        if lmax > 2048 or f64_sums:  # FP64 block sums: 8 maps per wave
             ncf = 1
         ncg = -(-nmaps // (8 * ncf))
         return ncg * blocks * 2 * (16 * ncf) * 16 * 4
 
     for lmax, nmaps in [(16, 1), (16, 3), (16, 12), (16, 20), (16, 40), (70, 33), (0, 1), (2048, 40), (2049, 40)]:
         assert _ws(lmax, lmax, g, nmaps, sht.SHT_MIXED) == delta(lmax, nmaps) + r256(tiles(lmax, nmaps)), (lmax, nmaps)
+        assert (_ws(lmax, lmax, g, nmaps, sht.SHT_MIXED | sht.SHT_MIXED_FP64_SUMS) ==
+                delta(lmax, nmaps) + r256(tiles(lmax, nmaps, True))), (lmax, nmaps)
+    # the FP64-sums bit needs SHT_MIXED
+    assert _ws(16, 16, g, 1, sht.SHT_MIXED_FP64_SUMS) == 0
     # the Delta layout flag does not change the workspace
     for nmaps in (1, 20):
         assert _ws(16, 16, g, nmaps, sht.SHT_MIXED | sht.SHT_DELTA_MAP_MINOR) == _ws(16, 16, g, nmaps, sht.SHT_MIXED)
@@ -106,7 +110,7 @@ def test_workspace_bytes_mixed():
 
 
 @pytest.mark.parametrize("args", [
-    (-1, 0, 1, 0), (4, 5, 1, 0), (4, -1, 1, 0), (4, 4, 0, 0), (4, 4, 1, 1 << 3),
+    (-1, 0, 1, 0), (4, 5, 1, 0), (4, -1, 1, 0), (4, 4, 0, 0), (4, 4, 1, 1 << 3), (4, 4, 1, 1 << 4),
 ])
 def test_workspace_bytes_invalid(args):
     lmax, mmax, nmaps, flags = args

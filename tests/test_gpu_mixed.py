@@ -226,6 +226,32 @@ def test_mixed_full_size_healpix1024_lmax2048_64maps(sht):
         assert relrms(bi, ref) <= MX_TOL, (i, relrms(bi, ref))
 
 
+def test_mixed_fp64_block_sums_healpix1024_lmax2048(sht):
+    """SHT_MIXED_FP64_SUMS: each 32-l block summed on the matrix cores in a
+    fresh FP32 accumulator, the block sums added in FP64 (the compensated
+    form of the synthesis l-sum).  8 power-law maps on HEALPix N_side = 1024
+    at lmax 2048: map 0 against the oracle over every pixel and every map
+    against the FP64 HIP path at 3e-7, below the plain FP32 chain's error."""
+    import torch
+    lmax, nmaps = 2048, 8
+    g = si.healpix(1024)
+    say("mixed alm2map with FP64 block sums: healpix 1024 lmax 2048 nmaps 8")
+    alm = torch.empty((nmaps, si.nalm(lmax, lmax)), dtype=torch.complex128, device="cuda")
+    for i in range(nmaps):
+        alm[i] = dev(si.powerlaw_alm(lmax, lmax, si.config_seed(2, i)))
+    comp = sht.alm2map(alm, g, lmax, flags=sht.SHT_MIXED | sht.SHT_MIXED_FP64_SUMS)
+    plain = sht.alm2map(alm, g, lmax, flags=sht.SHT_MIXED)
+    f64 = sht.alm2map(alm, g, lmax)
+    err0 = relrms(host(comp[0]), oc.config2_map())
+    e_comp = ((comp - f64).norm(dim=1) / f64.norm(dim=1)).cpu().numpy()
+    e_plain = ((plain - f64).norm(dim=1) / f64.norm(dim=1)).cpu().numpy()
+    say(f"FP64 block sums: map 0 vs oracle {err0:.3e}; vs FP64 max {e_comp.max():.3e} "
+        f"(one FP32 chain: max {e_plain.max():.3e})")
+    assert err0 <= 3e-7
+    assert np.all(e_comp <= 3e-7), e_comp
+    assert e_comp.max() < e_plain.max()
+
+
 def test_mixed_batched_gl1025_lmax1024_64maps(sht):
     """The batched configuration on a Gauss-Legendre grid: 64 power-law maps,
     1025 rings of 2049 points (2049 = 3 x 683: Bluestein), lmax = 1024.  All
@@ -297,8 +323,8 @@ def test_healpix2048_lmax4096_fp64_and_mixed(sht):
     analysis groups and the combine kernel at full size).  FP64 against the
     oracle on every eighth ring (synthesis) and every eighth m (analysis of a
     white-noise map), each set aggregated at 1e-12; a mixed batch of 8 maps
-    against the FP64 path in both directions at 1e-6 (synthesis sums in two
-    FP32 chains above lmax 2048)."""
+    against the FP64 path in both directions: synthesis at 5e-7 (its 32-l
+    block sums are added in FP64 above lmax 2048), analysis at 1e-6."""
     import torch
     lmax, nmaps = 4096, 8
     g = si.healpix(2048)
@@ -344,4 +370,4 @@ def test_healpix2048_lmax4096_fp64_and_mixed(sht):
     back = sht.map2alm(f64, g, lmax, flags=sht.SHT_MIXED)
     err_a = ((back - back64).norm(dim=1) / back64.norm(dim=1)).cpu().numpy()
     say(f"lmax 4096 mixed rel rms: alm2map max {err_s.max():.3e}, map2alm max {err_a.max():.3e}")
-    assert np.all(err_s <= MX_TOL) and np.all(err_a <= MX_TOL), (err_s.max(), err_a.max())
+    assert np.all(err_s <= 5e-7) and np.all(err_a <= MX_TOL), (err_s.max(), err_a.max())
