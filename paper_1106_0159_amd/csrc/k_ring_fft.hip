@@ -196,11 +196,11 @@ __device__ __forceinline__ void butterfly(double2 (&v)[R]) {
 // the tables and its other twiddles as powers of it (at most R - 2 further
 // products, a few ulp for R <= 8).
 constexpr int kTwLo = 64;
-// LDS index of point x: one unused slot after every 8 points, so that the
-// strided Stockham writes of the early stages spread over the banks
-__device__ __forceinline__ int pd(int x) { return x + (x >> 3); }
+// LDS index of point x (unpadded: a slot after every 8 points, meant to
+// spread the strided Stockham writes over the banks, timed slower on gfx950)
+__device__ __forceinline__ int pd(int x) { return x; }
 template <int L>
-constexpr int padded_len() { return L + (L >> 3); }
+constexpr int padded_len() { return L; }
 template <int MAXL>
 constexpr int tw_entries() { return kTwLo + (MAXL + kTwLo - 1) / kTwLo; }
 
@@ -346,18 +346,22 @@ __device__ __forceinline__ void fft_forward(double2 *buf, DescP d, TwLds tw) {
 // conj(chirp) when Bluestein): afterwards X_k is at_k(buf, d, k).
 template <int MAXL, int NT>
 __device__ __forceinline__ void transform(double2 *buf, DescP d, TwLds tw) {
-    if (!d->bluestein) {
-        fft_forward<MAXL, NT>(buf, d, tw);
-        return;
-    }
-    const int L = d->L;
+    // one copy of the stage code for both of Bluestein's transforms (the
+    // kernels are otherwise large enough to thrash the instruction cache)
+    const int L = d->L, passes = d->bluestein ? 2 : 1;
     const double2 *__restrict__ kern = d->kern;
-    for (int t = d->n + threadIdx.x; t < L; t += NT) buf[pd(t)] = make_double2(0.0, 0.0);
-    __syncthreads();
-    fft_forward<MAXL, NT>(buf, d, tw);
-    for (int t = threadIdx.x; t < L; t += NT) buf[pd(t)] = conj2(cmul(buf[pd(t)], kern[t]));
-    __syncthreads();
-    fft_forward<MAXL, NT>(buf, d, tw);
+    if (passes == 2) {
+        for (int t = d->n + threadIdx.x; t < L; t += NT) buf[pd(t)] = make_double2(0.0, 0.0);
+        __syncthreads();
+    }
+#pragma unroll 1
+    for (int pass = 0; pass < passes; ++pass) {
+        if (pass == 1) {
+            for (int t = threadIdx.x; t < L; t += NT) buf[pd(t)] = conj2(cmul(buf[pd(t)], kern[t]));
+            __syncthreads();
+        }
+        fft_forward<MAXL, NT>(buf, d, tw);
+    }
 }
 
 // Bluestein chirp b_t = e^{i pi t^2 / n}, t < n, computed in place: the
@@ -626,9 +630,9 @@ __global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan 
     // the first Delta of each of G bins of this thread is loaded before any
     // is used (all loads in flight together); aliases m + n <= mmax after
     constexpr int G = U < 2 ? U : 2;  // registers: 16 per bin
-    static_assert(U % G == 0, "whole groups of bins");
-#pragma unroll
-    for (int u0 = 0; u0 < U; u0 += G) {
+    // groups of G bins, the last one also covering k = U NT (thread 0, n = MAXL)
+#pragma unroll 1
+    for (int u0 = 0; u0 <= U; u0 += G) {
         double2 a0[G], a1[G], b0[G], b1[G];
 #pragma unroll
         for (int u = 0; u < G; ++u) first(threadIdx.x + (u0 + u) * NT, a0[u], a1[u], b0[u], b1[u]);
@@ -640,12 +644,6 @@ __global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan 
                 put(k, a0[u], a1[u], b0[u], b1[u]);
             }
         }
-    }
-    if (threadIdx.x == 0 && 2 * U * NT <= N) {
-        double2 a0, a1, b0, b1;
-        first(U * NT, a0, a1, b0, b1);
-        bins(U * NT, a0, a1, b0, b1);
-        put(U * NT, a0, a1, b0, b1);
     }
     __syncthreads();
     transform<MAXL, NT>(buf, d, TwLds{tlo, thi});
