@@ -98,11 +98,14 @@ enum sht_flags {
      * a time over up to 256 ring pairs in FP32 and adds those sums in FP64.  The
      * Delta and FFT stages stay FP64.  Expected relative RMS error against
      * the FP64 transform: about 1e-7 to 1e-6.  Built for batches: a wave
-     * covers 8 to 32 maps in synthesis (8 above lmax 2048) and 8 in analysis,
-     * so nmaps >= 8 fills it.  sht_alm2map with
-     * this flag and nmaps >= 8 keeps its workspace Delta map-minor (as
-     * SHT_DELTA_MAP_MINOR below), ring-major with fewer maps; sht_map2alm
-     * keeps it ring-major. */
+     * covers 8 to 32 maps in synthesis (8 with FP64 block sums) and 8 in
+     * analysis.  With fewer than 8 maps the FP64 kernels run instead (a
+     * single map would leave most matrix-core columns idle, and FP32 vector
+     * arithmetic is no faster than FP64 on this part), except in the stage
+     * calls with SHT_DELTA_MAP_MINOR, which always take the mixed kernels.
+     * sht_alm2map with this flag and nmaps >= 8 keeps its workspace Delta
+     * map-minor (as SHT_DELTA_MAP_MINOR below), ring-major with fewer maps;
+     * sht_map2alm keeps it ring-major. */
     SHT_MIXED = 1u,
     /* Layout of the `delta` argument of the stage calls: [nrings][mmax+1][nmaps]
      * (map index fastest) instead of [nmaps][nrings][mmax+1].  Accepted by

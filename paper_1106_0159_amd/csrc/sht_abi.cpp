@@ -37,8 +37,9 @@ size_t partial_bytes(int lmax, int mmax, int nslots, int nmaps) {
     return G > 1 ? (size_t)G * alm_bytes(lmax, mmax, nmaps) : 0;
 }
 size_t aux_bytes(int lmax, int mmax, int nslots, int nmaps, uint32_t flags) {
-    const size_t syn = (flags & SHT_MIXED) ? mx_aprime_bytes(lmax, mmax, nmaps, flags)
-                                           : alm_bytes(lmax, mmax, nmaps) + 16u * kCoefPad;
+    // with SHT_MIXED either kernel set may run (use_mx), so room for both
+    const size_t f64 = alm_bytes(lmax, mmax, nmaps) + 16u * kCoefPad;
+    const size_t syn = (flags & SHT_MIXED) ? std::max(f64, mx_aprime_bytes(lmax, mmax, nmaps, flags)) : f64;
     return std::max(round256(syn), round256(partial_bytes(lmax, mmax, nslots, nmaps)));
 }
 size_t ws_need(int lmax, int mmax, const HostGeom &h, int nmaps, uint32_t flags) {
@@ -95,7 +96,7 @@ int check_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, const 
 int enqueue_alm2map(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm, void *aprime,
                     void *delta, DeltaLayout dl, double *map, int nmaps, uint32_t flags, hipStream_t st, bool fork) {
     int rc;
-    if (flags & SHT_MIXED) {
+    if (use_mx(flags & ~SHT_DELTA_MAP_MINOR, nmaps)) {
         if ((rc = launch_leg_syn_mx(c, p, s, alm, aprime, delta, dl, nmaps, flags, st))) return rc;
     } else {
         if ((rc = launch_prescale(c, alm, aprime, nmaps, st))) return rc;
@@ -133,7 +134,7 @@ int sht_alm2delta(int lmax, int mmax, const sht_geom *g, const void *alm, void *
     if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p)) ||
         (rc = get_start(*c, p, as_stream(stream), &s)))
         return rc;
-    if (flags & SHT_MIXED)
+    if (use_mx(flags, nmaps))
         rc = launch_leg_syn_mx(*c, *p, *s, alm, workspace, delta, stage_layout(h, mmax, nmaps, flags), nmaps, flags,
                                as_stream(stream));
     else if (!(rc = launch_prescale(*c, alm, workspace, nmaps, as_stream(stream))))
@@ -188,7 +189,7 @@ int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void
     if ((rc = get_coef(lmax, mmax, &c)) || (rc = get_geom(h, mmax, &p)) ||
         (rc = get_start(*c, p, as_stream(stream), &s)))
         return rc;
-    if (flags & SHT_MIXED)
+    if (use_mx(flags, nmaps))
         rc = launch_leg_ana_mx(*c, *p, *s, delta, stage_layout(h, mmax, nmaps, flags), alm, nmaps, workspace,
                                as_stream(stream));
     else
@@ -244,7 +245,7 @@ int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *
     // loses about what the analysis kernel gains on its reads
     const DeltaLayout dl = delta_layout(h.nrings, mmax, nmaps, false);
     if (!(rc = launch_fft_ana(*p, mmax, map, delta, dl, nmaps, st))) {
-        if (flags & SHT_MIXED)
+        if (use_mx(flags & ~SHT_DELTA_MAP_MINOR, nmaps))
             rc = launch_leg_ana_mx(*c, *p, *s, delta, dl, alm, nmaps, partials, st);
         else
             rc = launch_leg_ana(*c, *p, *s, delta, alm, nmaps, partials, st);

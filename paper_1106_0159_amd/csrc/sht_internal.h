@@ -169,13 +169,23 @@ inline DeltaLayout delta_layout(int nrings, int mmax, int nmaps, bool map_minor)
     return DeltaLayout{(int64_t)nrings * nm, nm, 1, 0};
 }
 
+// The mixed-precision kernels pay from kMxMinMaps maps on (a wave's
+// matrix-core columns hold 8 maps, and FP32 vector arithmetic runs no faster
+// than FP64 here); with fewer maps SHT_MIXED runs the FP64 kernels, faster
+// there and at least as accurate.  Map-minor Delta in the stage calls always
+// takes the mixed kernels (the FP64 Legendre kernels use ring-major Delta).
+constexpr int kMxMinMaps = 8;
+inline bool use_mx(uint32_t flags, int nmaps) {
+    return (flags & SHT_MIXED) && (nmaps >= kMxMinMaps || (flags & SHT_DELTA_MAP_MINOR));
+}
+
 // Delta layout of sht_alm2map's workspace: with SHT_MIXED map-minor from 8
 // maps on (the matrix-core kernel then stores whole 128-byte lines per (ring,
 // m), which saves more than the ring FFT loses on its strided reads; with
 // fewer maps there are no whole lines to gain, and the ring-major FFT
 // transforms a mirror pair per workgroup instead of one ring).
 inline DeltaLayout alm2map_layout(int nrings, int mmax, int nmaps, uint32_t flags) {
-    return delta_layout(nrings, mmax, nmaps, (flags & SHT_MIXED) != 0 && nmaps >= 8);
+    return delta_layout(nrings, mmax, nmaps, use_mx(flags & ~SHT_DELTA_MAP_MINOR, nmaps));
 }
 
 // One length class of one plan's ring stage as the ring kernels read it: a

@@ -81,8 +81,9 @@ def test_workspace_bytes_values_and_monotonic():
 def test_workspace_bytes_mixed():
     """SHT_MIXED: aux holds FP32 tiles of c a_lm, [column group][l-block of
     column m][parity][16 NCF columns][16 k] floats, NCF = 1, 2, 4 for up to
-    8, 16 and more maps (8 NCF maps per column group; NCF = 1 above
-    lmax 2048), kMxL = 32 l per block."""
+    8, 16 and more maps (8 NCF maps per column group; NCF = 1 with FP64
+    block sums and above lmax 2048), kMxL = 32 l per block, or the FP64
+    c-scaled a_lm if larger."""
     g = si.healpix(8)
     r256 = lambda b: (b + 255) // 256 * 256
     delta = lambda lmax, n: r256(n * g.nrings * (lmax + 1) * 16)
@@ -95,10 +96,16 @@ def test_workspace_bytes_mixed():
         ncg = -(-nmaps // (8 * ncf))
         return ncg * blocks * 2 * (16 * ncf) * 16 * 4
 
+    # with SHT_MIXED either kernel set may run (the FP64 ones below 8 maps),
+    # so aux holds the larger of the tiles and the c-scaled a_lm (+32 entries)
+    def aux(lmax, nmaps, f64_sums=False):
+        f64 = nmaps * (lmax + 1) * (lmax + 2) // 2 * 16 + 32 * 16
+        return r256(max(tiles(lmax, nmaps, f64_sums), f64))
+
     for lmax, nmaps in [(16, 1), (16, 3), (16, 12), (16, 20), (16, 40), (70, 33), (0, 1), (2048, 40), (2049, 40)]:
-        assert _ws(lmax, lmax, g, nmaps, sht.SHT_MIXED) == delta(lmax, nmaps) + r256(tiles(lmax, nmaps)), (lmax, nmaps)
+        assert _ws(lmax, lmax, g, nmaps, sht.SHT_MIXED) == delta(lmax, nmaps) + aux(lmax, nmaps), (lmax, nmaps)
         assert (_ws(lmax, lmax, g, nmaps, sht.SHT_MIXED | sht.SHT_MIXED_FP64_SUMS) ==
-                delta(lmax, nmaps) + r256(tiles(lmax, nmaps, True))), (lmax, nmaps)
+                delta(lmax, nmaps) + aux(lmax, nmaps, True)), (lmax, nmaps)
     # the FP64-sums bit needs SHT_MIXED
     assert _ws(16, 16, g, 1, sht.SHT_MIXED_FP64_SUMS) == 0
     # the Delta layout flag does not change the workspace

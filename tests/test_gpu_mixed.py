@@ -4,9 +4,12 @@ The recurrence stays FP64 and only lambda_lm, the c-scaled a_lm (synthesis)
 or the pair sums of Delta (analysis), and the matrix-core sums are FP32, so
 the bar is the batched-mixed target: relative RMS <= 1e-6 of every map (or
 a_lm set) against the FP64 oracle and against the FP64 HIP path, itself
-pinned to 1e-12.  Synthesis batches of 1, 3, 12 and 40 maps take the three
-column widths of its kernel (8, 16 and 32 maps per wave) and a partly filled
-last column group; analysis groups 8 maps and 2048 ring pairs per workgroup.
+pinned to 1e-12.  Synthesis batches of 12, 17 and 40 maps take the column
+widths of its kernel (16 and 32 maps per wave) and a partly filled last
+column group; analysis groups 8 maps and 2048 ring pairs per workgroup.
+Below 8 maps SHT_MIXED runs the FP64 kernels (the same bits as flags 0); the
+stage calls with map-minor Delta take the mixed kernels at any batch size,
+which covers 1 and 3 maps and 8 maps per wave.
 """
 import sys
 
@@ -100,6 +103,43 @@ def test_mixed_alm2map_small(sht, case):
             continue
         assert relrms(got[i], ref) <= MX_TOL, (name, i, relrms(got[i], ref))
         assert relrms(got[i], f64[i]) <= MX_TOL, (name, i, relrms(got[i], f64[i]))
+
+
+def test_mixed_below_8_maps_runs_the_fp64_kernels(sht):
+    """With fewer than 8 maps the matrix-core columns would mostly idle and
+    FP32 vector arithmetic is no faster than FP64, so SHT_MIXED runs the FP64
+    kernels: the same bits as flags 0 in both directions."""
+    lmax, g = 40, si.healpix(8)
+    for nmaps in (1, 3, 7):
+        say(f"mixed below 8 maps: nmaps={nmaps}")
+        a = dev(batch(lmax, lmax, nmaps, 800 + nmaps))
+        assert np.array_equal(host(sht.alm2map(a, g, lmax, flags=sht.SHT_MIXED)), host(sht.alm2map(a, g, lmax)))
+        mp = dev(np.stack([si.random_map(g, 820 + i) for i in range(nmaps)]))
+        assert np.array_equal(host(sht.map2alm(mp, g, lmax, flags=sht.SHT_MIXED)), host(sht.map2alm(mp, g, lmax)))
+
+
+@pytest.mark.parametrize("case", [MX_CASES[0], MX_CASES[1], MX_CASES[3], MX_CASES[9]],
+                         ids=[MX_CASES[0][0], MX_CASES[1][0], MX_CASES[3][0], MX_CASES[9][0]])
+def test_mixed_kernels_small_batches_map_minor(sht, case):
+    """Map-minor Delta takes the mixed kernels at any batch size: 1, 3 and 8
+    maps (lmax 0, mmax < lmax, odd ring count, ragged pair tile) through the
+    Legendre stage calls, against the oracle's Delta and a_lm."""
+    name, mk, lmax, mmax, nmaps = case
+    g = mk()
+    a = batch(lmax, mmax, nmaps, 900)
+    X = sht.SHT_MIXED | sht.SHT_DELTA_MAP_MINOR
+    say(f"mixed kernels, map-minor stage calls: {name} nmaps={nmaps}")
+    d = host(sht.alm2delta(dev(a), g, lmax, mmax, flags=X))  # [nrings][mmax+1][nmaps]
+    refs = [oracle.delta_syn(lmax, mmax, g, a[i]) for i in range(nmaps)]
+    for i in range(nmaps):
+        if np.linalg.norm(refs[i]) > 0:
+            assert relrms(d[:, :, i], refs[i]) <= MX_TOL, (name, i, relrms(d[:, :, i], refs[i]))
+    dd = np.ascontiguousarray(np.stack(refs, axis=-1))
+    back = host(sht.delta2alm(dev(dd), g, lmax, mmax, flags=X))
+    for i in range(nmaps):
+        ref = oracle.delta2alm(lmax, mmax, g, refs[i])
+        if np.linalg.norm(ref) > 0:
+            assert relrms(back[i], ref) <= MX_TOL, (name, i, relrms(back[i], ref))
 
 
 @pytest.mark.parametrize("case", [MX_CASES[4], MX_CASES[6]], ids=[MX_CASES[4][0], MX_CASES[6][0]])
@@ -283,11 +323,14 @@ def test_mixed_batched_gl1025_lmax1024_64maps(sht):
 
 @pytest.mark.parametrize("nmaps", [1, 12, 40])
 def test_map_minor_delta_layout_is_bitwise_equal(sht, nmaps):
-    """SHT_DELTA_MAP_MINOR moves Delta.  The mixed Legendre stages give the
-    same bits in either layout.  The FFT stages pair two adjacent maps of one
-    ring in a complex transform instead of the two rings of a mirror pair, so
-    they agree to rounding (the ring-major FFT stages are pinned to the oracle
-    at 1e-12).  The combined mixed transforms equal the stage composition."""
+    """SHT_DELTA_MAP_MINOR moves Delta.  From 8 maps on the mixed Legendre
+    stages give the same bits in either layout; below 8 maps ring-major
+    Delta runs the FP64 kernels (the same bits as flags 0) and map-minor the
+    mixed ones (within the mixed tolerance).  The FFT stages pair two
+    adjacent maps of one ring in a complex transform instead of the two rings
+    of a mirror pair, so they agree to rounding (the ring-major FFT stages are
+    pinned to the oracle at 1e-12).  The combined mixed transforms equal the
+    stage composition."""
     import torch
     lmax, mmax, g = 77, 61, si.healpix(32)
     MM = sht.SHT_DELTA_MAP_MINOR
@@ -306,10 +349,16 @@ def test_map_minor_delta_layout_is_bitwise_equal(sht, nmaps):
     a = dev(batch(lmax, mmax, nmaps, 1200))
     dx = sht.alm2delta(a, g, lmax, mmax, flags=X)
     dx_mm = sht.alm2delta(a, g, lmax, mmax, flags=X | MM)
-    assert torch.equal(dx.permute(1, 2, 0), dx_mm)
     ax = sht.delta2alm(ds, g, lmax, mmax, flags=X)
     ax_mm = sht.delta2alm(ds_mm, g, lmax, mmax, flags=X | MM)
-    assert torch.equal(ax, ax_mm)
+    if nmaps >= 8:
+        assert torch.equal(dx.permute(1, 2, 0), dx_mm)
+        assert torch.equal(ax, ax_mm)
+    else:
+        assert torch.equal(dx, sht.alm2delta(a, g, lmax, mmax))
+        assert torch.equal(ax, sht.delta2alm(ds, g, lmax, mmax))
+        assert rel(dx_mm, dx.permute(1, 2, 0)) <= MX_TOL
+        assert rel(ax_mm, ax) <= MX_TOL
     # the combined mixed calls equal the stage composition: synthesis keeps
     # its Delta map-minor from 8 maps on (whole 128-byte lines), ring-major
     # below; analysis ring-major
