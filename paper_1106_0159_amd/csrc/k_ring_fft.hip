@@ -24,6 +24,8 @@
 //   X_k = conj(b_k) sum_n (x_n conj(b_n)) b_{k-n},  b_t = e^{i pi t^2/N},
 // as a cyclic convolution of 5-smooth length L >= 2N-1 done with two forward
 // transforms (the filter spectrum, scaled by 1/L, is a plan table).
+#include <type_traits>
+
 #include "k_device.h"
 
 namespace sht {
@@ -224,8 +226,25 @@ __device__ __forceinline__ void load_twiddles(double2 *lo, double2 *hi, const do
 // One Stockham stage of radix R on buf[0..L), L <= MAXL, Ns = product of
 // earlier radices.  Each thread holds up to kMaxB twiddled butterflies in
 // registers (NT threads) and writes them back after the barrier.
-template <int R, int MAXL, int NT>
-__device__ __forceinline__ void fft_stage(double2 *buf, int L, int Ns, TwLds tw) {
+// Point access of a stage: LDS (the default), or a caller's function that
+// supplies the first stage's input points / takes the last stage's output
+// points in registers (no LDS pass and no barrier for them).
+struct LdsIn {
+    const double2 *buf;
+    __device__ __forceinline__ double2 operator()(int t) const { return buf[pd(t)]; }
+};
+struct LdsOut {
+    double2 *buf;
+    __device__ __forceinline__ void operator()(int t, double2 v) const { buf[pd(t)] = v; }
+};
+
+// FIRST: the first stage (Ns = 1, all twiddles 1); a stage with register
+// input is always the first.
+template <int R, int MAXL, int NT, bool FIRST = false, class In = LdsIn, class Out = LdsOut>
+__device__ __forceinline__ void fft_stage(double2 *buf, int L, int Ns_, TwLds tw, In in = In{}, Out out = Out{}) {
+    constexpr bool kLdsIn = std::is_same<In, LdsIn>::value, kLdsOut = std::is_same<Out, LdsOut>::value;
+    constexpr bool kFirst = FIRST || !kLdsIn;
+    const int Ns = kFirst ? 1 : Ns_;
     constexpr int kMaxB = (MAXL / R + NT - 1) / NT;
     const int nbf = L / R;
     const int tstep = L / (Ns * R);
@@ -244,8 +263,8 @@ __device__ __forceinline__ void fft_stage(double2 *buf, int L, int Ns, TwLds tw)
             double2 wr = w1;
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                const double2 xv = buf[pd(j + r * nbf)];
-                if (r == 0) {
+                const double2 xv = kLdsIn ? buf[pd(j + r * nbf)] : in(j + r * nbf);
+                if (r == 0 || kFirst) {
                     v[b][r] = xv;
                 } else {
                     v[b][r] = cmul(xv, wr);
@@ -255,7 +274,7 @@ __device__ __forceinline__ void fft_stage(double2 *buf, int L, int Ns, TwLds tw)
             butterfly<R>(v[b]);
         }
     }
-    __syncthreads();
+    if (kLdsIn) __syncthreads();  // in place: every read is done before the writes
 #pragma unroll
     for (int b = 0; b < kMaxB; ++b) {
         const int j = threadIdx.x + b * NT;
@@ -264,91 +283,180 @@ __device__ __forceinline__ void fft_stage(double2 *buf, int L, int Ns, TwLds tw)
             const int k = j - jq * Ns;
             const int o = jq * Ns * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[pd(o + r * Ns)] = v[b][r];
+            for (int r = 0; r < R; ++r) {
+                if (kLdsOut)
+                    buf[pd(o + r * Ns)] = v[b][r];
+                else
+                    out(o + r * Ns, v[b][r]);
+            }
         }
     }
-    __syncthreads();
+    if (kLdsOut) __syncthreads();
 }
 
-// One Stockham stage of any radix R (the prime factors above 5): output
-// y_s of butterfly j is sum_q x_q W^{q (k tstep + s L/R)} with x_q the q-th
-// input of the butterfly, i.e. the twiddles and the R-point DFT of the
-// fixed-radix stages taken together.  Each thread computes up to kMaxOut
-// outputs directly (R terms each), then writes them back after the barrier.
-// The twiddle of term q is carried in registers (w <- w W^step) and taken
-// afresh from the table, at an exponent reduced exactly as an integer, every
-// kAnchor terms: one LDS read per term instead of three, and a recurrence
-// error of at most kAnchor roundings.
+// One Stockham stage of a prime radix R > 5 (a direct R-term DFT per
+// butterfly).  Butterfly j (k = j mod Ns) takes x_q = buf[j + q L/R] twiddled
+// to x'_q = x_q W_L^{q k tstep}; its outputs y_s = sum_q x'_q W_R^{q s} go to
+// o + s Ns.  With W_R^{q s} = cos t - i sin t (t = 2 pi q s / R) and the
+// inputs paired with their mirrors, P_q = x'_q + x'_{R-q} and M_q = x'_q -
+// x'_{R-q} (q = 1 .. h, h = (R-1)/2),
+//   y_s = A_s - i B_s,  y_{R-s} = A_s + i B_s,
+//   A_s = x'_0 + sum_q P_q cos t,  B_s = sum_q M_q sin t,
+// so an output pair costs 4 real multiply-adds per q instead of 8 per term
+// of each output.  Pass 1 forms P and M in place (q in slot q, M in slot R-q);
+// pass 2 gives each thread items of two output pairs (s, s+1) of one
+// butterfly, holds the outputs until every thread has read its inputs, then
+// writes them.  W_R^{q s} is carried in registers (w <- w W_R^s) and taken
+// afresh from the table, at the exact integer exponent q s mod R, every
+// kAnchor terms (a recurrence error of at most kAnchor roundings).
 template <int MAXL, int NT>
 __device__ __forceinline__ void fft_stage_generic(double2 *buf, int L, int Ns, int R, TwLds tw) {
-    constexpr int kMaxOut = (MAXL + NT - 1) / NT;
     constexpr int kAnchor = 16;
-    const int nbf = L / R;
+    constexpr int kPairs = 2;  // output pairs per item
+    // items per thread: at most L (R + 5) / (4 R) / NT items of pass 2 (R >= 7);
+    // 0.31 MAXL / NT at R = 13 is the most
+    constexpr int kMaxItems = (4 * MAXL / NT + 12) / 13;
+    const int nbf = L / R, h = (R - 1) / 2;
     const int tstep = L / (Ns * R);
-    double2 y[kMaxOut];
-#pragma unroll
-    for (int i = 0; i < kMaxOut; ++i) {
-        const int o = threadIdx.x + i * NT;
-        y[i] = make_double2(0.0, 0.0);
-        if (o < L) {
-            const int k = o % Ns, t = o / Ns;
-            const int sidx = t % R, jq = t / R;
-            const int j = jq * Ns + k;
-            const int step = (k * tstep + sidx * nbf) % L;
-            const int jump = (kAnchor * step) % L;  // kAnchor * step < 16 * 8192
-            const double2 ws = tw(step);
-            double yr = 0.0, yi = 0.0;
-            int e = 0;  // q0 * step mod L
-            for (int q0 = 0; q0 < R; q0 += kAnchor) {
-                double2 w = tw(e);
-                const int qe = min(R, q0 + kAnchor);
-                for (int q = q0; q < qe; ++q) {
-                    const double2 x = buf[pd(j + q * nbf)];
-                    yr = fma(x.x, w.x, fma(-x.y, w.y, yr));
-                    yi = fma(x.x, w.y, fma(x.y, w.x, yi));
-                    w = cmul(w, ws);
-                }
-                e += jump;
-                if (e >= L) e -= L;
-            }
-            y[i] = make_double2(yr, yi);
-        }
+    const float inv_nbf = 1.0f / (float)nbf, inv_ns = 1.0f / (float)Ns;
+    // pass 1: P_q, M_q for q = 1 .. h of every butterfly, in place
+    for (int i = threadIdx.x; i < nbf * h; i += NT) {
+        const int q = 1 + (int)(((float)i + 0.5f) * inv_nbf);  // (i + 0.5) / nbf is 0.5/nbf from an integer
+        const int j = i - (q - 1) * nbf;
+        const int jq = (int)(((float)j + 0.5f) * inv_ns);
+        const int kt = (j - jq * Ns) * tstep;  // k tstep < L / R: q kt < L
+        const double2 a = cmul(buf[pd(j + q * nbf)], tw(q * kt));
+        const double2 b = cmul(buf[pd(j + (R - q) * nbf)], tw((R - q) * kt));
+        buf[pd(j + q * nbf)] = add2(a, b);
+        buf[pd(j + (R - q) * nbf)] = sub2(a, b);
     }
     __syncthreads();
+    // pass 2: item i = (group g, butterfly j); group g holds s = 2 g, 2 g + 1 (<= h)
+    const int ng = (h + kPairs) / kPairs;
+    double2 y[kMaxItems][2 * kPairs];
 #pragma unroll
-    for (int i = 0; i < kMaxOut; ++i) {
-        const int o = threadIdx.x + i * NT;
-        if (o < L) buf[pd(o)] = y[i];
+    for (int it = 0; it < kMaxItems; ++it) {
+        const int i = threadIdx.x + it * NT;
+        if (i >= nbf * ng) break;
+        const int g = (int)(((float)i + 0.5f) * inv_nbf);
+        const int j = i - g * nbf;
+        const double2 x0 = buf[pd(j)];
+        double2 A[kPairs], Bp[kPairs], w[kPairs], ws[kPairs];
+#pragma unroll
+        for (int u = 0; u < kPairs; ++u) {
+            const int sv = min(kPairs * g + u, h);
+            A[u] = x0;
+            Bp[u] = make_double2(0.0, 0.0);
+            ws[u] = tw(sv * nbf);  // W_R^s
+        }
+        for (int q0 = 1; q0 <= h; q0 += kAnchor) {
+#pragma unroll
+            for (int u = 0; u < kPairs; ++u) {
+                const int sv = min(kPairs * g + u, h);
+                w[u] = tw(((q0 * sv) % R) * nbf);  // W_R^{q0 s}, exact exponent
+            }
+            const int qe = min(h, q0 + kAnchor - 1);
+            for (int q = q0; q <= qe; ++q) {
+                const double2 P = buf[pd(j + q * nbf)], M = buf[pd(j + (R - q) * nbf)];
+#pragma unroll
+                for (int u = 0; u < kPairs; ++u) {
+                    // A += cos t P, B' += -sin t M = w.y M  (so B = -B')
+                    A[u].x = fma(w[u].x, P.x, A[u].x);
+                    A[u].y = fma(w[u].x, P.y, A[u].y);
+                    Bp[u].x = fma(w[u].y, M.x, Bp[u].x);
+                    Bp[u].y = fma(w[u].y, M.y, Bp[u].y);
+                    w[u] = cmul(w[u], ws[u]);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kPairs; ++u) {
+            // y_s = A - i B = A + i B', y_{R-s} = A + i B = A - i B'
+            y[it][2 * u] = make_double2(A[u].x - Bp[u].y, A[u].y + Bp[u].x);
+            y[it][2 * u + 1] = make_double2(A[u].x + Bp[u].y, A[u].y - Bp[u].x);
+        }
+    }
+    __syncthreads();  // in place: every input is read before the outputs land
+#pragma unroll
+    for (int it = 0; it < kMaxItems; ++it) {
+        const int i = threadIdx.x + it * NT;
+        if (i >= nbf * ng) break;
+        const int g = (int)(((float)i + 0.5f) * inv_nbf);
+        const int j = i - g * nbf;
+        const int jq = (int)(((float)j + 0.5f) * inv_ns);
+        const int o = jq * Ns * R + (j - jq * Ns);
+#pragma unroll
+        for (int u = 0; u < kPairs; ++u) {
+            const int sv = kPairs * g + u;
+            if (sv > h) break;
+            buf[pd(o + sv * Ns)] = y[it][2 * u];
+            if (sv > 0) buf[pd(o + (R - sv) * Ns)] = y[it][2 * u + 1];
+        }
     }
     __syncthreads();
 }
 
-// Forward FFT of length d->L (<= MAXL) in LDS (natural order in and out).
+// Whether the first (last) stage of the transform of d can take its input
+// (give its output) in registers: a radix-4 or radix-8 stage of a direct
+// transform with more than one stage.  (Not under Bluestein: evaluating the
+// chirp inside the unrolled stage costs more registers than the LDS pass.)
+__device__ __forceinline__ bool reg_stage_ok(int R) { return R == 8 || R == 4; }
+__device__ __forceinline__ bool reg_first(DescP d) { return !d->bluestein && d->nrad > 1 && reg_stage_ok(d->rad[0]); }
+__device__ __forceinline__ bool reg_last(DescP d) {
+    return !d->bluestein && d->nrad > 1 && reg_stage_ok(d->rad[d->nrad - 1]);
+}
+
+// Stages s0 .. s1-1 of the forward FFT of length d->L (<= MAXL) in LDS, Ns0
+// the product of the radices before s0 (all stages: natural order in and out).
 template <int MAXL, int NT>
-__device__ __forceinline__ void fft_forward(double2 *buf, DescP d, TwLds tw) {
-    const int L = d->L, nrad = d->nrad;
-    int Ns = 1;
-    for (int s = 0; s < nrad; ++s) {
+__device__ __forceinline__ void fft_stages(double2 *buf, DescP d, TwLds tw, int s0, int s1, int Ns0) {
+    const int L = d->L;
+    int Ns = Ns0;
+    for (int s = s0; s < s1; ++s) {
         const int R = d->rad[s];
-        switch (R) {
+        switch (Ns == 1 ? -R : R) {
+            case -8: fft_stage<8, MAXL, NT, true>(buf, L, 1, tw); break;
+            case -4: fft_stage<4, MAXL, NT, true>(buf, L, 1, tw); break;
+            case -2: case 2: fft_stage<2, MAXL, NT>(buf, L, Ns, tw); break;
+            case -3: case 3: fft_stage<3, MAXL, NT>(buf, L, Ns, tw); break;
+            case -5: case 5: fft_stage<5, MAXL, NT>(buf, L, Ns, tw); break;
             case 8: fft_stage<8, MAXL, NT>(buf, L, Ns, tw); break;
             case 4: fft_stage<4, MAXL, NT>(buf, L, Ns, tw); break;
-            case 2: fft_stage<2, MAXL, NT>(buf, L, Ns, tw); break;
-            case 3: fft_stage<3, MAXL, NT>(buf, L, Ns, tw); break;
-            case 5: fft_stage<5, MAXL, NT>(buf, L, Ns, tw); break;
             default: fft_stage_generic<MAXL, NT>(buf, L, Ns, R, tw); break;
         }
         Ns *= R;
     }
 }
 
-// DFT of the n points already placed in buf[0..n) (pre-multiplied by
-// conj(chirp) when Bluestein): afterwards X_k is at_k(buf, d, k).
-template <int MAXL, int NT>
-__device__ __forceinline__ void transform(double2 *buf, DescP d, TwLds tw) {
-    // one copy of the stage code for both of Bluestein's transforms (the
-    // kernels are otherwise large enough to thrash the instruction cache)
-    const int L = d->L, passes = d->bluestein ? 2 : 1;
+// DFT of n points: afterwards X_k is result_at(buf, d, k).  The points are those
+// already placed in buf[0..n) (pre-multiplied by conj(chirp) when Bluestein),
+// or, when in_reg and reg_first(d), in(t) for t < L = n, read by the first
+// stage.  With out_reg and reg_last(d) the last stage hands X_t to out(t, X_t)
+// instead (t < n), and buf holds no result.  (The register stages sit outside
+// the stage loop, so that the compiler keeps none of their addresses live
+// across it.)
+template <int MAXL, int NT, class In = LdsIn, class Out = LdsOut>
+__device__ __forceinline__ void transform(double2 *buf, DescP d, TwLds tw, In in = In{}, bool in_reg = false,
+                                          Out out = Out{}, bool out_reg = false) {
+    constexpr bool kRegIn = !std::is_same<In, LdsIn>::value, kRegOut = !std::is_same<Out, LdsOut>::value;
+    const int L = d->L, nrad = d->nrad, passes = d->bluestein ? 2 : 1;
+    in_reg = kRegIn && in_reg && reg_first(d);
+    out_reg = kRegOut && out_reg && reg_last(d);
+    int s0 = 0, Ns0 = 1;
+    if constexpr (kRegIn) {
+        if (in_reg) {
+            s0 = 1;
+            Ns0 = d->rad[0];
+            if (Ns0 == 8)
+                fft_stage<8, MAXL, NT, true, In, LdsOut>(buf, L, 1, tw, in, LdsOut{buf});
+            else
+                fft_stage<4, MAXL, NT, true, In, LdsOut>(buf, L, 1, tw, in, LdsOut{buf});
+        }
+    }
+    const int s1 = out_reg ? nrad - 1 : nrad;
+    // Bluestein (no register stages): zero padding, then two transforms with
+    // one copy of the stage code (the kernels are otherwise large enough to
+    // thrash the instruction cache)
     const double2 *__restrict__ kern = d->kern;
     if (passes == 2) {
         for (int t = d->n + threadIdx.x; t < L; t += NT) buf[pd(t)] = make_double2(0.0, 0.0);
@@ -360,33 +468,94 @@ __device__ __forceinline__ void transform(double2 *buf, DescP d, TwLds tw) {
             for (int t = threadIdx.x; t < L; t += NT) buf[pd(t)] = conj2(cmul(buf[pd(t)], kern[t]));
             __syncthreads();
         }
-        fft_forward<MAXL, NT>(buf, d, tw);
+        fft_stages<MAXL, NT>(buf, d, tw, pass == 0 ? s0 : 0, pass == passes - 1 ? s1 : nrad, pass == 0 ? Ns0 : 1);
+    }
+    if constexpr (kRegOut) {
+        if (out_reg) {
+            const int R = d->rad[nrad - 1];
+            if (R == 8)
+                fft_stage<8, MAXL, NT, false, LdsIn, Out>(buf, L, L / 8, tw, LdsIn{buf}, out);
+            else
+                fft_stage<4, MAXL, NT, false, LdsIn, Out>(buf, L, L / 4, tw, LdsIn{buf}, out);
+        }
     }
 }
 
-// Bluestein chirp b_t = e^{i pi t^2 / n}, t < n, computed in place: the
-// angle's numerator t^2 mod 2n is an exact integer, taken into (-n, n] so
-// that the argument pi q / n of the reduced-range sin/cos lies in (-pi, pi].
-// (No table: the chirp of every ring length would otherwise be read from
-// memory per job.)
-__device__ __forceinline__ double2 chirp_at(int n, int t) {
+// Bluestein chirp b_t = e^{i pi t^2 / n}.  The angle's numerator q = t^2
+// mod 2n is an exact integer; b_t = hi[q / 64] lo[q % 64] from two LDS tables
+// filled per workgroup, lo[u] = e^{i pi u / n} (u < 64) and hi[h] = e^{i pi
+// 64 h / n} (64 h < 2n), each entry from the reduced-range sin/cos at pi r / n
+// with r = its numerator taken exactly into (-n, n]: one complex product per
+// point (about one more rounding) instead of a sin/cos evaluation, and no
+// per-length table in memory.
+constexpr int kChLo = 64;
+template <int MAXL>
+constexpr int chirp_entries() { return kChLo + MAXL / kChLo + 1; }  // 2n <= MAXL + 1
+__device__ __forceinline__ double2 e_pi_over(int r, int n) {
     const int n2 = 2 * n;
-    int q = (int)(((int64_t)t * t) % n2);
-    if (q > n) q -= n2;
+    r %= n2;
+    if (r > n) r -= n2;
     double sn, cs;
-    sincos_small(3.141592653589793 * (double)q / (double)n, sn, cs);
+    sincos_small(3.141592653589793 * (double)r / (double)n, sn, cs);
     return make_double2(cs, sn);
 }
+struct Chirp {
+    const double2 *lo, *hi;
+    int n;
+    double inv2n;  // 1 / (2n)
+    __device__ __forceinline__ double2 operator()(int t) const {
+        // t^2 < 2^27 (t < 8192); the quotient from the double reciprocal is
+        // off by at most one, corrected below
+        const int n2 = 2 * n, tt = t * t;
+        int q = tt - (int)((double)tt * inv2n) * n2;
+        q = q < 0 ? q + n2 : (q >= n2 ? q - n2 : q);
+        return cmul(hi[q / kChLo], lo[q % kChLo]);
+    }
+};
+// fills the chirp tables of length n (caller synchronises)
+template <int NT>
+__device__ __forceinline__ Chirp load_chirp(double2 *lo, double2 *hi, int n) {
+    const int nhi = (2 * n - 1) / kChLo + 1;
+    for (int t = threadIdx.x; t < kChLo + nhi; t += NT) {
+        if (t < kChLo)
+            lo[t] = e_pi_over(t, n);
+        else
+            hi[t - kChLo] = e_pi_over((t - kChLo) * kChLo, n);
+    }
+    return Chirp{lo, hi, n, 1.0 / (2.0 * (double)n)};
+}
 
-__device__ __forceinline__ double2 result_at(const double2 *buf, DescP d, int k) {
+__device__ __forceinline__ double2 result_at(const double2 *buf, DescP d, const Chirp &ch, int k) {
     if (!d->bluestein) return buf[pd(k)];
     // X_k = conj(b_k) * conj(y_k), y = conj(second transform)
-    return conj2(cmul(chirp_at(d->n, k), buf[pd(k)]));
+    return conj2(cmul(ch(k), buf[pd(k)]));
 }
 
-__device__ __forceinline__ double2 input_point(double2 v, DescP d, int t) {
-    return d->bluestein ? cmul(v, conj2(chirp_at(d->n, t))) : v;
+__device__ __forceinline__ double2 input_point(double2 v, DescP d, const Chirp &ch, int t) {
+    return d->bluestein ? cmul(v, conj2(ch(t))) : v;
 }
+
+// The analysis input point t of a job (direct transform), read from the
+// rings' pixels by the first stage: s_a(t) + i s_b(t).
+struct PixelsIn {
+    const double *a, *b;
+    bool two;
+    __device__ __forceinline__ double2 operator()(int t) const {
+        const double vb = b[t];  // b = a for a single ring
+        return make_double2(a[t], two ? vb : 0.0);
+    }
+};
+// The synthesis output point t of a job (direct transform), written to the
+// rings' pixels by the last stage: z = FFT(conj g)_t, s_a(t) = Re z,
+// s_b(t) = -Im z.
+struct PixelsOut {
+    double *a, *b;
+    bool two;
+    __device__ __forceinline__ void operator()(int t, double2 v) const {
+        a[t] = v.x;
+        if (two) b[t] = -v.y;
+    }
+};
 
 // ---------------------------------------------------------------- ring jobs
 // A job is one ring or two rings of the same length n, transformed together
@@ -552,7 +721,8 @@ template <int MAXL, int NT, bool BATCH>
 __global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan *__restrict__ plans,
                                                    const int2 *__restrict__ bjobs) {
     extern __shared__ double2 lds[];
-    double2 *tlo = lds, *thi = lds + kTwLo, *buf = lds + tw_entries<MAXL>();
+    double2 *tlo = lds, *thi = lds + kTwLo, *clo = lds + tw_entries<MAXL>(), *chi = clo + kChLo;
+    double2 *buf = clo + chirp_entries<MAXL>();
     RingPlan P;
     JobSeqs js;
     if (!ring_task<BATCH>(one, plans, bjobs, P, js)) return;  // whole workgroup
@@ -562,6 +732,9 @@ __global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan 
     const DescP d = ro(P.descs) + P.ring_desc[js.ra];
     const int N = d->n, L = d->L;
     load_twiddles<NT>(tlo, thi, d->tw, L);
+    const bool blue = d->bluestein != 0;
+    Chirp ch{clo, chi, N, 0.0};
+    if (blue) ch = load_chirp<NT>(clo, chi, N);
     const double2 *__restrict__ Da = P.din + js.ma * dl.s_map + js.ra * dl.s_ring;
     const double2 *__restrict__ Db = P.din + js.mb * dl.s_map + js.rb * dl.s_ring;
     const double pa = P.phi0[js.ra], pb = P.phi0[js.rb];
@@ -571,8 +744,8 @@ __global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan 
         pha = load_phases<NT>(tab, mmax, pa);
         phb = pha;
         if (two && js.rb != js.ra) phb = load_phases<NT>(tab + kPhLo + phase_hi_entries(mmax), mmax, pb);
-        __syncthreads();
     }
+    if (P.ph_tab || blue) __syncthreads();  // phase and chirp tables visible
     const bool lds_fold = fold_rows && (2 * N < mmax + 1);
     int lim = mmax;  // last index of the phased-term rows that the bins fold
     if (lds_fold) {
@@ -592,19 +765,19 @@ __global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan 
     constexpr int U = MAXL / (2 * NT);
     const double2 z = make_double2(0.0, 0.0);
     auto put = [&](int k, double2 a0, double2 a1, double2 b0, double2 b1) {
-        const int kn = (N - k) % N;
+        const int kn = k ? N - k : 0;  // (n - k) mod n, k < n
         // h_k = (c_k + conj c_{n-k}) / 2, h_{n-k} = conj h_k
         const double2 ha = make_double2(0.5 * (a0.x + a1.x), 0.5 * (a0.y - a1.y));
         const double2 hb = make_double2(0.5 * (b0.x + b1.x), 0.5 * (b0.y - b1.y));
         // g = h_a + i h_b; the transform input is conj(g)
         const double2 gk = make_double2(ha.x - hb.y, ha.y + hb.x);
         const double2 gn = make_double2(ha.x + hb.y, -ha.y + hb.x);  // h_a* + i h_b* at n-k
-        buf[pd(k)] = input_point(conj2(gk), d, k);
-        if (kn != k) buf[pd(kn)] = input_point(conj2(gn), d, kn);
+        buf[pd(k)] = input_point(conj2(gk), d, ch, k);
+        if (kn != k) buf[pd(kn)] = input_point(conj2(gn), d, ch, kn);
     };
     // the four folded bins of one k: c_a(k), c_a(n-k), c_b(k), c_b(n-k)
     auto bins = [&](int k, double2 &a0, double2 &a1, double2 &b0, double2 &b1) {
-        const int kn = (N - k) % N;
+        const int kn = k ? N - k : 0;  // (n - k) mod n, k < n
         if (lds_fold) {
             const double2 *ta = buf + pd(L), *tb = buf + pd(L) + (mmax + 1);
             a0 = fold_terms(ta, k, N, lim);
@@ -620,7 +793,7 @@ __global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan 
         }
     };
     auto first = [&](int k, double2 &a0, double2 &a1, double2 &b0, double2 &b1) {
-        const int kn = (N - k) % N;
+        const int kn = k ? N - k : 0;  // (n - k) mod n, k < n
         const bool ok = !lds_fold && 2 * k <= N;
         a0 = (ok && k <= mmax) ? Da[k * dl.s_m] : z;
         a1 = (ok && kn <= mmax) ? Da[kn * dl.s_m] : z;
@@ -646,11 +819,15 @@ __global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan 
         }
     }
     __syncthreads();
-    transform<MAXL, NT>(buf, d, TwLds{tlo, thi});
     double *outa = P.mout + (int64_t)js.ma * P.npix + P.ofs[js.ra];
     double *outb = P.mout + (int64_t)js.mb * P.npix + P.ofs[js.rb];
+    // the last stage writes the pixels when it can (radix 4 or 8)
+    const bool reg_out = reg_last(d);
+    transform<MAXL, NT, LdsIn, PixelsOut>(buf, d, TwLds{tlo, thi}, LdsIn{buf}, false,
+                                          PixelsOut{outa, outb, two}, true);
+    if (reg_out) return;
     for (int j = threadIdx.x; j < N; j += NT) {
-        const double2 z = result_at(buf, d, j);  // FFT(conj g)_j; IDFT(g)_j = conj of it
+        const double2 z = result_at(buf, d, ch, j);  // FFT(conj g)_j; IDFT(g)_j = conj of it
         outa[j] = z.x;
         if (two) outb[j] = -z.y;
     }
@@ -660,7 +837,8 @@ template <int MAXL, int NT, bool BATCH>
 __global__ __launch_bounds__(NT, 4) void k_fft_ana(RingPlan one, const RingPlan *__restrict__ plans,
                                                    const int2 *__restrict__ bjobs) {
     extern __shared__ double2 lds[];
-    double2 *tlo = lds, *thi = lds + kTwLo, *buf = lds + tw_entries<MAXL>();
+    double2 *tlo = lds, *thi = lds + kTwLo, *clo = lds + tw_entries<MAXL>(), *chi = clo + kChLo;
+    double2 *buf = clo + chirp_entries<MAXL>();
     RingPlan P;
     JobSeqs js;
     if (!ring_task<BATCH>(one, plans, bjobs, P, js)) return;  // whole workgroup
@@ -670,6 +848,11 @@ __global__ __launch_bounds__(NT, 4) void k_fft_ana(RingPlan one, const RingPlan 
     const DescP d = ro(P.descs) + P.ring_desc[js.ra];
     const int N = d->n;
     load_twiddles<NT>(tlo, thi, d->tw, d->L);
+    Chirp ch{clo, chi, N, 0.0};
+    if (d->bluestein) {
+        ch = load_chirp<NT>(clo, chi, N);
+        __syncthreads();  // the input points below take the chirp
+    }
     const double pa = P.phi0[js.ra], wa = P.weight[js.ra];
     const double pb = P.phi0[js.rb], wb = P.weight[js.rb];
     // phase tables: visible after the barrier that follows the input below
@@ -682,27 +865,31 @@ __global__ __launch_bounds__(NT, 4) void k_fft_ana(RingPlan one, const RingPlan 
     }
     const double *ina = P.min + (int64_t)js.ma * P.npix + P.ofs[js.ra];
     const double *inb = P.min + (int64_t)js.mb * P.npix + P.ofs[js.rb];
-    // every pixel of this thread is loaded before any is used (N <= MAXL)
-    constexpr int U = MAXL / NT;
-    double va[U], vb[U];
+    // the first stage reads the pixels when it can (radix 4 or 8)
+    const bool reg_in = reg_first(d);
+    if (!reg_in) {
+        // every pixel of this thread is loaded before any is used (N <= MAXL)
+        constexpr int U = MAXL / NT;
+        double va[U], vb[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int j = threadIdx.x + u * NT;
-        va[u] = j < N ? ina[j] : 0.0;
-        vb[u] = (two && j < N) ? inb[j] : 0.0;
-    }
+        for (int u = 0; u < U; ++u) {
+            const int j = threadIdx.x + u * NT;
+            va[u] = j < N ? ina[j] : 0.0;
+            vb[u] = (two && j < N) ? inb[j] : 0.0;
+        }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int j = threadIdx.x + u * NT;
-        if (j < N) buf[pd(j)] = input_point(make_double2(va[u], vb[u]), d, j);
+        for (int u = 0; u < U; ++u) {
+            const int j = threadIdx.x + u * NT;
+            if (j < N) buf[pd(j)] = input_point(make_double2(va[u], vb[u]), d, ch, j);
+        }
     }
-    __syncthreads();
-    transform<MAXL, NT>(buf, d, TwLds{tlo, thi});
+    __syncthreads();  // twiddle and phase tables (and the points) visible
+    transform<MAXL, NT, PixelsIn>(buf, d, TwLds{tlo, thi}, PixelsIn{ina, inb, two}, true);
     double2 *Da = P.dout + js.ma * dl.s_map + js.ra * dl.s_ring;
     double2 *Db = P.dout + js.mb * dl.s_map + js.rb * dl.s_ring;
     for (int m = threadIdx.x; m <= mmax; m += NT) {
-        const int k = m % N, kn = (N - k) % N;
-        const double2 Z = result_at(buf, d, k), Zn = result_at(buf, d, kn);
+        const int k = m < N ? m : m % N, kn = k ? N - k : 0;  // m mod n, (n - k) mod n
+        const double2 Z = result_at(buf, d, ch, k), Zn = result_at(buf, d, ch, kn);
         // S_a = (Z_k + conj Z_{n-k}) / 2, S_b = (Z_k - conj Z_{n-k}) / (2i)
         const double2 Sa = make_double2(0.5 * (Z.x + Zn.x), 0.5 * (Z.y - Zn.y));
         const double2 Sb = make_double2(0.5 * (Z.y + Zn.y), -0.5 * (Z.x - Zn.x));
@@ -753,7 +940,8 @@ int set_lds_attr() {
     return SHT_OK;
 }
 
-static_assert((tw_entries<kMaxFftLen>() + padded_len<kMaxFftLen>()) * sizeof(double2) <= kMaxLds, "largest class fits LDS");
+static_assert((tw_entries<kMaxFftLen>() + chirp_entries<kMaxFftLen>() + padded_len<kMaxFftLen>()) * sizeof(double2) <= kMaxLds,
+              "largest class fits LDS");
 
 // the phase tables of a job's two rings; used for mmax < 64 kPhHiMax when
 // they fit next to the other LDS data
@@ -765,7 +953,7 @@ int phase_tables_fit(int mmax, size_t lds) {
 // LDS bytes and layout flags of class MAXL for a plan of this mmax
 template <int MAXL>
 size_t class_lds(int mmax, bool synthesis, int *fold_rows, int *ph_tab) {
-    const size_t base = (size_t)(tw_entries<MAXL>() + padded_len<MAXL>()) * sizeof(double2);
+    const size_t base = (size_t)(tw_entries<MAXL>() + chirp_entries<MAXL>() + padded_len<MAXL>()) * sizeof(double2);
     const size_t rows = 2 * (size_t)(mmax + 1) * sizeof(double2);
     // the small-length class of synthesis keeps the phased terms in LDS when they fit
     *fold_rows = (synthesis && MAXL <= 1024 && base + rows <= kMaxLds) ? 1 : 0;

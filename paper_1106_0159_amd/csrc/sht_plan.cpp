@@ -360,6 +360,12 @@ static bool factor_all(int n, std::vector<int> &rad) {
     return (int)rad.size() <= kMaxRadices;
 }
 
+// Cost of a prime-radix stage in flops per point and unit of R, against 400
+// per point of Bluestein's length: of the weights 12, 6, 4 and 3 the last
+// timed best with the mirror-paired stage (ring stages at HEALPix 1024,
+// one map and 64 maps).
+constexpr double kPrimeCost = 3.0;
+
 static bool smooth5(int n) {
     for (int p : {2, 3, 5})
         while (n % p == 0) n /= p;
@@ -445,16 +451,16 @@ static int fft_desc(FftCache &fc, int n, FftDesc *out, FftAdded &added) {
     std::vector<int> rad;
     int rc;
     // Direct transform of length n when it is 5-smooth, or when its direct
-    // R-term stages (about 12 R flops per point each) cost less than
-    // Bluestein's two transforms of length L >= 2n - 1 (taken as 400 flops
-    // per point of L: of 200, 400 and 800, the weight that timed best here),
-    // or when Bluestein's L would not fit the largest class.
+    // R-term stages (with the mirror-paired inputs about kPrimeCost R flops
+    // per point each) cost less than Bluestein's two transforms of length
+    // L >= 2n - 1 (taken as 400 flops per point of L), or when Bluestein's L
+    // would not fit the largest class.
     int Lb = 2 * n - 1;
     while (!smooth5(Lb)) ++Lb;
     std::vector<int> all;
     const bool all_ok = factor_all(n, all);
     double direct = 0.0;
-    for (int f : all) direct += f > 5 ? 12.0 * f * n : 0.0;
+    for (int f : all) direct += f > 5 ? kPrimeCost * f * n : 0.0;
     if (factor_small(n, rad)) {
         d.L = n;
         d.bluestein = 0;
@@ -489,6 +495,20 @@ static int fft_desc(FftCache &fc, int n, FftDesc *out, FftAdded &added) {
         d.kern = dk;
     }
     if (d.L > kMaxFftLen) return SHT_EUNSUPPORTED;
+    // Stockham stages may come in any order: with two radix-8/4 factors or
+    // more, one of them goes last, so that both the first and the last stage
+    // can move their points through registers (pixels in, pixels out)
+    // instead of LDS.
+    {
+        int n84 = 0, last84 = -1;
+        for (int i = 0; i < (int)rad.size(); ++i)
+            if (rad[i] == 8 || rad[i] == 4) ++n84, last84 = i;
+        if (n84 >= 2 && last84 != (int)rad.size() - 1) {
+            const int r = rad[last84];
+            rad.erase(rad.begin() + last84);
+            rad.push_back(r);
+        }
+    }
     d.nrad = (int)rad.size();
     for (int i = 0; i < d.nrad; ++i) d.rad[i] = rad[i];
     if ((rc = twiddle_table(fc, d.L, &d.tw, added))) return rc;
