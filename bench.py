@@ -592,7 +592,8 @@ def main():
                     help="skip the launch-bound lmax=256 latency leg (e.g. to profile the main step alone)")
     ap.add_argument("--copy-probe", type=int, default=0, help="run only a device copy of this many bytes")
     ap.add_argument("--peak-probe", action="store_true",
-                    help="run only the throughput probes (FP64 FMA, FP32 and BF16 matrix instructions)")
+                    help="run only the throughput probes (FP64 FMA, FP32 and BF16 matrix instructions, and "
+                         "whether FP32 matrix and FP64 vector work overlap)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); run it with --gpus 1.",
@@ -603,8 +604,8 @@ def main():
         return
     if args.peak_probe:
         from paper_1106_0159_amd import probe
-        rates = [probe.rate(k) for k in probe.KINDS]
-        print(json.dumps({"peak_probe": rates,
+        rates = [probe.rate(k) for k in probe.KINDS if k != "fp32_mfma_with_fp64_fma"]
+        print(json.dumps({"peak_probe": rates, "coexec": probe.coexec(),
                           "nominal_tflops": {"fp64_fma": PEAK_FP64_VALU_TFLOPS,
                                              "fp32_mfma_16x16x4": PEAK_FP32_MFMA_TFLOPS,
                                              "bf16_mfma_16x16x32": 2500.0}}))

@@ -8,7 +8,8 @@ import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(os.path.dirname(_HERE), "libsht_probe.so")
-KINDS = {"fp64_fma": 0, "fp32_mfma_16x16x4": 1, "bf16_mfma_16x16x32": 2}  # sht_probe.h
+KINDS = {"fp64_fma": 0, "fp32_mfma_16x16x4": 1, "bf16_mfma_16x16x32": 2,
+         "fp32_mfma_with_fp64_fma": 3}  # sht_probe.h
 EXPORTS = ("sht_probe_flops", "sht_probe_run")
 
 _lib = None
@@ -49,3 +50,16 @@ def rate(kind: str, blocks: int = 8192, iters: int = 4000, device="cuda") -> dic
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
     return {"kind": kind, "blocks": blocks, "iters": iters, "flops": flops, "ms": ms, "tflops": flops / ms / 1e9}
+
+
+def coexec(blocks: int = 8192, iters: int = 4000, device="cuda") -> dict:
+    """Whether FP32 matrix instructions and FP64 FMAs overlap: the interleaved
+    probe's time against the FP32 matrix probe at iters plus the FP64 FMA
+    probe at 8 x iters (the same work apart).  overlap = (separate sum -
+    interleaved) / the shorter of the two (0: the times add, 1: full overlap)."""
+    mf = rate("fp32_mfma_16x16x4", blocks, iters, device)
+    fm = rate("fp64_fma", blocks, 8 * iters, device)
+    both = rate("fp32_mfma_with_fp64_fma", blocks, iters, device)
+    sep = mf["ms"] + fm["ms"]
+    return {"blocks": blocks, "iters": iters, "mfma_ms": mf["ms"], "fma64_ms": fm["ms"], "separate_sum_ms": sep,
+            "interleaved_ms": both["ms"], "overlap": (sep - both["ms"]) / min(mf["ms"], fm["ms"])}

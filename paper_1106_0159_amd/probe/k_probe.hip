@@ -1,7 +1,8 @@
 // Throughput probes (sht_probe.h; a benchmark-only library, libsht_probe.so,
 // separate from the transform library): long runs of independent FP64 FMAs,
-// FP32 16x16x4 and BF16 16x16x32 matrix instructions, with no memory traffic
-// in the loop.
+// FP32 16x16x4 and BF16 16x16x32 matrix instructions, and FP32 matrix
+// instructions interleaved with FP64 FMAs (do the two overlap?), with no
+// memory traffic in the loop.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -57,6 +58,34 @@ __global__ __launch_bounds__(kProbeThreads) void k_probe_mfma(int iters, double 
     out[(int64_t)blockIdx.x * kProbeThreads + threadIdx.x] = s;
 }
 
+// kChains FP32 16x16x4 matrix instructions and kChains x kChains independent
+// FP64 FMAs per iteration, interleaved (one matrix instruction, then kChains
+// FMAs, as the compiler schedules them): its time against the sum of the two
+// pure streams shows whether vector and matrix work overlap.
+__global__ __launch_bounds__(kProbeThreads) void k_probe_mixed(int iters, double *__restrict__ out) {
+    const float x = 1e-3f * threadIdx.x;
+    const double dx = 1.0 + 1e-9 * threadIdx.x, y = 1.0 - 1e-12;
+    floatx4 acc[kChains];
+    double a[kChains];
+#pragma unroll
+    for (int i = 0; i < kChains; ++i) {
+        acc[i] = floatx4{0.f, 0.f, 0.f, 0.f};
+        a[i] = dx + i;
+    }
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int i = 0; i < kChains; ++i) {
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x4f32(x, x + i, acc[i], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < kChains; ++j) a[j] = fma(a[j], y, dx);
+        }
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < kChains; ++i) s += a[i] + acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
+    out[(int64_t)blockIdx.x * kProbeThreads + threadIdx.x] = s;
+}
+
 }  // namespace
 
 extern "C" {
@@ -68,6 +97,8 @@ double sht_probe_flops(int kind, int blocks, int iters) {
         case SHT_PROBE_FMA_F64: return threads * iters * kChains * 2.0;
         case SHT_PROBE_MFMA_F32: return waves * iters * kChains * (2.0 * 16 * 16 * 4);
         case SHT_PROBE_MFMA_BF16: return waves * iters * kChains * (2.0 * 16 * 16 * 32);
+        case SHT_PROBE_MFMA_F32_FMA_F64:
+            return waves * iters * kChains * (2.0 * 16 * 16 * 4) + threads * iters * kChains * kChains * 2.0;
         default: return 0.0;
     }
 }
@@ -84,9 +115,12 @@ int sht_probe_run(int kind, int blocks, int iters, void *out, void *stream) {
             hipLaunchKernelGGL(k_probe_mfma<SHT_PROBE_MFMA_F32>, dim3((unsigned)blocks), dim3(kProbeThreads), 0, st,
                                iters, o);
             break;
-        default:
+        case SHT_PROBE_MFMA_BF16:
             hipLaunchKernelGGL(k_probe_mfma<SHT_PROBE_MFMA_BF16>, dim3((unsigned)blocks), dim3(kProbeThreads), 0,
                                st, iters, o);
+            break;
+        default:
+            hipLaunchKernelGGL(k_probe_mixed, dim3((unsigned)blocks), dim3(kProbeThreads), 0, st, iters, o);
             break;
     }
     return hipGetLastError() == hipSuccess ? 0 : -3;

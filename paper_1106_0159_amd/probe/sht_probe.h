@@ -20,8 +20,16 @@ extern "C" {
  *   0  FP64 FMA on the vector ALUs (v_fma_f64), 8 independent chains per lane
  *   1  FP32 matrix instruction v_mfma_f32_16x16x4_f32, 8 independent accumulators per wave
  *   2  BF16 matrix instruction v_mfma_f32_16x16x32_bf16, 8 independent accumulators per wave
+ *   3  kinds 1 and 0 interleaved: per iteration 8 FP32 matrix instructions and
+ *      64 FP64 FMAs per lane (the work of kind 1 at the same iters plus kind 0
+ *      at 8 x iters), to time whether vector and matrix work overlap
  * Workgroups of 256 threads. */
-enum sht_probe_kind { SHT_PROBE_FMA_F64 = 0, SHT_PROBE_MFMA_F32 = 1, SHT_PROBE_MFMA_BF16 = 2 };
+enum sht_probe_kind {
+    SHT_PROBE_FMA_F64 = 0,
+    SHT_PROBE_MFMA_F32 = 1,
+    SHT_PROBE_MFMA_BF16 = 2,
+    SHT_PROBE_MFMA_F32_FMA_F64 = 3
+};
 
 /* Floating-point operations one sht_probe_run with these arguments performs
  * (an FMA counts 2); 0 for invalid arguments (unknown kind, blocks or iters

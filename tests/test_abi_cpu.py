@@ -214,7 +214,7 @@ def test_probe_library_is_separate_and_checks_arguments():
     (libsht_probe.so, probe/sht_probe.h), not in the transform library.  Flop
     counts: 256 threads per workgroup, 8 chains; FP64 FMA 2 flops per lane
     and step, matrix instructions 2*16*16*K per wave and step (K = 4 for FP32,
-    32 for BF16)."""
+    32 for BF16); the interleaved probe is the sum of its two streams."""
     from paper_1106_0159_amd import probe
     if not os.path.exists(probe.LIB_PATH):
         pytest.skip("libsht_probe.so not built")
@@ -226,7 +226,10 @@ def test_probe_library_is_separate_and_checks_arguments():
     assert P.sht_probe_flops(0, blocks, iters) == blocks * 256 * iters * 8 * 2
     assert P.sht_probe_flops(1, blocks, iters) == blocks * 4 * iters * 8 * 2 * 16 * 16 * 4
     assert P.sht_probe_flops(2, blocks, iters) == blocks * 4 * iters * 8 * 2 * 16 * 16 * 32
-    for kind, b, it in [(3, 1, 1), (-1, 1, 1), (0, 0, 1), (0, 1, 0)]:
+    # kinds 1 and 0 interleaved: kind 1 at iters plus kind 0 at 8 x iters
+    assert P.sht_probe_flops(3, blocks, iters) == (P.sht_probe_flops(1, blocks, iters)
+                                                   + P.sht_probe_flops(0, blocks, 8 * iters))
+    for kind, b, it in [(4, 1, 1), (-1, 1, 1), (0, 0, 1), (0, 1, 0)]:
         assert P.sht_probe_flops(kind, b, it) == 0.0
     # rejected on the host, before any device call
     assert P.sht_probe_run(0, 1, 1, None, None) == -1
