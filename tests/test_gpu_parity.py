@@ -344,6 +344,36 @@ def test_stage_entry_points_several_maps(sht):
         assert relrms(dd[i], oracle.map2delta(lmax, g, mp[i])) <= TOL
 
 
+def test_ring_stages_prime_radix_lengths(sht):
+    """Ring lengths whose prime factors above 5 run the mirror-paired direct
+    stage, in every length class: 4095 = 3^2 5 7 13 and 8190 = 2 3^2 5 7 13
+    (radix 13 fills the most work items per thread, in the 4096 and 8192
+    classes), 8173 = 11 x 743 (a 743-point stage: Bluestein would exceed the
+    largest class), 1001 = 7 11 13, 4 x 61, 4 x 97, and for contrast 4091
+    (prime: Bluestein on 8192 points) and 139 (prime).  Both ring stages
+    against the oracle's plain DFTs, rings at arbitrary colatitudes (no
+    mirror pairs) and phases."""
+    nphi = np.array([4095, 8190, 8173, 1001, 244, 388, 4091, 139], dtype=np.int32)
+    nr = nphi.size
+    rng = np.random.default_rng(41)
+    th = np.sort(rng.uniform(0.05, math.pi - 0.05, nr))
+    g = si._pack(th, nphi, rng.uniform(-1.0, 2.0, nr), rng.uniform(0.2, 1.0, nr), "prime_lengths")
+    for mmax in (40, 600):
+        d = rng.standard_normal((nr, mmax + 1)) + 1j * rng.standard_normal((nr, mmax + 1))
+        say(f"prime ring lengths delta2map mmax={mmax}")
+        ref = oracle.delta2map(mmax, g, d)
+        got = host(sht.delta2map(dev(d), g, mmax))
+        for r in range(nr):
+            o, n = int(g.ofs[r]), int(nphi[r])
+            assert relrms(got[o:o + n], ref[o:o + n]) <= TOL, (mmax, n, relrms(got[o:o + n], ref[o:o + n]))
+        s_map = si.random_map(g, 42 + mmax)
+        say(f"prime ring lengths map2delta mmax={mmax}")
+        ref = oracle.map2delta(mmax, g, s_map)
+        got = host(sht.map2delta(dev(s_map), g, mmax))
+        for r in range(nr):
+            assert relrms(got[r], ref[r]) <= TOL, (mmax, int(nphi[r]), relrms(got[r], ref[r]))
+
+
 def test_gl_lmax2048_direct_prime_radices(sht):
     """Gauss-Legendre, 2049 rings of 4097 = 17 x 241 points, lmax = 2048: the
     ring transforms run as direct radix-17 and radix-241 stages (Bluestein's
