@@ -731,12 +731,26 @@ __global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan 
     const bool two = js.two;
     const DescP d = ro(P.descs) + P.ring_desc[js.ra];
     const int N = d->n, L = d->L;
+    const double2 *__restrict__ Da = P.din + js.ma * dl.s_map + js.ra * dl.s_ring;
+    const double2 *__restrict__ Db = P.din + js.mb * dl.s_map + js.rb * dl.s_ring;
+    const bool lds_fold = fold_rows && (2 * N < mmax + 1);
+    const double2 z = make_double2(0.0, 0.0);
+    // the first Delta of each bin of pair (k, n-k): c_a(k), c_a(n-k), c_b(k), c_b(n-k)
+    auto first = [&](int k, double2 &a0, double2 &a1, double2 &b0, double2 &b1) {
+        const int kn = k ? N - k : 0;  // (n - k) mod n, k < n
+        const bool ok = !lds_fold && 2 * k <= N;
+        a0 = (ok && k <= mmax) ? Da[k * dl.s_m] : z;
+        a1 = (ok && kn <= mmax) ? Da[kn * dl.s_m] : z;
+        b0 = (ok && two && k <= mmax) ? Db[k * dl.s_m] : z;
+        b1 = (ok && two && kn <= mmax) ? Db[kn * dl.s_m] : z;
+    };
+    // this thread's first bin: its loads are in flight while the tables are set up
+    double2 ca0, ca1, cb0, cb1;
+    first(threadIdx.x, ca0, ca1, cb0, cb1);
     load_twiddles<NT>(tlo, thi, d->tw, L);
     const bool blue = d->bluestein != 0;
     Chirp ch{clo, chi, N, 0.0};
     if (blue) ch = load_chirp<NT>(clo, chi, N);
-    const double2 *__restrict__ Da = P.din + js.ma * dl.s_map + js.ra * dl.s_ring;
-    const double2 *__restrict__ Db = P.din + js.mb * dl.s_map + js.rb * dl.s_ring;
     const double pa = P.phi0[js.ra], pb = P.phi0[js.rb];
     Phase pha{nullptr, nullptr, pa}, phb{nullptr, nullptr, pb};
     if (P.ph_tab) {
@@ -746,7 +760,6 @@ __global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan 
         if (two && js.rb != js.ra) phb = load_phases<NT>(tab + kPhLo + phase_hi_entries(mmax), mmax, pb);
     }
     if (P.ph_tab || blue) __syncthreads();  // phase and chirp tables visible
-    const bool lds_fold = fold_rows && (2 * N < mmax + 1);
     int lim = mmax;  // last index of the phased-term rows that the bins fold
     if (lds_fold) {
         // all threads evaluate phases; short rings first sum the rows in columns
@@ -763,7 +776,6 @@ __global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan 
     // thread handles the bin pairs (k, n-k), k = threadIdx.x + u NT <= n/2:
     // u < U for every thread, and k = U NT (only when n = MAXL) by thread 0
     constexpr int U = MAXL / (2 * NT);
-    const double2 z = make_double2(0.0, 0.0);
     auto put = [&](int k, double2 a0, double2 a1, double2 b0, double2 b1) {
         const int kn = k ? N - k : 0;  // (n - k) mod n, k < n
         // h_k = (c_k + conj c_{n-k}) / 2, h_{n-k} = conj h_k
@@ -792,31 +804,24 @@ __global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan 
             b1 = two ? fold_bin(kn <= mmax ? bin_term(b1, kn, phb) : z, Db, dl.s_m, kn, N, mmax, phb) : z;
         }
     };
-    auto first = [&](int k, double2 &a0, double2 &a1, double2 &b0, double2 &b1) {
-        const int kn = k ? N - k : 0;  // (n - k) mod n, k < n
-        const bool ok = !lds_fold && 2 * k <= N;
-        a0 = (ok && k <= mmax) ? Da[k * dl.s_m] : z;
-        a1 = (ok && kn <= mmax) ? Da[kn * dl.s_m] : z;
-        b0 = (ok && two && k <= mmax) ? Db[k * dl.s_m] : z;
-        b1 = (ok && two && kn <= mmax) ? Db[kn * dl.s_m] : z;
-    };
-    // the first Delta of each of G bins of this thread is loaded before any
-    // is used (all loads in flight together); aliases m + n <= mmax after
-    constexpr int G = U < 2 ? U : 2;  // registers: 16 per bin
-    // groups of G bins, the last one also covering k = U NT (thread 0, n = MAXL)
+    // bins k = threadIdx.x + u NT, u = 0 .. U (k = U NT only for thread 0 when
+    // n = MAXL): the first Delta values of the next bin are loaded while this
+    // one is folded, so that only the first load's latency is exposed;
+    // aliases m + n <= mmax are loaded by the fold
 #pragma unroll 1
-    for (int u0 = 0; u0 <= U; u0 += G) {
-        double2 a0[G], a1[G], b0[G], b1[G];
-#pragma unroll
-        for (int u = 0; u < G; ++u) first(threadIdx.x + (u0 + u) * NT, a0[u], a1[u], b0[u], b1[u]);
-#pragma unroll
-        for (int u = 0; u < G; ++u) {
-            const int k = threadIdx.x + (u0 + u) * NT;
-            if (2 * k <= N) {
-                bins(k, a0[u], a1[u], b0[u], b1[u]);
-                put(k, a0[u], a1[u], b0[u], b1[u]);
-            }
+    for (int u = 0; u <= U; ++u) {
+        double2 na0 = z, na1 = z, nb0 = z, nb1 = z;
+        if (u < U) first(threadIdx.x + (u + 1) * NT, na0, na1, nb0, nb1);
+        asm volatile("" ::: "memory");  // compiler-only fence: the loads above issue before the fold below
+        const int k = threadIdx.x + u * NT;
+        if (2 * k <= N) {
+            bins(k, ca0, ca1, cb0, cb1);
+            put(k, ca0, ca1, cb0, cb1);
         }
+        ca0 = na0;
+        ca1 = na1;
+        cb0 = nb0;
+        cb1 = nb1;
     }
     __syncthreads();
     double *outa = P.mout + (int64_t)js.ma * P.npix + P.ofs[js.ra];
