@@ -735,18 +735,17 @@ __global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan 
     const double2 *__restrict__ Db = P.din + js.mb * dl.s_map + js.rb * dl.s_ring;
     const bool lds_fold = fold_rows && (2 * N < mmax + 1);
     const double2 z = make_double2(0.0, 0.0);
-    // the first Delta of each bin of pair (k, n-k): c_a(k), c_a(n-k), c_b(k), c_b(n-k)
-    auto first = [&](int k, double2 &a0, double2 &a1, double2 &b0, double2 &b1) {
-        const int kn = k ? N - k : 0;  // (n - k) mod n, k < n
-        const bool ok = !lds_fold && 2 * k <= N;
-        a0 = (ok && k <= mmax) ? Da[k * dl.s_m] : z;
-        a1 = (ok && kn <= mmax) ? Da[kn * dl.s_m] : z;
-        b0 = (ok && two && k <= mmax) ? Db[k * dl.s_m] : z;
-        b1 = (ok && two && kn <= mmax) ? Db[kn * dl.s_m] : z;
-    };
-    // this thread's first bin: its loads are in flight while the tables are set up
-    double2 ca0, ca1, cb0, cb1;
-    first(threadIdx.x, ca0, ca1, cb0, cb1);
+    // Delta at m = k of every bin k = threadIdx.x + u NT of this thread (both
+    // rings): all in flight while the tables are set up
+    constexpr int U = MAXL / (2 * NT);
+    double2 fa[U + 1], fb[U + 1];
+#pragma unroll
+    for (int u = 0; u <= U; ++u) {
+        const int k = threadIdx.x + u * NT;
+        const bool ok = !lds_fold && 2 * k <= N && k <= mmax;
+        fa[u] = ok ? Da[k * dl.s_m] : z;
+        fb[u] = (ok && two) ? Db[k * dl.s_m] : z;
+    }
     load_twiddles<NT>(tlo, thi, d->tw, L);
     const bool blue = d->bluestein != 0;
     Chirp ch{clo, chi, N, 0.0};
@@ -775,7 +774,6 @@ __global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan 
     }
     // thread handles the bin pairs (k, n-k), k = threadIdx.x + u NT <= n/2:
     // u < U for every thread, and k = U NT (only when n = MAXL) by thread 0
-    constexpr int U = MAXL / (2 * NT);
     auto put = [&](int k, double2 a0, double2 a1, double2 b0, double2 b1) {
         const int kn = k ? N - k : 0;  // (n - k) mod n, k < n
         // h_k = (c_k + conj c_{n-k}) / 2, h_{n-k} = conj h_k
@@ -805,23 +803,21 @@ __global__ __launch_bounds__(NT, 4) void k_fft_syn(RingPlan one, const RingPlan 
         }
     };
     // bins k = threadIdx.x + u NT, u = 0 .. U (k = U NT only for thread 0 when
-    // n = MAXL): the first Delta values of the next bin are loaded while this
-    // one is folded, so that only the first load's latency is exposed;
-    // aliases m + n <= mmax are loaded by the fold
-#pragma unroll 1
+    // n = MAXL); the second Delta of a bin pair (m = n - k) exists only for
+    // rings shorter than 2 mmax + 1, and aliases m + n <= mmax are loaded by
+    // the fold
+#pragma unroll
     for (int u = 0; u <= U; ++u) {
-        double2 na0 = z, na1 = z, nb0 = z, nb1 = z;
-        if (u < U) first(threadIdx.x + (u + 1) * NT, na0, na1, nb0, nb1);
-        asm volatile("" ::: "memory");  // compiler-only fence: the loads above issue before the fold below
         const int k = threadIdx.x + u * NT;
+        const int kn = k ? N - k : 0;  // (n - k) mod n, k < n
+        const bool ok = !lds_fold && 2 * k <= N && kn <= mmax;
+        double2 a0 = fa[u], b0 = fb[u];
+        double2 a1 = ok ? Da[kn * dl.s_m] : z;
+        double2 b1 = (ok && two) ? Db[kn * dl.s_m] : z;
         if (2 * k <= N) {
-            bins(k, ca0, ca1, cb0, cb1);
-            put(k, ca0, ca1, cb0, cb1);
+            bins(k, a0, a1, b0, b1);
+            put(k, a0, a1, b0, b1);
         }
-        ca0 = na0;
-        ca1 = na1;
-        cb0 = nb0;
-        cb1 = nb1;
     }
     __syncthreads();
     double *outa = P.mout + (int64_t)js.ma * P.npix + P.ofs[js.ra];
