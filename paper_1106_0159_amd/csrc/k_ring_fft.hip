@@ -313,8 +313,8 @@ template <int MAXL, int NT>
 __device__ __forceinline__ void fft_stage_generic(double2 *buf, int L, int Ns, int R, TwLds tw) {
     constexpr int kAnchor = 16;
     constexpr int kPairs = 2;  // output pairs per item
-    // items per thread: at most L (R + 5) / (4 R) / NT items of pass 2 (R >= 7);
-    // 0.31 MAXL / NT at R = 13 is the most
+    // pass 2 has (L / R) floor((R + 3) / 4) items; over the primes R >= 7 that
+    // is at most 0.31 L (R = 13), so 0.31 MAXL / NT items per thread
     constexpr int kMaxItems = (4 * MAXL / NT + 12) / 13;
     const int nbf = L / R, h = (R - 1) / 2;
     const int tstep = L / (Ns * R);
