@@ -844,11 +844,22 @@ int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const StartTable &s, 
     // lane (faster than 4 maps and 2 slots: 29.7 against 30.6 ms for 64 maps
     // at HEALPix 1024 / lmax 2048)
     if (nmaps >= 2) return launch_syn_mm<4, 2>(A, p.nslots, c.mmax, nmaps, st);
-    constexpr int T = kSynSlotsPerLane;
+    // Slots per lane: kSynSlotsPerLane for large geometries.  With few slots a
+    // tile of kSynSlotsPerLane per lane would leave most lanes of the
+    // workgroup idle while one wave walks the l-recurrences of all of them in
+    // turn, and small transforms are bound by that sequential walk of the
+    // longest m: one or two slots per lane spread it over more lanes (at
+    // lmax 256 on 129 slots, 17.7 -> 6 us for the kernel).
+    const int T = p.nslots <= kBlock ? 1 : p.nslots <= 2 * kBlock ? 2 : kSynSlotsPerLane;
     const int tiles = (p.nslots + kBlock * T - 1) / (kBlock * T);
     const int64_t gx = (int64_t)tiles * padded_m(c.mmax);
     if (!grid_ok(gx)) return SHT_EUNSUPPORTED;
-    hipLaunchKernelGGL(k_leg_syn<T>, dim3((unsigned)gx, (unsigned)nmaps), dim3(kBlock), 0, st, A, tiles);
+    const dim3 grid((unsigned)gx, (unsigned)nmaps);
+    switch (T) {
+        case 1: hipLaunchKernelGGL(k_leg_syn<1>, grid, dim3(kBlock), 0, st, A, tiles); break;
+        case 2: hipLaunchKernelGGL(k_leg_syn<2>, grid, dim3(kBlock), 0, st, A, tiles); break;
+        default: hipLaunchKernelGGL(k_leg_syn<kSynSlotsPerLane>, grid, dim3(kBlock), 0, st, A, tiles); break;
+    }
     SHT_HIP(hipGetLastError());
     return SHT_OK;
 }
