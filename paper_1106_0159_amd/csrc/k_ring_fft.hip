@@ -490,7 +490,7 @@ __device__ __forceinline__ void transform(double2 *buf, DescP d, TwLds tw, In in
 // per-length table in memory.
 constexpr int kChLo = 64;
 template <int MAXL>
-constexpr int chirp_entries() { return kChLo + MAXL / kChLo + 1; }  // 2n <= MAXL + 1
+constexpr int chirp_entries() { return kChLo + MAXL / kChLo + 1; }  // 2n <= L + 2 <= MAXL + 2
 __device__ __forceinline__ double2 e_pi_over(int r, int n) {
     const int n2 = 2 * n;
     r %= n2;

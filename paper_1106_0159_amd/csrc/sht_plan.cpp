@@ -452,10 +452,15 @@ static int fft_desc(FftCache &fc, int n, FftDesc *out, FftAdded &added) {
     int rc;
     // Direct transform of length n when it is 5-smooth, or when its direct
     // R-term stages (with the mirror-paired inputs about kPrimeCost R flops
-    // per point each) cost less than Bluestein's two transforms of length
-    // L >= 2n - 1 (taken as 400 flops per point of L), or when Bluestein's L
-    // would not fit the largest class.
-    int Lb = 2 * n - 1;
+    // per point each) cost less than Bluestein's two transforms of length L
+    // (taken as 400 flops per point of L), or when Bluestein's L would not
+    // fit the largest class.
+    // Bluestein's cyclic convolution takes the chirp at offsets -(n-1) ..
+    // n-1.  The chirp is even in its offset, so the one pair of offsets that
+    // share an index modulo L = 2n - 2, +-(n-1), needs the same value there:
+    // L >= 2n - 2 is exact (L = 4096 for n = 2049 = 2 lmax + 1 at lmax 1024,
+    // where L >= 2n - 1 would take 4320 and the 8192 class).
+    int Lb = n > 1 ? 2 * n - 2 : 1;
     while (!smooth5(Lb)) ++Lb;
     std::vector<int> all;
     const bool all_ok = factor_all(n, all);
@@ -475,7 +480,8 @@ static int fft_desc(FftCache &fc, int n, FftDesc *out, FftAdded &added) {
         factor_small(L, rad);
         // chirp b_t = exp(i pi t^2 / n), angle reduced exactly: t^2 mod 2n
         // (the kernels compute b_t themselves; the plan keeps the spectrum of
-        // its extension to length L)
+        // its extension to length L: b at t and at L - t, which are one index
+        // for t = n - 1 when L = 2n - 2, with the same value)
         std::vector<cld> ext(L, cld(0, 0));
         for (int t = 0; t < n; ++t) {
             const long long q = (long long)t * t % (2LL * n);

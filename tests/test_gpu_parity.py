@@ -374,10 +374,39 @@ def test_ring_stages_prime_radix_lengths(sht):
             assert relrms(got[r], ref[r]) <= TOL, (mmax, int(nphi[r]), relrms(got[r], ref[r]))
 
 
+def test_ring_stages_bluestein_shortest_length(sht):
+    """Bluestein at its shortest cyclic length L = 2n - 2 (5-smooth n - 1):
+    641 -> 1280, 1153 -> 2304, 2049 = 3 x 683 -> 4096 and 3457 -> 6912, one
+    per length class from 2048 up; offsets +-(n-1) of the even chirp share
+    one index there.  For contrast 4091 (L = 8192 > 2n - 2) and 1021 (L =
+    2048).  Both ring stages against the oracle's plain DFTs, rings at
+    arbitrary colatitudes and phases, with mmax below and above n / 2 (bins
+    folding several m)."""
+    nphi = np.array([641, 1153, 2049, 3457, 4091, 1021], dtype=np.int32)
+    nr = nphi.size
+    rng = np.random.default_rng(43)
+    th = np.sort(rng.uniform(0.05, math.pi - 0.05, nr))
+    g = si._pack(th, nphi, rng.uniform(-1.0, 2.0, nr), rng.uniform(0.2, 1.0, nr), "bluestein_short")
+    for mmax in (300, 2500):
+        d = rng.standard_normal((nr, mmax + 1)) + 1j * rng.standard_normal((nr, mmax + 1))
+        say(f"Bluestein L = 2n - 2 delta2map mmax={mmax}")
+        ref = oracle.delta2map(mmax, g, d)
+        got = host(sht.delta2map(dev(d), g, mmax))
+        for r in range(nr):
+            o, n = int(g.ofs[r]), int(nphi[r])
+            assert relrms(got[o:o + n], ref[o:o + n]) <= TOL, (mmax, n, relrms(got[o:o + n], ref[o:o + n]))
+        s_map = si.random_map(g, 44 + mmax)
+        say(f"Bluestein L = 2n - 2 map2delta mmax={mmax}")
+        ref = oracle.map2delta(mmax, g, s_map)
+        got = host(sht.map2delta(dev(s_map), g, mmax))
+        for r in range(nr):
+            assert relrms(got[r], ref[r]) <= TOL, (mmax, int(nphi[r]), relrms(got[r], ref[r]))
+
+
 def test_gl_lmax2048_direct_prime_radices(sht):
     """Gauss-Legendre, 2049 rings of 4097 = 17 x 241 points, lmax = 2048: the
-    ring transforms run as direct radix-17 and radix-241 stages (Bluestein's
-    length would exceed the largest LDS class).  FP64 against the oracle on
+    ring transforms run as direct radix-17 and radix-241 stages (by the plan's
+    cost model cheaper than Bluestein on 8192 points, the largest class).  FP64 against the oracle on
     every fourth ring (synthesis) and every fourth m (analysis of a white-noise
     map), each set aggregated at 1e-12, and per ring / per m column."""
     lmax = 2048
