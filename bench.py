@@ -154,8 +154,9 @@ def run_batch(sht, gh, g, lmax, alm, steps, warmup, flags):
     stage.  With SHT_MIXED, Delta is kept as sht_alm2map / sht_map2alm keep
     it (the stage calls give the same bits as the combined ones): map-minor,
     [nrings][mmax+1][nmaps], in synthesis from 8 maps on, ring-major in
-    analysis.  Returns (stage ms, per-batch ms list, wall ms per batch, map,
-    a_lm')."""
+    analysis.  SHT_MIXED_SPLIT_BF16, a synthesis variant, goes to the
+    synthesis call only.  Returns (stage ms, per-batch ms list, wall ms per
+    batch, map, a_lm')."""
     import numpy as np
     import torch
     dev = alm.device
@@ -184,7 +185,7 @@ def run_batch(sht, gh, g, lmax, alm, steps, warmup, flags):
         mark(2)
         sht.map2delta(mp, gh, lmax, out=delta_s)
         mark(3)
-        sht.delta2alm(delta_s, gh, lmax, lmax, out=a_out, ws=ws, flags=flags)
+        sht.delta2alm(delta_s, gh, lmax, lmax, out=a_out, ws=ws, flags=flags & ~sht.SHT_MIXED_SPLIT_BF16)
         mark(4)
 
     for _ in range(warmup):
@@ -270,8 +271,10 @@ def batched_legs(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a_
     relative RMS differences of its map and of its analysed a_lm to the plain
     results are reported, and every map of the mixed batch against the FP64
     batch.  "variants" gives maps/s and the largest errors against the FP64
-    batch of the plain FP32 l-chain and of SHT_MIXED_FP64_SUMS (synthesis
-    block sums added in FP64)."""
+    batch of the plain FP32 l-chain, of SHT_MIXED_FP64_SUMS (synthesis
+    block sums added in FP64) and of SHT_MIXED_SPLIT_BF16 (synthesis products
+    from three-way bf16 splits of the FP32 operands on the bf16 matrix cores;
+    analysis as the FP32 chain)."""
     alm = power_law_batch(si, lmax, nmaps, 2)
     flops_mx = 4 * nmaps * count_triples(nslots, lmax, lmax)
     st, bm, wall, mp_x, a_x = run_batch(sht, gh, g, lmax, alm, steps, warmup, sht.SHT_MIXED)
@@ -297,6 +300,14 @@ def batched_legs(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a_
     e_map, e_alm = rel_per_map(mp_c, mp_d), rel_per_map(a_c, a_d)
     comp["relrms_vs_fp64_batch"] = {"map_max": max(e_map), "map_mean": sum(e_map) / nmaps,
                                     "alm_max": max(e_alm), "alm_mean": sum(e_alm) / nmaps}
+    del mp_c, a_c
+    # the split low-precision variant of the synthesis products
+    fsp = sht.SHT_MIXED | sht.SHT_MIXED_SPLIT_BF16
+    st, bm, wall, mp_s, a_s = run_batch(sht, gh, g, lmax, alm, steps, warmup, fsp)
+    spl = batch_record(nmaps, st, bm, wall, steps, "f64 recurrence, 3 x bf16 split synthesis products", flops_mx,
+                       PEAK_FP32_MFMA_TFLOPS, "mfma", MX_KERNELS)
+    e_map_s, e_alm_s = rel_per_map(mp_s, mp_d), rel_per_map(a_s, a_d)
+    del mp_s, a_s
     mx["variants"] = {
         "fp32_chain": {"value": mx["value"], "map_relrms_max": mx["relrms_vs_fp64_batch"]["map_max"],
                        "alm_relrms_max": mx["relrms_vs_fp64_batch"]["alm_max"]},
@@ -304,8 +315,10 @@ def batched_legs(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a_
                             "stages_ms": comp["stages_ms"],
                             "map_relrms_max": comp["relrms_vs_fp64_batch"]["map_max"],
                             "alm_relrms_max": comp["relrms_vs_fp64_batch"]["alm_max"]},
+        "split_bf16x3": {"value": spl["value"], "ms_per_batch": spl["ms_per_batch"],
+                         "stages_ms": spl["stages_ms"], "map_relrms_max": max(e_map_s),
+                         "map_relrms_mean": sum(e_map_s) / nmaps, "alm_relrms_max": max(e_alm_s)},
     }
-    del mp_c, a_c
     mx["fft_roofline"] = fft_roofline(g, lmax, nmaps, mx["stages_ms"])
     f64["fft_roofline"] = fft_roofline(g, lmax, nmaps, f64["stages_ms"])
     mx["direction"] = f64["direction"] = "alm2map+map2alm"

@@ -127,7 +127,19 @@ enum sht_flags {
      * block sums in FP64 (a compensated l-sum; analysis always does so), so
      * the FP32 rounding no longer accumulates over the whole l range.  A wave
      * then covers 8 maps.  Always in effect above lmax 2048. */
-    SHT_MIXED_FP64_SUMS = 8u
+    SHT_MIXED_FP64_SUMS = 8u,
+    /* With SHT_MIXED only (alone: SHT_EUNSUPPORTED), and for synthesis only
+     * (sht_alm2map, sht_alm2delta; the analysis calls return
+     * SHT_EUNSUPPORTED): the split low-precision form of the synthesis
+     * matrix products (Sec. 3, eq. matrix_vec).  Each FP32 operand (q_lm and
+     * c_lm a_lm, rounded to FP32 as with SHT_MIXED alone) is split exactly
+     * into three bf16 parts, hi + mid + lo, and each product is the sum of the
+     * six bf16 matrix-core products whose terms exceed 2^-24 of it (hi*hi,
+     * hi*mid, mid*hi, hi*lo, mid*mid, lo*hi), accumulated in FP32.  Combines
+     * with SHT_MIXED_FP64_SUMS.  A wave covers 8 or 16 maps (8 with FP64
+     * block sums).  No effect where SHT_MIXED runs the FP64 kernels (fewer
+     * than 8 maps). */
+    SHT_MIXED_SPLIT_BF16 = 16u
 };
 
 /* Bytes of device workspace needed by sht_alm2map, sht_map2alm,

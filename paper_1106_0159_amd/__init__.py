@@ -24,6 +24,7 @@ SHT_MIXED = 1  # flag: FP32 matrix-core Legendre contraction (include/sht.h)
 SHT_DELTA_MAP_MINOR = 2  # flag: stage-call Delta laid out [nrings][mmax+1][nmaps]
 SHT_PIN = 4  # sht_prepare flag: keep the plan's tables until sht_unpin
 SHT_MIXED_FP64_SUMS = 8  # with SHT_MIXED: synthesis block sums added in FP64
+SHT_MIXED_SPLIT_BF16 = 16  # with SHT_MIXED, synthesis only: three-way bf16 split products
 
 EXPORTS = ("sht_workspace_bytes", "sht_alm2map", "sht_map2alm", "sht_alm2delta", "sht_delta2map",
            "sht_map2delta", "sht_delta2alm", "sht_strerror", "sht_shutdown",

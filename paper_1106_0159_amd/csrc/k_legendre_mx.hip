@@ -40,6 +40,38 @@ namespace sht {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef short shortx4 __attribute__((ext_vector_type(4)));  // four bf16 matrix-core operands
+
+// Split of an FP32 value f into three bf16 parts by truncation: hi keeps the
+// sign, exponent and top 7 fraction bits of f; r = f - hi is exact in FP32
+// and has at most 16 significant bits, mid is its top 8, and lo = r - mid
+// has at most 8, so f = hi + mid + lo exactly (unless lo falls below the
+// normal FP32 range).  Each part is returned in the upper half of an FP32
+// bit pattern whose lower half is zero.
+struct Split3 {
+    uint32_t hi, mid, lo;
+};
+__device__ __forceinline__ Split3 split3(float f) {
+    Split3 s;
+    s.hi = __float_as_uint(f) & 0xffff0000u;
+    const float r = f - __uint_as_float(s.hi);
+    s.mid = __float_as_uint(r) & 0xffff0000u;
+    s.lo = __float_as_uint(r - __uint_as_float(s.mid));
+    return s;
+}
+// bf16 pair (a, b) from the upper halves of two such bit patterns (a in the
+// lower 16 bits)
+__device__ __forceinline__ uint32_t bf16_pair(uint32_t a, uint32_t b) { return __builtin_amdgcn_perm(b, a, 0x07060302u); }
+// the six products of the split operands that carry more than 2^-24 of the
+// whole, smallest first, added to acc
+__device__ __forceinline__ floatx4 mfma_split3(const shortx4 (&a)[3], const shortx4 (&b)[3], floatx4 acc) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[2], b[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1], b[1], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[2], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[1], b[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[1], acc, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[0], b[0], acc, 0, 0, 0);
+}
 
 constexpr int kMxHalf = kMxL / 2;  // k values (l of one parity) per block
 constexpr int kPRow = 5;           // 16-byte words per LDS row: 16 k + 4 floats of padding (conflict-free reads)
@@ -50,18 +82,21 @@ constexpr int kWaves = kBlock / 64;
 // (consecutive threads: consecutive l of one map, so the reads are
 // contiguous) and writes its two columns into the workgroup's tile.  Entries
 // with l > lmax or with a map index >= nmaps are zero, and Im a_l0 is ignored.
-template <int NCF>
+// SPLIT: the tile holds three bf16 planes (hi, mid, lo of split3) of the same
+// layout instead of one FP32 plane.
+template <int NCF, bool SPLIT>
 __global__ __launch_bounds__(kBlock) void k_prescale_mx(int lmax, int nmaps, int64_t nalm, int64_t mxblocks,
                                                       const int64_t *__restrict__ mxofs,
                                                       const double2 *__restrict__ alm,
                                                       const double *__restrict__ cfac,
-                                                      float *__restrict__ out) {
+                                                      void *__restrict__ out) {
     constexpr int NC = 16 * NCF;
-    constexpr int kTile = 2 * NC * kMxHalf;
+    constexpr int kPlane = 2 * NC * kMxHalf;
+    constexpr int kTile = (SPLIT ? 3 : 1) * kPlane;
     const int kb = blockIdx.x, m = blockIdx.y, cg = blockIdx.z;
     if (kb >= mx_blocks(lmax, m)) return;
     const int64_t base = (int64_t)m * (2 * lmax + 1 - m) / 2;
-    float *__restrict__ o = out + ((int64_t)cg * mxblocks + mxofs[m] + kb) * kTile;
+    const int64_t tile = ((int64_t)cg * mxblocks + mxofs[m] + kb) * kTile;
     for (int e = threadIdx.x; e < kMxL * (NC / 2); e += kBlock) {
         const int lt = e % kMxL, mm = e / kMxL;  // l offset in the block, map in the group
         const int l = m + kMxL * kb + lt, map = cg * (NC / 2) + mm;
@@ -72,17 +107,40 @@ __global__ __launch_bounds__(kBlock) void k_prescale_mx(int lmax, int nmaps, int
             re = a.x * c;
             im = m == 0 ? 0.0 : a.y * c;
         }
-        float *__restrict__ t = o + ((lt & 1) * NC + 2 * mm) * kMxHalf + (lt >> 1);
-        t[0] = (float)re;
-        t[kMxHalf] = (float)im;
+        const int at = ((lt & 1) * NC + 2 * mm) * kMxHalf + (lt >> 1);
+        if constexpr (SPLIT) {
+            uint16_t *__restrict__ t = static_cast<uint16_t *>(out) + tile + at;
+            const Split3 r = split3((float)re), i = split3((float)im);
+            t[0] = (uint16_t)(r.hi >> 16);
+            t[kPlane] = (uint16_t)(r.mid >> 16);
+            t[2 * kPlane] = (uint16_t)(r.lo >> 16);
+            t[kMxHalf] = (uint16_t)(i.hi >> 16);
+            t[kPlane + kMxHalf] = (uint16_t)(i.mid >> 16);
+            t[2 * kPlane + kMxHalf] = (uint16_t)(i.lo >> 16);
+        } else {
+            float *__restrict__ t = static_cast<float *>(out) + tile + at;
+            t[0] = (float)re;
+            t[kMxHalf] = (float)im;
+        }
     }
 }
 
-template <int NCF, bool F64S>
+// LDS q tiles of one workgroup: per wave, parity and lane row, the four
+// 4-k words of a block as FP32, or (SPLIT) as bf16 in three planes (8-byte
+// words; a row of 5 words keeps the row writes and the operand reads free of
+// bank conflicts, as kPRow does for the 16-byte words)
+struct QTileF32 {
+    floatx4 v[kWaves][2][64][kPRow];
+};
+struct QTileSplit {
+    uint2 v[kWaves][3][2][64][kPRow];
+};
+
+template <int NCF, bool F64S, bool SPLIT>
 __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, int nslots, int tiles, DeltaLayout dl,
                                                         int nmaps, int64_t mxblocks,
                                                         const int64_t *__restrict__ mxofs,
-                                                        const float *__restrict__ ap,
+                                                        const void *__restrict__ ap,
                                                         const double *__restrict__ alpha,
                                                         const int32_t *__restrict__ lstart,
                                                         const double2 *__restrict__ state,
@@ -91,8 +149,9 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
                                                         const int32_t *__restrict__ rsouth,
                                                         double2 *__restrict__ delta) {
     constexpr int NC = 16 * NCF;
-    constexpr int kTile = 2 * NC * kMxHalf;
-    __shared__ floatx4 pt[kWaves][2][64][kPRow];
+    constexpr int kPlane = 2 * NC * kMxHalf;
+    constexpr int kTile = (SPLIT ? 3 : 1) * kPlane;
+    __shared__ typename std::conditional<SPLIT, QTileSplit, QTileF32>::type pt;
 
     const MPart mp = xcd_m_part(tiles);
     const int m = mp.m, tile = mp.part;
@@ -110,7 +169,7 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
 
     const int64_t base = uniform64((int64_t)m * (2 * lmax + 1 - m) / 2);  // (l, m) lives at base + l
     const double *__restrict__ al = alpha + base;
-    const float *__restrict__ apm = ap + ((int64_t)cg * mxblocks + mxofs[m]) * kTile;
+    const int64_t apm = ((int64_t)cg * mxblocks + mxofs[m]) * kTile;  // this m's tiles (elements)
     const int nb = mx_blocks(lmax, m);
 
     // FP32 accumulators of the matrix instructions; with F64S they hold one
@@ -143,13 +202,23 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
     // kb - 1 runs (the index is clamped, so the load after the last block
     // re-reads it and stays in bounds)
     floatx4 an[2][NCF];
+    shortx4 ans[2][NCF][3];  // SPLIT: hi, mid, lo
     auto load_a = [&](int kb) {
-        const float *__restrict__ t = apm + (int64_t)min(kb, nb - 1) * kTile;
+        const int64_t t = apm + (int64_t)min(kb, nb - 1) * kTile;
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
-            for (int cf = 0; cf < NCF; ++cf)
-                an[p][cf] = *reinterpret_cast<const floatx4 *>(t + p * NC * kMxHalf + (cf * 16 + c16) * kMxHalf + kq * 4);
+            for (int cf = 0; cf < NCF; ++cf) {
+                const int at = p * NC * kMxHalf + (cf * 16 + c16) * kMxHalf + kq * 4;
+                if constexpr (SPLIT) {
+#pragma unroll
+                    for (int h = 0; h < 3; ++h)
+                        ans[p][cf][h] =
+                            *reinterpret_cast<const shortx4 *>(static_cast<const uint16_t *>(ap) + t + h * kPlane + at);
+                } else {
+                    an[p][cf] = *reinterpret_cast<const floatx4 *>(static_cast<const float *>(ap) + t + at);
+                }
+            }
     };
     if (kb0 < nb) load_a(kb0);
     for (int kb = kb0; kb < nb; ++kb) {
@@ -158,10 +227,18 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
         // value ls in its place)
         const int l0 = __builtin_amdgcn_readfirstlane(m + kMxL * kb);
         floatx4 av[2][NCF];
+        shortx4 avs[2][NCF][3];
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
-            for (int cf = 0; cf < NCF; ++cf) av[p][cf] = an[p][cf];
+            for (int cf = 0; cf < NCF; ++cf) {
+                if constexpr (SPLIT) {
+#pragma unroll
+                    for (int h = 0; h < 3; ++h) avs[p][cf][h] = ans[p][cf][h];
+                } else {
+                    av[p][cf] = an[p][cf];
+                }
+            }
         load_a(kb + 1);
         // compiler-only fence: the prefetch stays here, ahead of this block's work
         asm volatile("" ::: "memory");
@@ -194,8 +271,23 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
                     else
                         pe[i >> 1] = f;
                 }
-                pt[w][0][lane][g] = floatx4{pe[0], pe[1], pe[2], pe[3]};
-                pt[w][1][lane][g] = floatx4{po[0], po[1], po[2], po[3]};
+                if constexpr (SPLIT) {
+                    Split3 e[4], o[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        e[i] = split3(pe[i]);
+                        o[i] = split3(po[i]);
+                    }
+                    pt.v[w][0][0][lane][g] = make_uint2(bf16_pair(e[0].hi, e[1].hi), bf16_pair(e[2].hi, e[3].hi));
+                    pt.v[w][1][0][lane][g] = make_uint2(bf16_pair(e[0].mid, e[1].mid), bf16_pair(e[2].mid, e[3].mid));
+                    pt.v[w][2][0][lane][g] = make_uint2(bf16_pair(e[0].lo, e[1].lo), bf16_pair(e[2].lo, e[3].lo));
+                    pt.v[w][0][1][lane][g] = make_uint2(bf16_pair(o[0].hi, o[1].hi), bf16_pair(o[2].hi, o[3].hi));
+                    pt.v[w][1][1][lane][g] = make_uint2(bf16_pair(o[0].mid, o[1].mid), bf16_pair(o[2].mid, o[3].mid));
+                    pt.v[w][2][1][lane][g] = make_uint2(bf16_pair(o[0].lo, o[1].lo), bf16_pair(o[2].lo, o[3].lo));
+                } else {
+                    pt.v[w][0][lane][g] = floatx4{pe[0], pe[1], pe[2], pe[3]};
+                    pt.v[w][1][lane][g] = floatx4{po[0], po[1], po[2], po[3]};
+                }
             }
         };
         if (l0 <= hi || l0 + kMxL - 1 > lmax)
@@ -204,22 +296,41 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
             steps(std::false_type{});
         // LDS operations of one wave complete in order: the reads below see
         // the writes above, and the next block's writes follow these reads
-        floatx4 bv[2][4];
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-            for (int rf = 0; rf < 4; ++rf)
-                bv[p][rf] = pt[w][p][rf * 16 + c16][kq];
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
+        if constexpr (SPLIT) {
+            // one 16 x 16 x 16 bf16 instruction covers the 16 k of a parity
+            // (lane l: k = 4 (l / 16) + i, the k of the FP32 steps j = i)
+            shortx4 bvs[2][4][3];
 #pragma unroll
             for (int p = 0; p < 2; ++p)
 #pragma unroll
                 for (int rf = 0; rf < 4; ++rf)
 #pragma unroll
-                    for (int cf = 0; cf < NCF; ++cf)
-                        acc[p][rf][cf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[p][cf][j], bv[p][rf][j],
-                                                                              acc[p][rf][cf], 0, 0, 0);
+                    for (int h = 0; h < 3; ++h)
+                        bvs[p][rf][h] = __builtin_bit_cast(shortx4, pt.v[w][h][p][rf * 16 + c16][kq]);
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int rf = 0; rf < 4; ++rf)
+#pragma unroll
+                    for (int cf = 0; cf < NCF; ++cf) acc[p][rf][cf] = mfma_split3(avs[p][cf], bvs[p][rf], acc[p][rf][cf]);
+        } else {
+            floatx4 bv[2][4];
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int rf = 0; rf < 4; ++rf)
+                    bv[p][rf] = pt.v[w][p][rf * 16 + c16][kq];
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int rf = 0; rf < 4; ++rf)
+#pragma unroll
+                        for (int cf = 0; cf < NCF; ++cf)
+                            acc[p][rf][cf] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[p][cf][j], bv[p][rf][j],
+                                                                                  acc[p][rf][cf], 0, 0, 0);
+        }
         if constexpr (F64S) {
 #pragma unroll
             for (int p = 0; p < 2; ++p)
@@ -464,7 +575,7 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
     }
 }
 
-template <int NCF, bool F64S>
+template <int NCF, bool F64S, bool SPLIT>
 int launch_syn_mx_t(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm, void *aprime,
                     void *delta, DeltaLayout dl, int nmaps, hipStream_t st) {
     constexpr int NC = 16 * NCF;
@@ -472,12 +583,12 @@ int launch_syn_mx_t(const CoefTables &c, const GeomPlan &p, const StartTable &s,
     const int tiles = (p.nslots + kBlock - 1) / kBlock;
     const int64_t gx = (int64_t)tiles * padded_m(c.mmax);
     if (!grid_ok(gx) || c.mmax + 1 > 65535 || ncg > 65535) return SHT_EUNSUPPORTED;
-    hipLaunchKernelGGL(k_prescale_mx<NCF>, dim3((unsigned)mx_blocks(c.lmax, 0), (unsigned)(c.mmax + 1), (unsigned)ncg),
+    hipLaunchKernelGGL((k_prescale_mx<NCF, SPLIT>), dim3((unsigned)mx_blocks(c.lmax, 0), (unsigned)(c.mmax + 1), (unsigned)ncg),
                        dim3(kBlock), 0, st, c.lmax, nmaps, c.nalm, c.mxblocks, c.mxofs,
-                       static_cast<const double2 *>(alm), c.cfac, static_cast<float *>(aprime));
+                       static_cast<const double2 *>(alm), c.cfac, aprime);
     SHT_HIP(hipGetLastError());
-    hipLaunchKernelGGL((k_leg_syn_mx<NCF, F64S>), dim3((unsigned)gx, (unsigned)ncg), dim3(kBlock), 0, st, c.lmax, c.mmax,
-                       p.nslots, tiles, dl, nmaps, c.mxblocks, c.mxofs, static_cast<const float *>(aprime),
+    hipLaunchKernelGGL((k_leg_syn_mx<NCF, F64S, SPLIT>), dim3((unsigned)gx, (unsigned)ncg), dim3(kBlock), 0, st, c.lmax, c.mmax,
+                       p.nslots, tiles, dl, nmaps, c.mxblocks, c.mxofs, static_cast<const void *>(aprime),
                        c.alpha, s.lstart, s.state, p.slot_x, p.slot_north, p.slot_south,
                        static_cast<double2 *>(delta));
     SHT_HIP(hipGetLastError());
@@ -507,8 +618,11 @@ int launch_leg_ana_mx(const CoefTables &c, const GeomPlan &p, const StartTable &
 // column groups, so such a wave covers 8 maps.
 constexpr int kMxOneChainLmax = 2048;
 bool mx_f64_sums(int lmax, uint32_t flags) { return lmax > kMxOneChainLmax || (flags & SHT_MIXED_FP64_SUMS); }
+// 16-column groups per wave: the split operands (three bf16 planes of both
+// operands) take the registers of two more groups
 int mx_col_frags(int nmaps, int lmax, uint32_t flags) {
     if (mx_f64_sums(lmax, flags)) return 1;
+    if (flags & SHT_MIXED_SPLIT_BF16) return nmaps <= 8 ? 1 : 2;
     return nmaps <= 8 ? 1 : nmaps <= 16 ? 2 : 4;
 }
 
@@ -517,16 +631,24 @@ size_t mx_aprime_bytes(int lmax, int mmax, int nmaps, uint32_t flags) {
     for (int m = 0; m <= mmax; ++m) blocks += mx_blocks(lmax, m);
     const int nc = 16 * mx_col_frags(nmaps, lmax, flags);
     const int64_t ncg = (nmaps + nc / 2 - 1) / (nc / 2);
-    return (size_t)(ncg * blocks * 2 * nc * kMxHalf) * sizeof(float);
+    const size_t elem = (flags & SHT_MIXED_SPLIT_BF16) ? 3 * sizeof(uint16_t) : sizeof(float);
+    return (size_t)(ncg * blocks * 2 * nc * kMxHalf) * elem;
 }
 
 int launch_leg_syn_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *alm, void *aprime,
                       void *delta, DeltaLayout dl, int nmaps, uint32_t flags, hipStream_t st) {
-    if (mx_f64_sums(c.lmax, flags)) return launch_syn_mx_t<1, true>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+    const bool f64s = mx_f64_sums(c.lmax, flags);
+    if (flags & SHT_MIXED_SPLIT_BF16) {
+        if (f64s) return launch_syn_mx_t<1, true, true>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+        if (mx_col_frags(nmaps, c.lmax, flags) == 1)
+            return launch_syn_mx_t<1, false, true>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+        return launch_syn_mx_t<2, false, true>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+    }
+    if (f64s) return launch_syn_mx_t<1, true, false>(c, p, s, alm, aprime, delta, dl, nmaps, st);
     switch (mx_col_frags(nmaps, c.lmax, flags)) {
-        case 1: return launch_syn_mx_t<1, false>(c, p, s, alm, aprime, delta, dl, nmaps, st);
-        case 2: return launch_syn_mx_t<2, false>(c, p, s, alm, aprime, delta, dl, nmaps, st);
-        default: return launch_syn_mx_t<4, false>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+        case 1: return launch_syn_mx_t<1, false, false>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+        case 2: return launch_syn_mx_t<2, false, false>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+        default: return launch_syn_mx_t<4, false, false>(c, p, s, alm, aprime, delta, dl, nmaps, st);
     }
 }
 

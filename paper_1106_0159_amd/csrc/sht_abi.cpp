@@ -15,7 +15,7 @@ using namespace sht;
 
 namespace {
 
-constexpr uint32_t kKnownFlags = SHT_MIXED | SHT_DELTA_MAP_MINOR | SHT_MIXED_FP64_SUMS;
+constexpr uint32_t kKnownFlags = SHT_MIXED | SHT_DELTA_MAP_MINOR | SHT_MIXED_FP64_SUMS | SHT_MIXED_SPLIT_BF16;
 
 size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 
@@ -72,7 +72,7 @@ int check_common(int lmax, int mmax, const sht_geom *g, int nmaps, uint32_t flag
     int rc = validate_sizes(lmax, mmax, nmaps);
     if (rc) return rc;
     if (flags & ~kKnownFlags) return SHT_EUNSUPPORTED;
-    if ((flags & SHT_MIXED_FP64_SUMS) && !(flags & SHT_MIXED)) return SHT_EUNSUPPORTED;
+    if ((flags & (SHT_MIXED_FP64_SUMS | SHT_MIXED_SPLIT_BF16)) && !(flags & SHT_MIXED)) return SHT_EUNSUPPORTED;
     return validate_geom(g, need_weight, h);
 }
 
@@ -175,7 +175,7 @@ int sht_delta2alm(int lmax, int mmax, const sht_geom *g, const void *delta, void
     HostGeom h;
     int rc = check_common(lmax, mmax, g, nmaps, flags, false, &h);
     if (rc) return rc;
-    if (!legendre_layout_ok(flags)) return SHT_EUNSUPPORTED;
+    if (!legendre_layout_ok(flags) || (flags & SHT_MIXED_SPLIT_BF16)) return SHT_EUNSUPPORTED;
     if (!delta || !alm || !aligned(delta, 16) || !aligned(alm, 16)) return SHT_EINVAL;
     const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
     if (!workspace || !aligned(workspace, 16) || ws_bytes < ws_need(lmax, mmax, h, nmaps, flags))
@@ -225,6 +225,7 @@ int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *
     HostGeom h;
     int rc = check_common(lmax, mmax, g, nmaps, flags, true, &h);
     if (rc) return rc;
+    if (flags & SHT_MIXED_SPLIT_BF16) return SHT_EUNSUPPORTED;  // a synthesis variant
     if (!alm || !map || !aligned(alm, 16) || !aligned(map, 8)) return SHT_EINVAL;
     const size_t ab = alm_bytes(lmax, mmax, nmaps), db = delta_bytes(h.nrings, mmax, nmaps);
     const size_t mb = (size_t)h.npix * 8u * nmaps;

@@ -82,30 +82,36 @@ def test_workspace_bytes_mixed():
     """SHT_MIXED: aux holds FP32 tiles of c a_lm, [column group][l-block of
     column m][parity][16 NCF columns][16 k] floats, NCF = 1, 2, 4 for up to
     8, 16 and more maps (8 NCF maps per column group; NCF = 1 with FP64
-    block sums and above lmax 2048), kMxL = 32 l per block, or the FP64
+    block sums and above lmax 2048, at most 2 with the bf16 split, whose
+    tiles hold three bf16 planes), kMxL = 32 l per block, or the FP64
     c-scaled a_lm if larger."""
     g = si.healpix(8)
     r256 = lambda b: (b + 255) // 256 * 256
     delta = lambda lmax, n: r256(n * g.nrings * (lmax + 1) * 16)
 
-    def tiles(lmax, nmaps, f64_sums=False):
+    def tiles(lmax, nmaps, f64_sums=False, split=False):
         blocks = sum((lmax - m + 32) // 32 for m in range(lmax + 1))
-        ncf = 1 if nmaps <= 8 else 2 if nmaps <= 16 else 4
+        ncf = 1 if nmaps <= 8 else 2 if (nmaps <= 16 or split) else 4
         if lmax > 2048 or f64_sums:  # FP64 block sums: 8 maps per wave
             ncf = 1
         ncg = -(-nmaps // (8 * ncf))
-        return ncg * blocks * 2 * (16 * ncf) * 16 * 4
+        # split: three bf16 planes (6 bytes per entry) instead of FP32
+        return ncg * blocks * 2 * (16 * ncf) * 16 * (6 if split else 4)
 
     # with SHT_MIXED either kernel set may run (the FP64 ones below 8 maps),
     # so aux holds the larger of the tiles and the c-scaled a_lm (+32 entries)
-    def aux(lmax, nmaps, f64_sums=False):
+    def aux(lmax, nmaps, f64_sums=False, split=False):
         f64 = nmaps * (lmax + 1) * (lmax + 2) // 2 * 16 + 32 * 16
-        return r256(max(tiles(lmax, nmaps, f64_sums), f64))
+        return r256(max(tiles(lmax, nmaps, f64_sums, split), f64))
 
     for lmax, nmaps in [(16, 1), (16, 3), (16, 12), (16, 20), (16, 40), (70, 33), (0, 1), (2048, 40), (2049, 40)]:
         assert _ws(lmax, lmax, g, nmaps, sht.SHT_MIXED) == delta(lmax, nmaps) + aux(lmax, nmaps), (lmax, nmaps)
         assert (_ws(lmax, lmax, g, nmaps, sht.SHT_MIXED | sht.SHT_MIXED_FP64_SUMS) ==
                 delta(lmax, nmaps) + aux(lmax, nmaps, True)), (lmax, nmaps)
+        assert (_ws(lmax, lmax, g, nmaps, sht.SHT_MIXED | sht.SHT_MIXED_SPLIT_BF16) ==
+                delta(lmax, nmaps) + aux(lmax, nmaps, split=True)), (lmax, nmaps)
+        assert (_ws(lmax, lmax, g, nmaps, sht.SHT_MIXED | sht.SHT_MIXED_SPLIT_BF16 | sht.SHT_MIXED_FP64_SUMS) ==
+                delta(lmax, nmaps) + aux(lmax, nmaps, True, True)), (lmax, nmaps)
     # the FP64-sums bit needs SHT_MIXED
     assert _ws(16, 16, g, 1, sht.SHT_MIXED_FP64_SUMS) == 0
     # the Delta layout flag does not change the workspace
@@ -171,7 +177,14 @@ def test_invalid_arguments_rejected_on_host(L):
     assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, big, 1 << 31, None) == sht.SHT_EUNSUPPORTED
     assert L.sht_map2alm(4, 4, g.ref(), m, a, 1, w, big, sht.SHT_MIXED | 4, None) == sht.SHT_EUNSUPPORTED
     assert L.sht_delta2alm(4, 4, g.ref(), m, a, 1, w, big, 8, None) == sht.SHT_EUNSUPPORTED
-    assert L.sht_delta2map(4, g.ref(), m, a, 1, 16, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_delta2map(4, g.ref(), m, a, 1, 32, None) == sht.SHT_EUNSUPPORTED
+    # the split-bf16 bit needs SHT_MIXED and is a synthesis variant (analysis calls reject it)
+    sp = sht.SHT_MIXED | sht.SHT_MIXED_SPLIT_BF16
+    assert L.sht_alm2map(4, 4, g.ref(), a, m, 1, w, big, sht.SHT_MIXED_SPLIT_BF16, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_alm2delta(4, 4, g.ref(), a, m, 1, w, big, sht.SHT_MIXED_SPLIT_BF16, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_map2alm(4, 4, g.ref(), m, a, 1, w, big, sp, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_delta2alm(4, 4, g.ref(), m, a, 1, w, big, sp, None) == sht.SHT_EUNSUPPORTED
+    assert L.sht_workspace_bytes(4, 4, g.ref(), 1, sht.SHT_MIXED_SPLIT_BF16) == 0
     assert L.sht_alm2delta(4, 4, g.ref(), a, m, 1, w, big, sht.SHT_DELTA_MAP_MINOR, None) == sht.SHT_EUNSUPPORTED
     assert L.sht_delta2alm(4, 4, g.ref(), m, a, 1, w, big, sht.SHT_DELTA_MAP_MINOR, None) == sht.SHT_EUNSUPPORTED
     # null and misaligned pointers

@@ -292,6 +292,76 @@ def test_mixed_fp64_block_sums_healpix1024_lmax2048(sht):
     assert e_comp.max() < e_plain.max()
 
 
+SPLIT_CASES = [c for c in MX_CASES if c[4] >= 8]
+
+
+@pytest.mark.parametrize("case", SPLIT_CASES, ids=[c[0] for c in SPLIT_CASES])
+def test_split_bf16_alm2map_small(sht, case):
+    """SHT_MIXED_SPLIT_BF16: every map against the oracle and the FP64 HIP
+    path at the mixed bar, and no worse than the FP32 matrix-core path on the
+    same FP32 operands (1.5x its error + 5e-8): a part of the three-way split
+    lost or misplaced would leave about 2^-16 = 1.5e-5 relative.  Also with
+    FP64 block sums (8 maps per wave)."""
+    name, mk, lmax, mmax, nmaps = case
+    g = mk()
+    a = batch(lmax, mmax, nmaps, 700)
+    sp = sht.SHT_MIXED | sht.SHT_MIXED_SPLIT_BF16
+    say(f"split-bf16 alm2map {name} lmax={lmax} mmax={mmax} nrings={g.nrings} nmaps={nmaps}")
+    got = host(sht.alm2map(dev(a), g, lmax, mmax, flags=sp))
+    got_f64s = host(sht.alm2map(dev(a), g, lmax, mmax, flags=sp | sht.SHT_MIXED_FP64_SUMS))
+    f32 = host(sht.alm2map(dev(a), g, lmax, mmax, flags=sht.SHT_MIXED))
+    f64 = host(sht.alm2map(dev(a), g, lmax, mmax))
+    for i in range(nmaps):
+        ref = oracle.alm2map(lmax, mmax, g, a[i])
+        if np.linalg.norm(ref) == 0:
+            assert np.all(got[i] == 0.0) and np.all(got_f64s[i] == 0.0)
+            continue
+        for v in (got[i], got_f64s[i]):
+            assert relrms(v, ref) <= MX_TOL, (name, i, relrms(v, ref))
+            assert relrms(v, f64[i]) <= MX_TOL, (name, i, relrms(v, f64[i]))
+        e_sp, e_f32 = relrms(got[i], f64[i]), relrms(f32[i], f64[i])
+        assert e_sp <= 1.5 * e_f32 + 5e-8, (name, i, e_sp, e_f32)
+
+
+def test_split_bf16_alm2delta_map_minor(sht):
+    """The split variant through the synthesis stage call with map-minor
+    Delta: every map's Delta against the oracle's delta_syn (12 maps, one
+    16-map column group with 4 empty columns)."""
+    name, mk, lmax, mmax, nmaps = MX_CASES[1]
+    g = mk()
+    a = batch(lmax, mmax, nmaps, 710)
+    say(f"split-bf16 alm2delta map-minor {name} nmaps={nmaps}")
+    got = host(sht.alm2delta(dev(a), g, lmax, mmax,
+                             flags=sht.SHT_MIXED | sht.SHT_MIXED_SPLIT_BF16 | sht.SHT_DELTA_MAP_MINOR))
+    for i in range(nmaps):
+        ref = oracle.delta_syn(lmax, mmax, g, a[i])
+        assert relrms(got[..., i], ref) <= MX_TOL, (name, i, relrms(got[..., i], ref))
+
+
+def test_split_bf16_healpix1024_lmax2048(sht):
+    """The split variant at full size: 16 power-law maps on HEALPix N_side =
+    1024 at lmax 2048 (two 16-column groups per wave), map 0 against the
+    oracle over every pixel and every map against the FP64 HIP path at the
+    mixed bar; the analysis calls reject the flag."""
+    import torch
+    lmax, nmaps = 2048, 16
+    g = si.healpix(1024)
+    say("split-bf16 alm2map: healpix 1024 lmax 2048 nmaps 16")
+    alm = torch.empty((nmaps, si.nalm(lmax, lmax)), dtype=torch.complex128, device="cuda")
+    for i in range(nmaps):
+        alm[i] = dev(si.powerlaw_alm(lmax, lmax, si.config_seed(2, i)))
+    sp = sht.SHT_MIXED | sht.SHT_MIXED_SPLIT_BF16
+    got = sht.alm2map(alm, g, lmax, flags=sp)
+    f64 = sht.alm2map(alm, g, lmax)
+    err0 = relrms(host(got[0]), oc.config2_map())
+    e = ((got - f64).norm(dim=1) / f64.norm(dim=1)).cpu().numpy()
+    say(f"split-bf16: map 0 vs oracle {err0:.3e}; vs FP64 max {e.max():.3e}")
+    assert err0 <= MX_TOL
+    assert np.all(e <= MX_TOL), e
+    with pytest.raises(sht.ShtError):
+        sht.map2alm(got, g, lmax, flags=sp)
+
+
 def test_mixed_batched_gl1025_lmax1024_64maps(sht):
     """The batched configuration on a Gauss-Legendre grid: 64 power-law maps,
     1025 rings of 2049 points (2049 = 3 x 683: Bluestein), lmax = 1024.  All
