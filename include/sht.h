@@ -156,8 +156,9 @@ size_t sht_workspace_bytes(int lmax, int mmax, const sht_geom *g, int nmaps, uin
  *              rings are left untouched)
  *   workspace  DEVICE, >= sht_workspace_bytes(...) bytes, 256-byte aligned,
  *              must not alias alm or map; contents undefined afterwards
- *   flags      0 (FP64) or SHT_MIXED (SHT_DELTA_MAP_MINOR has no effect).  Any
- *              other bit: SHT_EUNSUPPORTED. */
+ *   flags      0 (FP64) or SHT_MIXED, optionally with SHT_MIXED_FP64_SUMS
+ *              and SHT_MIXED_SPLIT_BF16 (SHT_DELTA_MAP_MINOR has no effect).
+ *              Any other bit: SHT_EUNSUPPORTED. */
 int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *map,
                 int nmaps, void *workspace, size_t ws_bytes, uint32_t flags, void *stream);
 
@@ -168,7 +169,8 @@ int sht_alm2map(int lmax, int mmax, const sht_geom *g, const void *alm, double *
  *   map        DEVICE float64   [nmaps][npix], read only
  *   alm        DEVICE complex128 [nmaps][nalm], fully written
  *   workspace  as for sht_alm2map
- *   flags      as for sht_alm2map. */
+ *   flags      as for sht_alm2map, except SHT_MIXED_SPLIT_BF16 (a synthesis
+ *              variant): SHT_EUNSUPPORTED. */
 int sht_map2alm(int lmax, int mmax, const sht_geom *g, const double *map, void *alm,
                 int nmaps, void *workspace, size_t ws_bytes, uint32_t flags, void *stream);
 
