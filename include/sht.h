@@ -136,9 +136,9 @@ enum sht_flags {
      * into three bf16 parts, hi + mid + lo, and each product is the sum of the
      * six bf16 matrix-core products whose terms exceed 2^-24 of it (hi*hi,
      * hi*mid, mid*hi, hi*lo, mid*mid, lo*hi), accumulated in FP32.  Combines
-     * with SHT_MIXED_FP64_SUMS.  A wave covers 8 or 16 maps (8 with FP64
-     * block sums).  No effect where SHT_MIXED runs the FP64 kernels (fewer
-     * than 8 maps). */
+     * with SHT_MIXED_FP64_SUMS.  A wave covers 8 to 32 maps as with
+     * SHT_MIXED alone (8 with FP64 block sums).  No effect where SHT_MIXED
+     * runs the FP64 kernels (fewer than 8 maps). */
     SHT_MIXED_SPLIT_BF16 = 16u
 };
 

@@ -198,9 +198,10 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
 
     double q1 = 0.0, q2 = 0.0;  // a pair carries zeros until it starts
     const int kb0 = lo <= lmax ? (lo - m) / kMxL : nb;
-    // a' operands one block ahead: those of block kb are loaded while block
+    // a' operands: FP32 one block ahead, those of block kb loaded while block
     // kb - 1 runs (the index is clamped, so the load after the last block
-    // re-reads it and stays in bounds)
+    // re-reads it and stays in bounds); SPLIT (three times the registers) at
+    // the start of their own block, in flight during its recurrence steps
     floatx4 an[2][NCF];
     shortx4 ans[2][NCF][3];  // SPLIT: hi, mid, lo
     auto load_a = [&](int kb) {
@@ -220,27 +221,25 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
                 }
             }
     };
-    if (kb0 < nb) load_a(kb0);
+    if constexpr (!SPLIT) {
+        if (kb0 < nb) load_a(kb0);
+    }
     for (int kb = kb0; kb < nb; ++kb) {
         // uniform; restated so that the compiler keeps alpha on scalar loads
         // (inside the injection branch it may otherwise use the equal lane
         // value ls in its place)
         const int l0 = __builtin_amdgcn_readfirstlane(m + kMxL * kb);
         floatx4 av[2][NCF];
-        shortx4 avs[2][NCF][3];
+        if constexpr (SPLIT) {
+            load_a(kb);
+        } else {
 #pragma unroll
-        for (int p = 0; p < 2; ++p)
+            for (int p = 0; p < 2; ++p)
 #pragma unroll
-            for (int cf = 0; cf < NCF; ++cf) {
-                if constexpr (SPLIT) {
-#pragma unroll
-                    for (int h = 0; h < 3; ++h) avs[p][cf][h] = ans[p][cf][h];
-                } else {
-                    av[p][cf] = an[p][cf];
-                }
-            }
-        load_a(kb + 1);
-        // compiler-only fence: the prefetch stays here, ahead of this block's work
+                for (int cf = 0; cf < NCF; ++cf) av[p][cf] = an[p][cf];
+            load_a(kb + 1);
+        }
+        // compiler-only fence: the loads stay here, ahead of this block's work
         asm volatile("" ::: "memory");
 
         // 32 recurrence steps, written as FP32 to this lane's LDS rows; starts
@@ -298,21 +297,18 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
         // the writes above, and the next block's writes follow these reads
         if constexpr (SPLIT) {
             // one 16 x 16 x 16 bf16 instruction covers the 16 k of a parity
-            // (lane l: k = 4 (l / 16) + i, the k of the FP32 steps j = i)
-            shortx4 bvs[2][4][3];
+            // (lane l: k = 4 (l / 16) + i, the k of the FP32 steps j = i);
+            // the q planes of one 16-pair tile are read just before its products
 #pragma unroll
             for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int rf = 0; rf < 4; ++rf)
+                for (int rf = 0; rf < 4; ++rf) {
+                    shortx4 b3[3];
 #pragma unroll
-                    for (int h = 0; h < 3; ++h)
-                        bvs[p][rf][h] = __builtin_bit_cast(shortx4, pt.v[w][h][p][rf * 16 + c16][kq]);
+                    for (int h = 0; h < 3; ++h) b3[h] = __builtin_bit_cast(shortx4, pt.v[w][h][p][rf * 16 + c16][kq]);
 #pragma unroll
-            for (int p = 0; p < 2; ++p)
-#pragma unroll
-                for (int rf = 0; rf < 4; ++rf)
-#pragma unroll
-                    for (int cf = 0; cf < NCF; ++cf) acc[p][rf][cf] = mfma_split3(avs[p][cf], bvs[p][rf], acc[p][rf][cf]);
+                    for (int cf = 0; cf < NCF; ++cf) acc[p][rf][cf] = mfma_split3(ans[p][cf], b3, acc[p][rf][cf]);
+                }
         } else {
             floatx4 bv[2][4];
 #pragma unroll
@@ -618,11 +614,9 @@ int launch_leg_ana_mx(const CoefTables &c, const GeomPlan &p, const StartTable &
 // column groups, so such a wave covers 8 maps.
 constexpr int kMxOneChainLmax = 2048;
 bool mx_f64_sums(int lmax, uint32_t flags) { return lmax > kMxOneChainLmax || (flags & SHT_MIXED_FP64_SUMS); }
-// 16-column groups per wave: the split operands (three bf16 planes of both
-// operands) take the registers of two more groups
+// 16-column groups per wave
 int mx_col_frags(int nmaps, int lmax, uint32_t flags) {
     if (mx_f64_sums(lmax, flags)) return 1;
-    if (flags & SHT_MIXED_SPLIT_BF16) return nmaps <= 8 ? 1 : 2;
     return nmaps <= 8 ? 1 : nmaps <= 16 ? 2 : 4;
 }
 
@@ -640,9 +634,11 @@ int launch_leg_syn_mx(const CoefTables &c, const GeomPlan &p, const StartTable &
     const bool f64s = mx_f64_sums(c.lmax, flags);
     if (flags & SHT_MIXED_SPLIT_BF16) {
         if (f64s) return launch_syn_mx_t<1, true, true>(c, p, s, alm, aprime, delta, dl, nmaps, st);
-        if (mx_col_frags(nmaps, c.lmax, flags) == 1)
-            return launch_syn_mx_t<1, false, true>(c, p, s, alm, aprime, delta, dl, nmaps, st);
-        return launch_syn_mx_t<2, false, true>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+        switch (mx_col_frags(nmaps, c.lmax, flags)) {
+            case 1: return launch_syn_mx_t<1, false, true>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+            case 2: return launch_syn_mx_t<2, false, true>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+            default: return launch_syn_mx_t<4, false, true>(c, p, s, alm, aprime, delta, dl, nmaps, st);
+        }
     }
     if (f64s) return launch_syn_mx_t<1, true, false>(c, p, s, alm, aprime, delta, dl, nmaps, st);
     switch (mx_col_frags(nmaps, c.lmax, flags)) {

@@ -82,16 +82,16 @@ def test_workspace_bytes_mixed():
     """SHT_MIXED: aux holds FP32 tiles of c a_lm, [column group][l-block of
     column m][parity][16 NCF columns][16 k] floats, NCF = 1, 2, 4 for up to
     8, 16 and more maps (8 NCF maps per column group; NCF = 1 with FP64
-    block sums and above lmax 2048, at most 2 with the bf16 split, whose
-    tiles hold three bf16 planes), kMxL = 32 l per block, or the FP64
-    c-scaled a_lm if larger."""
+    block sums and above lmax 2048; with the bf16 split the tiles hold three
+    bf16 planes), kMxL = 32 l per block, or the FP64 c-scaled a_lm if
+    larger."""
     g = si.healpix(8)
     r256 = lambda b: (b + 255) // 256 * 256
     delta = lambda lmax, n: r256(n * g.nrings * (lmax + 1) * 16)
 
     def tiles(lmax, nmaps, f64_sums=False, split=False):
         blocks = sum((lmax - m + 32) // 32 for m in range(lmax + 1))
-        ncf = 1 if nmaps <= 8 else 2 if (nmaps <= 16 or split) else 4
+        ncf = 1 if nmaps <= 8 else 2 if nmaps <= 16 else 4
         if lmax > 2048 or f64_sums:  # FP64 block sums: 8 maps per wave
             ncf = 1
         ncg = -(-nmaps // (8 * ncf))

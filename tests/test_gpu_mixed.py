@@ -339,14 +339,14 @@ def test_split_bf16_alm2delta_map_minor(sht):
 
 
 def test_split_bf16_healpix1024_lmax2048(sht):
-    """The split variant at full size: 16 power-law maps on HEALPix N_side =
-    1024 at lmax 2048 (two 16-column groups per wave), map 0 against the
-    oracle over every pixel and every map against the FP64 HIP path at the
-    mixed bar; the analysis calls reject the flag."""
+    """The split variant at full size: 24 power-law maps on HEALPix N_side =
+    1024 at lmax 2048 (one 32-map column group per wave, 8 columns empty),
+    map 0 against the oracle over every pixel and every map against the FP64
+    HIP path at the mixed bar; the analysis calls reject the flag."""
     import torch
-    lmax, nmaps = 2048, 16
+    lmax, nmaps = 2048, 24
     g = si.healpix(1024)
-    say("split-bf16 alm2map: healpix 1024 lmax 2048 nmaps 16")
+    say("split-bf16 alm2map: healpix 1024 lmax 2048 nmaps 24")
     alm = torch.empty((nmaps, si.nalm(lmax, lmax)), dtype=torch.complex128, device="cuda")
     for i in range(nmaps):
         alm[i] = dev(si.powerlaw_alm(lmax, lmax, si.config_seed(2, i)))
