@@ -265,21 +265,23 @@ def rel_per_map(x, y):
 
 def batched_legs(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a_fp64):
     """Batches of nmaps power-law maps on the benchmark grid, both transforms:
-    "batched_mixed" (SHT_MIXED: FP64 recurrence, FP32 matrix-core
-    contraction; Delta and FFTs FP64) and "batched_fp64" (the same work in
-    FP64).  Map 0 of the batch is the map of the plain FP64 step: the
-    relative RMS differences of its map and of its analysed a_lm to the plain
-    results are reported, and every map of the mixed batch against the FP64
-    batch.  "variants" gives maps/s and the largest errors against the FP64
-    batch of the plain FP32 l-chain, of SHT_MIXED_FP64_SUMS (synthesis
-    block sums added in FP64) and of SHT_MIXED_SPLIT_BF16 (synthesis products
-    from three-way bf16 splits of the FP32 operands on the bf16 matrix cores;
-    analysis as the FP32 chain)."""
+    "batched_mixed" (FP64 recurrence; synthesis products from three-way bf16
+    splits of the FP32 operands on the bf16 matrix cores, SHT_MIXED |
+    SHT_MIXED_SPLIT_BF16, the fastest mixed synthesis; analysis on the FP32
+    matrix cores, SHT_MIXED; Delta and FFTs FP64) and "batched_fp64" (the
+    same work in FP64).  Map 0 of the batch is the map of the plain FP64
+    step: the relative RMS differences of its map and of its analysed a_lm
+    to the plain results are reported, and every map of the mixed batch
+    against the FP64 batch.  "variants" gives maps/s and the largest errors
+    against the FP64 batch of the split products, of the FP32 products
+    (SHT_MIXED alone, one FP32 l-chain) and of SHT_MIXED_FP64_SUMS (FP32
+    products, synthesis block sums added in FP64)."""
     alm = power_law_batch(si, lmax, nmaps, 2)
     flops_mx = 4 * nmaps * count_triples(nslots, lmax, lmax)
-    st, bm, wall, mp_x, a_x = run_batch(sht, gh, g, lmax, alm, steps, warmup, sht.SHT_MIXED)
-    mx = batch_record(nmaps, st, bm, wall, steps, "f64 recurrence, f32 contraction", flops_mx,
-                      PEAK_FP32_MFMA_TFLOPS, "mfma", MX_KERNELS)
+    fsp = sht.SHT_MIXED | sht.SHT_MIXED_SPLIT_BF16
+    st, bm, wall, mp_x, a_x = run_batch(sht, gh, g, lmax, alm, steps, warmup, fsp)
+    mx = batch_record(nmaps, st, bm, wall, steps, "f64 recurrence; synthesis 3 x bf16 split products, "
+                      "analysis f32 products; f32 accumulation", flops_mx, PEAK_FP32_MFMA_TFLOPS, "mfma", MX_KERNELS)
     flops_64 = FLOPS_PER_TRIPLE * nmaps * count_triples(nslots, lmax, lmax)
     st, bm, wall, mp_d, a_d = run_batch(sht, gh, g, lmax, alm, steps, warmup, 0)
     f64 = batch_record(nmaps, st, bm, wall, steps, "f64", flops_64, PEAK_FP64_VALU_TFLOPS, "alu", F64_KERNELS)
@@ -292,32 +294,21 @@ def batched_legs(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a_
     mx["relrms_vs_fp64_batch"] = {"map_max": max(e_map), "map_mean": sum(e_map) / nmaps,
                                   "alm_max": max(e_alm), "alm_mean": sum(e_alm) / nmaps}
     mx["speedup_vs_batched_fp64"] = mx["value"] / f64["value"]
-    # the compensated variant: synthesis block sums added in FP64
-    fc = sht.SHT_MIXED | sht.SHT_MIXED_FP64_SUMS
-    st, bm, wall, mp_c, a_c = run_batch(sht, gh, g, lmax, alm, steps, warmup, fc)
-    comp = batch_record(nmaps, st, bm, wall, steps, "f64 recurrence, f32 contraction, f64 block sums", flops_mx,
-                        PEAK_FP32_MFMA_TFLOPS, "mfma", MX_KERNELS)
-    e_map, e_alm = rel_per_map(mp_c, mp_d), rel_per_map(a_c, a_d)
-    comp["relrms_vs_fp64_batch"] = {"map_max": max(e_map), "map_mean": sum(e_map) / nmaps,
-                                    "alm_max": max(e_alm), "alm_mean": sum(e_alm) / nmaps}
-    del mp_c, a_c
-    # the split low-precision variant of the synthesis products
-    fsp = sht.SHT_MIXED | sht.SHT_MIXED_SPLIT_BF16
-    st, bm, wall, mp_s, a_s = run_batch(sht, gh, g, lmax, alm, steps, warmup, fsp)
-    spl = batch_record(nmaps, st, bm, wall, steps, "f64 recurrence, 3 x bf16 split synthesis products", flops_mx,
-                       PEAK_FP32_MFMA_TFLOPS, "mfma", MX_KERNELS)
-    e_map_s, e_alm_s = rel_per_map(mp_s, mp_d), rel_per_map(a_s, a_d)
-    del mp_s, a_s
+    del mp_x, a_x
+
+    def variant(flags, dtype):
+        st, bm, wall, mp_v, a_v = run_batch(sht, gh, g, lmax, alm, steps, warmup, flags)
+        rec = batch_record(nmaps, st, bm, wall, steps, dtype, flops_mx, PEAK_FP32_MFMA_TFLOPS, "mfma", MX_KERNELS)
+        e_m, e_a = rel_per_map(mp_v, mp_d), rel_per_map(a_v, a_d)
+        return {"value": rec["value"], "ms_per_batch": rec["ms_per_batch"], "stages_ms": rec["stages_ms"],
+                "map_relrms_max": max(e_m), "map_relrms_mean": sum(e_m) / nmaps, "alm_relrms_max": max(e_a)}
+
     mx["variants"] = {
-        "fp32_chain": {"value": mx["value"], "map_relrms_max": mx["relrms_vs_fp64_batch"]["map_max"],
-                       "alm_relrms_max": mx["relrms_vs_fp64_batch"]["alm_max"]},
-        "fp64_block_sums": {"value": comp["value"], "ms_per_batch": comp["ms_per_batch"],
-                            "stages_ms": comp["stages_ms"],
-                            "map_relrms_max": comp["relrms_vs_fp64_batch"]["map_max"],
-                            "alm_relrms_max": comp["relrms_vs_fp64_batch"]["alm_max"]},
-        "split_bf16x3": {"value": spl["value"], "ms_per_batch": spl["ms_per_batch"],
-                         "stages_ms": spl["stages_ms"], "map_relrms_max": max(e_map_s),
-                         "map_relrms_mean": sum(e_map_s) / nmaps, "alm_relrms_max": max(e_alm_s)},
+        "split_bf16x3": {"value": mx["value"], "map_relrms_max": mx["relrms_vs_fp64_batch"]["map_max"],
+                         "alm_relrms_max": mx["relrms_vs_fp64_batch"]["alm_max"]},
+        "fp32_chain": variant(sht.SHT_MIXED, "f64 recurrence, f32 products and accumulation"),
+        "fp64_block_sums": variant(sht.SHT_MIXED | sht.SHT_MIXED_FP64_SUMS,
+                                   "f64 recurrence, f32 products, f64 block sums"),
     }
     mx["fft_roofline"] = fft_roofline(g, lmax, nmaps, mx["stages_ms"])
     f64["fft_roofline"] = fft_roofline(g, lmax, nmaps, f64["stages_ms"])
@@ -328,7 +319,8 @@ def batched_legs(sht, si, gh, g, lmax, nmaps, steps, warmup, nslots, mp_fp64, a_
 def config3(sht, si, steps, warmup, with_oracle):
     """The batched Gauss-Legendre configuration: 64 power-law maps on 1025
     rings x 2049 points (2049 = 3 x 683: Bluestein ring transforms), lmax =
-    mmax = 1024, both transforms, mixed precision and FP64.  Errors: every
+    mmax = 1024, both transforms, mixed precision (synthesis from split bf16
+    products, analysis from FP32 products) and FP64.  Errors: every
     mixed map against the FP64 map, map 0 against the oracle over every
     pixel, and the round trip against the seed a_lm (exact on this grid, so
     a property of the transforms, independent of either implementation)."""
@@ -339,9 +331,11 @@ def config3(sht, si, steps, warmup, with_oracle):
     nslots = mirror_slots(g.theta)
     alm = power_law_batch(si, lmax, nmaps, 3)
     tri = count_triples(nslots, lmax, lmax)
-    st, bm, wall, mp_x, a_x = run_batch(sht, gh, g, lmax, alm, steps, warmup, sht.SHT_MIXED)
-    mx = batch_record(nmaps, st, bm, wall, steps, "f64 recurrence, f32 contraction", 4 * nmaps * tri,
-                      PEAK_FP32_MFMA_TFLOPS, "mfma", MX_KERNELS)
+    st, bm, wall, mp_x, a_x = run_batch(sht, gh, g, lmax, alm, steps, warmup,
+                                        sht.SHT_MIXED | sht.SHT_MIXED_SPLIT_BF16)
+    mx = batch_record(nmaps, st, bm, wall, steps, "f64 recurrence; synthesis 3 x bf16 split products, "
+                      "analysis f32 products; f32 accumulation", 4 * nmaps * tri, PEAK_FP32_MFMA_TFLOPS, "mfma",
+                      MX_KERNELS)
     st, bm, wall, mp_d, a_d = run_batch(sht, gh, g, lmax, alm, steps, warmup, 0)
     f64 = batch_record(nmaps, st, bm, wall, steps, "f64", FLOPS_PER_TRIPLE * nmaps * tri,
                        PEAK_FP64_VALU_TFLOPS, "alu", F64_KERNELS)
