@@ -17,8 +17,11 @@
 // FP32 by v_mfma_f32_16x16x4_f32: over all l (one FP32 chain), or, with
 // block sums in FP64 (F64S), over the 32 l of one block in a fresh FP32
 // accumulator whose sum is then added to FP64 totals -- the compensated form
-// of the l-sum, whose error no longer grows with the number of blocks.  The
-// ring FFTs stay FP64.
+// of the l-sum, whose error no longer grows with the number of blocks.  In
+// the split form (SPLIT) each FP32 operand is cut exactly into three bf16
+// parts and each product is formed from the six part products above 2^-24
+// of it by v_mfma_f32_16x16x16_bf16, again summed in FP32.  The ring FFTs
+// stay FP64.
 //
 // Tiling: a wave owns 64 ring pairs (one recurrence per lane) and 16 NCF
 // columns (NCF = 1, 2, 4) of one m; a workgroup holds four such waves on 256 consecutive
