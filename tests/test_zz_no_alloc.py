@@ -34,7 +34,8 @@ def test_noalloc_rejects_oversize_and_bad_arguments_before_any_device_call():
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("flags,nmaps", [(0, 1), (0, 3), (1, 8)], ids=["fp64", "fp64-3maps", "mixed-8maps"])
+@pytest.mark.parametrize("flags,nmaps", [(0, 1), (0, 3), (1, 8), (17, 20)],
+                         ids=["fp64", "fp64-3maps", "mixed-8maps", "mixed-split-bf16-20maps"])
 def test_noalloc_matches_alm2map_on_two_calls(flags, nmaps):
     import torch
     sht, L = _lib()
