@@ -387,15 +387,19 @@ __global__ __launch_bounds__(kBlock, 2) void k_leg_syn_mx(int lmax, int mmax, in
 // lane l takes pair 16 (l / 16) + 4 u + j of the tile for its u-th operand
 // load).  The waves' sums of two consecutive blocks are added in wave order in
 // FP64 after one barrier (two LDS buffers in turn), scaled by c_lm and written.
-constexpr int kAnaMxWaves = 8;
-constexpr int kAnaMxThreads = 64 * kAnaMxWaves;
 constexpr int kAnaMxTiles = 4;
 constexpr int kAnaMxMaps = 8;   // 16 columns
 constexpr int kQRow = 64 + 4;   // floats per k row of a q tile (padding: conflict-free operand reads)
-static_assert(kAnaMxGroup == kAnaMxWaves * kAnaMxTiles * 64, "pairs per analysis group");
-static_assert(2 * 2 * kMxHalf * kAnaMxMaps <= kAnaMxThreads, "one thread per finished (block, parity, k, map)");
+static_assert(kAnaMxGroup == 8 * kAnaMxTiles * 64, "pairs per analysis group of the widest workgroup");
+constexpr int kAnaMxOut = 2 * 2 * kMxHalf * kAnaMxMaps;  // finished (block, parity, k, map) per two blocks
 
-__global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int mmax, int nslots, DeltaLayout dl,
+// WAVES waves per workgroup (kAnaMxTiles * 64 * WAVES ring pairs): 8 for large
+// geometries, 4 or 2 where the pairs fill no more than that, so that a
+// workgroup's waves carry whole tiles and, with less LDS each, two or four
+// workgroups share a CU (two waves per SIMD in every case: the Delta operands
+// take 128 VGPRs)
+template <int WAVES>
+__global__ __launch_bounds__(64 * WAVES, WAVES == 8 ? 1 : 2) void k_leg_ana_mx(int lmax, int mmax, int nslots, DeltaLayout dl,
                                                               int nmaps, int64_t nalm, int groups,
                                                               const double2 *__restrict__ delta,
                                                               const double *__restrict__ alpha,
@@ -407,9 +411,10 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
                                                               const int32_t *__restrict__ rsouth,
                                                               double2 *__restrict__ alm,
                                                               double2 *__restrict__ part) {
-    __shared__ float qs[kAnaMxWaves][2][kMxHalf][kQRow];
-    __shared__ float red[2][2][kAnaMxWaves][2][kMxHalf][16];  // [buffer][block of the pair]...
-    __shared__ int wlo[kAnaMxWaves];
+    constexpr int kThreads = 64 * WAVES, kGroup = WAVES * kAnaMxTiles * 64;
+    __shared__ float qs[WAVES][2][kMxHalf][kQRow];
+    __shared__ float red[2][2][WAVES][2][kMxHalf][16];  // [buffer][block of the pair]...
+    __shared__ int wlo[WAVES];
 
     const MPart mp = xcd_m_part(groups);
     const int m = mp.m, grp = mp.part;
@@ -419,10 +424,10 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
     const int c16 = lane & 15, kq = lane >> 4;
     const int map_c = cg * kAnaMxMaps + (c16 >> 1);  // this lane's column: map and part
     const bool col_ok = map_c < nmaps;
-    // tile t of wave w holds pairs from (t * kAnaMxWaves + w) * 64 on: pairs are
+    // tile t of wave w holds pairs from (t * WAVES + w) * 64 on: pairs are
     // sorted by latitude and start late near the poles, so every wave gets
     // tiles from the whole range and the waves' work per block stays even
-    auto tile0 = [&](int t) { return grp * kAnaMxGroup + (t * kAnaMxWaves + w) * 64; };
+    auto tile0 = [&](int t) { return grp * kGroup + (t * WAVES + w) * 64; };
 
     double x[kAnaMxTiles], q1[kAnaMxTiles], q2[kAnaMxTiles];
     double2 stv[kAnaMxTiles];
@@ -463,7 +468,7 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
     __syncthreads();
     int lo = lmax + 1;
 #pragma unroll
-    for (int i = 0; i < kAnaMxWaves; ++i) lo = min(lo, wlo[i]);
+    for (int i = 0; i < WAVES; ++i) lo = min(lo, wlo[i]);
     lo = __builtin_amdgcn_readfirstlane(lo);
 
     const int64_t base = uniform64((int64_t)m * (2 * lmax + 1 - m) / 2);  // (l, m) lives at base + l
@@ -475,7 +480,7 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
                            : part + ((int64_t)map * groups + grp) * nalm + base + l;
     };
     // no pair of the group has started before block kb0: those a_lm get no term
-    for (int i = threadIdx.x; i < kb0 * kMxL * kAnaMxMaps; i += kAnaMxThreads) {
+    for (int i = threadIdx.x; i < kb0 * kMxL * kAnaMxMaps; i += kThreads) {
         const int l = m + i / kAnaMxMaps, map = cg * kAnaMxMaps + i % kAnaMxMaps;
         if (l <= lmax && map < nmaps) *out_at(map, l) = make_double2(0.0, 0.0);
     }
@@ -548,15 +553,15 @@ __global__ __launch_bounds__(kAnaMxThreads, 1) void k_leg_ana_mx(int lmax, int m
 #pragma unroll
                 for (int r = 0; r < 4; ++r) red[buf][b][w][p][4 * kq + r][c16] = acc2[b][p][r];
         __syncthreads();
-        {
-            const int b = threadIdx.x / (2 * kMxHalf * kAnaMxMaps);
-            const int p = (threadIdx.x / (kMxHalf * kAnaMxMaps)) % 2;
-            const int k = (threadIdx.x / kAnaMxMaps) % kMxHalf, mm = threadIdx.x % kAnaMxMaps;
+        for (int e = threadIdx.x; e < kAnaMxOut; e += kThreads) {
+            const int b = e / (2 * kMxHalf * kAnaMxMaps);
+            const int p = (e / (kMxHalf * kAnaMxMaps)) % 2;
+            const int k = (e / kAnaMxMaps) % kMxHalf, mm = e % kAnaMxMaps;
             const int l = m + kMxL * (kb - slot + b) + 2 * k + p, map = cg * kAnaMxMaps + mm;
             if (b <= slot && l <= lmax && map < nmaps) {
                 double sr = 0.0, si = 0.0;
 #pragma unroll
-                for (int v = 0; v < kAnaMxWaves; ++v) {
+                for (int v = 0; v < WAVES; ++v) {
                     sr += red[buf][b][v][p][k][2 * mm];
                     si += red[buf][b][v][p][k][2 * mm + 1];
                 }
@@ -594,21 +599,30 @@ int launch_syn_mx_t(const CoefTables &c, const GeomPlan &p, const StartTable &s,
     return SHT_OK;
 }
 
-}  // namespace
-
-int launch_leg_ana_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *delta,
-                      DeltaLayout dl, void *alm, int nmaps, void *partials, hipStream_t st) {
-    const int groups = (p.nslots + kAnaMxGroup - 1) / kAnaMxGroup;
+template <int WAVES>
+int launch_ana_mx_t(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *delta,
+                    DeltaLayout dl, void *alm, int nmaps, void *partials, hipStream_t st) {
+    constexpr int kGroup = WAVES * kAnaMxTiles * 64;
+    const int groups = (p.nslots + kGroup - 1) / kGroup;
     const int ncg = (nmaps + kAnaMxMaps - 1) / kAnaMxMaps;
     const int64_t gx = (int64_t)groups * padded_m(c.mmax);
     if (!grid_ok(gx) || ncg > 65535) return SHT_EUNSUPPORTED;
     if (groups > 1 && !partials) return SHT_EWORKSPACE;
-    hipLaunchKernelGGL(k_leg_ana_mx, dim3((unsigned)gx, (unsigned)ncg), dim3(kAnaMxThreads), 0, st, c.lmax, c.mmax,
-                       p.nslots, dl, nmaps, c.nalm, groups, static_cast<const double2 *>(delta), c.alpha,
+    hipLaunchKernelGGL(k_leg_ana_mx<WAVES>, dim3((unsigned)gx, (unsigned)ncg), dim3(64 * WAVES), 0, st, c.lmax,
+                       c.mmax, p.nslots, dl, nmaps, c.nalm, groups, static_cast<const double2 *>(delta), c.alpha,
                        c.cfac, s.lstart, s.state, p.slot_x, p.slot_north, p.slot_south, static_cast<double2 *>(alm),
                        static_cast<double2 *>(partials));
     SHT_HIP(hipGetLastError());
     return groups > 1 ? launch_ana_combine(c, nmaps, groups, partials, alm, st) : SHT_OK;
+}
+
+}  // namespace
+
+int launch_leg_ana_mx(const CoefTables &c, const GeomPlan &p, const StartTable &s, const void *delta,
+                      DeltaLayout dl, void *alm, int nmaps, void *partials, hipStream_t st) {
+    if (p.nslots <= 2 * kAnaMxTiles * 64) return launch_ana_mx_t<2>(c, p, s, delta, dl, alm, nmaps, partials, st);
+    if (p.nslots <= 4 * kAnaMxTiles * 64) return launch_ana_mx_t<4>(c, p, s, delta, dl, alm, nmaps, partials, st);
+    return launch_ana_mx_t<8>(c, p, s, delta, dl, alm, nmaps, partials, st);
 }
 
 // Block sums in FP64 (the compensated l-sum) with SHT_MIXED_FP64_SUMS, and
