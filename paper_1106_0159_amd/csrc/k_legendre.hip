@@ -840,17 +840,29 @@ int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const StartTable &s, 
     const SynArgs A{c.lmax, c.mmax, p.nslots, p.nrings, c.nalm, static_cast<const double2 *>(aprime), c.alpha,
                     s.lstart, s.state, p.slot_x, p.slot_north, p.slot_south, static_cast<double2 *>(delta)};
     if (nmaps > 65535) return SHT_EUNSUPPORTED;
-    // several maps share each recurrence: 2 maps per workgroup, 4 slots per
-    // lane (faster than 4 maps and 2 slots: 29.7 against 30.6 ms for 64 maps
-    // at HEALPix 1024 / lmax 2048)
-    if (nmaps >= 2) return launch_syn_mm<4, 2>(A, p.nslots, c.mmax, nmaps, st);
-    // Slots per lane: kSynSlotsPerLane for large geometries.  With few slots a
-    // tile of kSynSlotsPerLane per lane would leave most lanes of the
-    // workgroup idle while one wave walks the l-recurrences of all of them in
-    // turn, and small transforms are bound by that sequential walk of the
-    // longest m: one or two slots per lane spread it over more lanes (at
-    // lmax 256 on 129 slots, 17.7 -> 6 us for the kernel).
-    const int T = p.nslots <= kBlock ? 1 : p.nslots <= 2 * kBlock ? 2 : kSynSlotsPerLane;
+    // Slots per lane: kSynSlotsPerLane for large geometries, else the fewest
+    // of 1 to 3 that put every slot of an m in one workgroup.  With few slots
+    // a tile of kSynSlotsPerLane per lane would leave lanes and waves of the
+    // workgroup idle while the others walk the l-recurrences of their slots in
+    // turn; small transforms are bound by that sequential walk of the longest
+    // m (at lmax 256 on 129 slots, 17.7 -> 8.5 us for the kernel with one slot
+    // per lane), and on 513 slots (Gauss-Legendre at lmax 1024) three per lane
+    // fill three waves with 9 slot-units of work where four per lane take 12.
+    const int T = p.nslots <= kBlock         ? 1
+                  : p.nslots <= 2 * kBlock   ? 2
+                  : p.nslots <= 3 * kBlock   ? 3
+                                             : kSynSlotsPerLane;
+    // several maps share each recurrence: 2 maps per workgroup (at 4 slots per
+    // lane faster than 4 maps and 2 slots: 29.7 against 30.6 ms for 64 maps at
+    // HEALPix 1024 / lmax 2048)
+    if (nmaps >= 2) {
+        switch (T) {
+            case 1: return launch_syn_mm<1, 2>(A, p.nslots, c.mmax, nmaps, st);
+            case 2: return launch_syn_mm<2, 2>(A, p.nslots, c.mmax, nmaps, st);
+            case 3: return launch_syn_mm<3, 2>(A, p.nslots, c.mmax, nmaps, st);
+            default: return launch_syn_mm<kSynSlotsPerLane, 2>(A, p.nslots, c.mmax, nmaps, st);
+        }
+    }
     const int tiles = (p.nslots + kBlock * T - 1) / (kBlock * T);
     const int64_t gx = (int64_t)tiles * padded_m(c.mmax);
     if (!grid_ok(gx)) return SHT_EUNSUPPORTED;
@@ -858,6 +870,7 @@ int launch_leg_syn(const CoefTables &c, const GeomPlan &p, const StartTable &s, 
     switch (T) {
         case 1: hipLaunchKernelGGL(k_leg_syn<1>, grid, dim3(kBlock), 0, st, A, tiles); break;
         case 2: hipLaunchKernelGGL(k_leg_syn<2>, grid, dim3(kBlock), 0, st, A, tiles); break;
+        case 3: hipLaunchKernelGGL(k_leg_syn<3>, grid, dim3(kBlock), 0, st, A, tiles); break;
         default: hipLaunchKernelGGL(k_leg_syn<kSynSlotsPerLane>, grid, dim3(kBlock), 0, st, A, tiles); break;
     }
     SHT_HIP(hipGetLastError());
@@ -884,6 +897,7 @@ int launch_leg_ana(const CoefTables &c, const GeomPlan &p, const StartTable &s, 
     switch (T) {
         case 1: launch_ana_t<1>(c, p, s, groups, delta, alm, partials, nmaps, st); break;
         case 2: launch_ana_t<2>(c, p, s, groups, delta, alm, partials, nmaps, st); break;
+        case 3: launch_ana_t<3>(c, p, s, groups, delta, alm, partials, nmaps, st); break;
         case 4: launch_ana_t<4>(c, p, s, groups, delta, alm, partials, nmaps, st); break;
         default: launch_ana_t<kAnaSlotsPerThread>(c, p, s, groups, delta, alm, partials, nmaps, st); break;
     }

@@ -27,8 +27,16 @@ constexpr int kFftClassLen[kFftClasses] = {1024, 2048, 4096, 8192};
 constexpr int kAnaThreads = 256;
 constexpr int kAnaSlotsPerThread = 8;
 
+// Slots per lane: the fewest of 1 to 4 that put every slot in one workgroup,
+// else kAnaSlotsPerThread.  (At 513 slots, Gauss-Legendre at lmax 1024, three
+// per lane fill three waves with 9 slot-units of work where four per lane
+// would take 12.)
 inline int ana_slots_per_thread(int nslots) {
-    return nslots <= kAnaThreads ? 1 : nslots <= 2 * kAnaThreads ? 2 : nslots <= 4 * kAnaThreads ? 4 : kAnaSlotsPerThread;
+    return nslots <= kAnaThreads         ? 1
+           : nslots <= 2 * kAnaThreads   ? 2
+           : nslots <= 3 * kAnaThreads   ? 3
+           : nslots <= 4 * kAnaThreads   ? 4
+                                         : kAnaSlotsPerThread;
 }
 inline int ana_groups(int nslots) {
     const int per = kAnaThreads * ana_slots_per_thread(nslots);
@@ -92,7 +100,7 @@ struct CoefTables : Fenced {
 
 // One FFT length (device view).  Points of length n are transformed in LDS
 // either directly (L == n, radices of n) or by Bluestein's chirp-z method
-// with a power-of-two length L >= 2n-1.
+// with the shortest 5-smooth length L >= 2n - 2.
 struct FftDesc {
     int n;
     int L;
